@@ -1,0 +1,324 @@
+"""Randomized Krylov-Schur in plain FP64 (oracle side).
+
+Follows Algorithm 1 (rKS) and Algorithm 2 (extension of an rKS factorisation)
+of the paper in their order, with:
+  * the sketch S = Omega U stored and truncated without re-sketching
+    (Section 3.1, after Algorithm 2);
+  * residual estimates |b^T y| / |lambda| (Section 4.1, eq. "rks_reserror_bound");
+  * locking of converged leading Schur vectors, which stay as the leading
+    basis columns so every new vector is sketch-orthogonalised against them
+    (Sections 4.2-4.4, deflated operator of eq. "AqSchurDeflatedSubspace");
+  * whitening re-orthogonalisation U <- U R^-1 from a Householder QR of the
+    sketch (Section 3.3).
+
+Small dense steps use LAPACK through SciPy: dgees (real Schur form),
+dtrexc (Bai-Demmel reordering of adjacent blocks), dgeev (eigenpairs of the
+truncated factor), Householder QR (dgeqrf) for the least-squares problems.
+
+Readings where the paper is open (listed with the reasons in the design notes):
+  * which: LM |lambda| largest, SM smallest, LR Re largest, SR Re smallest;
+    ties broken by larger imaginary part; the wanted eigenvalues are moved to
+    the front one block at a time in that priority order; if the k-th and
+    (k+1)-th form a conjugate pair both are kept (effective k = k+1).
+  * least squares h = S_j^+ z: Householder QR of S_j.
+  * locking: leading position i (a 1x1 or 2x2 diagonal block) is locked when
+    every |b_i| of the block is <= tol * max(|lambda_block|, u ||T||_F);
+    locking stops at the first position that fails.
+  * whitening when ||S_k^T S_k - I||_F > whiten_tol (default 1e-12).
+  * breakdown (an invariant subspace): when beta <= 1e-12 ||Omega w|| the new
+    vector is replaced by a seeded random vector sketch-orthogonalised against
+    U_j, and B(j+1, j) is set to 0.
+  * convergence: all effective-k estimates <= tol; at most max_restarts
+    contraction/extension cycles after the first extension.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+from scipy.linalg import lapack
+
+from .philox import start_vector, breakdown_vector
+from .sketch import sketch_matrix
+
+UNIT_ROUNDOFF = 2.0**-53
+BREAKDOWN_REL = 1e-12
+
+
+def which_key(lam: complex, which: str):
+    """Sort key, larger = more wanted (ties: larger imaginary part first)."""
+    lam = complex(lam)
+    if which == "LM":
+        return (abs(lam), lam.imag)
+    if which == "SM":
+        return (-abs(lam), lam.imag)
+    if which == "LR":
+        return (lam.real, lam.imag)
+    if which == "SR":
+        return (-lam.real, lam.imag)
+    raise ValueError(f"unknown which {which!r}")
+
+
+def _blocks(T: np.ndarray, start: int = 0):
+    """Diagonal blocks (position, size, eigenvalue with Im >= 0) of a
+    quasi-triangular T from ``start`` on."""
+    n = T.shape[0]
+    out = []
+    i = start
+    while i < n:
+        if i + 1 < n and T[i + 1, i] != 0.0:
+            blk = T[i:i + 2, i:i + 2]
+            ev = np.linalg.eigvals(blk)
+            lam = ev[0] if ev[0].imag >= ev[1].imag else ev[1]
+            out.append((i, 2, complex(lam)))
+            i += 2
+        else:
+            out.append((i, 1, complex(T[i, i])))
+            i += 1
+    return out
+
+
+def order_wanted(T: np.ndarray, Z: np.ndarray, which: str, kw: int):
+    """Move the kw most wanted eigenvalues of the real Schur form (T, Z) to the
+    leading positions, most wanted first.  Returns (T, Z, p) where p = kw, or
+    kw + 1 when a conjugate pair straddles the boundary."""
+    T = np.array(T, order="F")
+    Z = np.array(Z, order="F")
+    pos = 0
+    n = T.shape[0]
+    while pos < kw and pos < n:
+        blks = _blocks(T, pos)
+        best = max(blks, key=lambda b: which_key(b[2], which))
+        if best[0] != pos:
+            T, Z, info = lapack.dtrexc(T, Z, best[0] + 1, pos + 1)
+            if info != 0:
+                raise RuntimeError(f"dtrexc rejected a swap (info={info})")
+        size = 2 if pos + 1 < n and T[pos + 1, pos] != 0.0 else 1
+        pos += size
+    return T, Z, pos
+
+
+@dataclass
+class OracleResult:
+    lam: np.ndarray          # effective-k Ritz values, sorted by `which`
+    X: np.ndarray            # n x keff Ritz vectors, LAPACK real packing, unit 2-norm
+    resid: np.ndarray        # ||A x - lam x|| / (||A||_1 ||x||)
+    est: np.ndarray          # paper's estimates |b^T y| / |lam| at exit
+    converged: bool
+    restarts: int
+    matvecs: int
+    locked: int
+    history: list = field(default_factory=list)   # max estimate after each contraction
+
+
+class RKSOracle:
+    """State of an rKS run: U (n x (m+1)), S = Omega U, B ((m+1) x m)."""
+
+    def __init__(self, A, k, m, d, which="LM", tol=1e-10, sketch="sparse", zeta=8,
+                 sketch_seed=0, start_seed=1, lock=True, whiten_tol=1e-12,
+                 max_restarts=300):
+        if hasattr(A, "row_ptr"):
+            A = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+        self.A = sp.csr_matrix(A, dtype=np.float64)
+        n = self.A.shape[0]
+        if not (1 <= k and k + 2 <= m and m + 1 <= d and d <= n and m + 1 <= n):
+            raise ValueError("need 1 <= k, k+2 <= m, m+1 <= d <= n")
+        self.n, self.k, self.m, self.d = n, k, m, d
+        self.which, self.tol, self.lock = which, tol, lock
+        self.whiten_tol, self.max_restarts = whiten_tol, max_restarts
+        self.start_seed = start_seed
+        self.Om = sketch_matrix(n, d, sketch, sketch_seed, zeta)
+        self.normA1 = float(abs(self.A).sum(axis=0).max())
+        self.U = np.zeros((n, m + 1))
+        self.S = np.zeros((d, m + 1))
+        self.B = np.zeros((m + 1, m))
+        self.j = 0          # index of the last basis column
+        self.q = 0          # number of locked columns
+        self.keff = 0
+        self.matvecs = 0
+        self.breakdowns = 0
+        self.whitenings = 0
+
+    # -- sketch --------------------------------------------------------------
+    def sketch(self, x):
+        return np.asarray(self.Om @ x).ravel()
+
+    # -- start (Algorithm 2 with no initial decomposition) -------------------
+    def start(self, u0=None):
+        ut = start_vector(self.n, self.start_seed) if u0 is None else np.asarray(u0, dtype=np.float64)
+        s = self.sketch(ut)
+        nrm = np.linalg.norm(s)
+        self.U[:, 0] = ut / nrm
+        self.S[:, 0] = s / nrm
+        self.j = 0
+
+    # -- least squares with the stored sketch ------------------------------
+    @staticmethod
+    def lstsq(Sj, z):
+        """h = argmin ||S_j h - z||_2 by Householder QR of S_j."""
+        Qs, Rs = np.linalg.qr(Sj, mode="reduced")
+        return sla.solve_triangular(Rs, Qs.T @ z)
+
+    # -- Algorithm 2 ---------------------------------------------------------
+    def extend(self):
+        """Grow the sketch-orthonormal Krylov decomposition from j+1 to m+1 columns."""
+        for j in range(self.j, self.m):
+            w = self.A @ self.U[:, j]                      # apply A
+            self.matvecs += 1
+            z = self.sketch(w)                             # sketch
+            Sj = self.S[:, :j + 1]
+            h = self.lstsq(Sj, z)                          # low-dimensional projection
+            ut = w - self.U[:, :j + 1] @ h                 # high-dimensional update
+            st = self.sketch(ut)                           # re-sketch
+            beta = np.linalg.norm(st)
+            self.B[:j + 1, j] = h
+            if beta <= BREAKDOWN_REL * np.linalg.norm(z):
+                # invariant subspace: continue from a fresh direction, B(j+1, j) = 0
+                self.breakdowns += 1
+                r = breakdown_vector(self.n, self.start_seed, self.breakdowns)
+                hr = self.lstsq(Sj, self.sketch(r))
+                ut = r - self.U[:, :j + 1] @ hr
+                st = self.sketch(ut)
+                nb = np.linalg.norm(st)
+                self.U[:, j + 1] = ut / nb
+                self.S[:, j + 1] = st / nb
+                self.B[j + 1, j] = 0.0
+            else:
+                self.U[:, j + 1] = ut / beta               # augment basis
+                self.S[:, j + 1] = st / beta               # augment sketched basis
+                self.B[j + 1, j] = beta                    # augment Rayleigh quotient
+        self.j = self.m
+
+    # -- Algorithm 1, lines 2-4 ---------------------------------------------
+    def contract(self):
+        """Schur form of the active block, reorder the wanted eigenvalues to the
+        front, truncate.  Leaves an rKS decomposition of order keff."""
+        m, q, k = self.m, self.q, self.k
+        B = self.B
+        T_a, Z = sla.schur(B[q:m, q:m], output="real")
+        T_a, Z, p = order_wanted(T_a, Z, self.which, k - q)
+        keff = q + p
+        Q = np.eye(m)
+        Q[q:, q:] = Z
+        T = np.zeros((m, m))
+        T[:q, :q] = B[:q, :q]
+        T[:q, q:] = B[:q, q:m] @ Z
+        T[q:, q:] = T_a
+        b = B[m, :m] @ Q
+        Unew = self.U[:, :m] @ Q[:, :keff]
+        Snew = self.S[:, :m] @ Q[:, :keff]
+        self.U[:, :keff] = Unew
+        self.S[:, :keff] = Snew
+        self.U[:, keff] = self.U[:, m]
+        self.S[:, keff] = self.S[:, m]
+        self.U[:, keff + 1:] = 0.0
+        self.S[:, keff + 1:] = 0.0
+        Tk = T[:keff, :keff].copy()
+        bk = b[:keff].copy()
+        # whitening (Section 3.3)
+        Sk = self.S[:, :keff]
+        if np.linalg.norm(Sk.T @ Sk - np.eye(keff)) > self.whiten_tol:
+            Qs, R = np.linalg.qr(Sk, mode="reduced")
+            Rinv = sla.solve_triangular(R, np.eye(keff))
+            self.U[:, :keff] = self.U[:, :keff] @ Rinv
+            self.S[:, :keff] = Qs
+            Tk = R @ Tk @ Rinv
+            bk = bk @ Rinv
+            self.whitenings += 1
+        self.B[:] = 0.0
+        self.B[:keff, :keff] = Tk
+        self.B[keff, :keff] = bk
+        self.keff = keff
+        self.j = keff
+
+    def ritz(self):
+        """Eigenpairs of T_k and the estimates |b^T y| / |lambda| (Section 4.1)."""
+        keff = self.keff
+        Tk = self.B[:keff, :keff]
+        bk = self.B[keff, :keff]
+        lam, Y = sla.eig(Tk)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            est = np.abs(bk @ Y) / np.abs(lam)
+        return lam, Y, est
+
+    def lock_converged(self):
+        """Extend the locked set over leading blocks whose b entries are small
+        relative to the block's eigenvalue (Section 4.4), and zero them."""
+        keff = self.keff
+        Tk = self.B[:keff, :keff]
+        bk = self.B[keff, :keff]
+        tnorm = np.linalg.norm(Tk)
+        q = self.q
+        for (i, s, lam) in _blocks(Tk, q):
+            if i != q:
+                break
+            scale = max(abs(lam), UNIT_ROUNDOFF * tnorm)
+            if np.all(np.abs(bk[i:i + s]) <= self.tol * scale):
+                q = i + s
+            else:
+                break
+        self.B[keff, :q] = 0.0
+        self.q = q
+
+    def run(self, u0=None):
+        self.start(u0)
+        self.extend()
+        history = []
+        restarts = 0
+        while True:
+            self.contract()
+            lam, Y, est = self.ritz()
+            history.append(float(np.max(est)))
+            converged = bool(np.all(est <= self.tol))
+            if converged or restarts >= self.max_restarts:
+                break
+            if self.lock:
+                self.lock_converged()
+            self.extend()
+            restarts += 1
+        return self._finish(converged, restarts, history)
+
+    def _finish(self, converged, restarts, history):
+        keff = self.keff
+        Tk = self.B[:keff, :keff]
+        bk = self.B[keff, :keff]
+        lam, Y = sla.eig(Tk)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            est = np.abs(bk @ Y) / np.abs(lam)
+        lam, X, resid, est = eigpairs(self.A, self.U[:, :keff], lam, Y, est, self.which, self.normA1)
+        return OracleResult(lam, X, resid, est, converged, restarts, self.matvecs, self.q, history)
+
+
+def eigpairs(A, Uk, lam, Y, est, which, normA1):
+    """Ritz vectors x = U_k y sorted by ``which``, packed as LAPACK does (a
+    conjugate pair occupies two columns: real and imaginary part of the
+    member with positive imaginary part), each of unit 2-norm, with the
+    relative residual ||A x - lambda x||_2 / (||A||_1 ||x||_2)."""
+    order = sorted(range(len(lam)), key=lambda i: which_key(lam[i], which), reverse=True)
+    lam = lam[order]
+    Y = Y[:, order]
+    est = est[order]
+    n = Uk.shape[0]
+    X = np.zeros((n, len(lam)))
+    resid = np.zeros(len(lam))
+    i = 0
+    while i < len(lam):
+        x = Uk @ Y[:, i]
+        x = x / np.linalg.norm(x)
+        r = A @ x - lam[i] * x
+        res = np.linalg.norm(r) / normA1
+        if abs(lam[i].imag) > 0 and i + 1 < len(lam):
+            X[:, i] = x.real
+            X[:, i + 1] = x.imag
+            resid[i] = resid[i + 1] = res
+            i += 2
+        else:
+            X[:, i] = x.real
+            resid[i] = res
+            i += 1
+    return lam, X, resid, est
+
+
+def rks(A, k, m, d, which="LM", tol=1e-10, u0=None, **kw):
+    """Run the oracle rKS to convergence (or max_restarts); see RKSOracle."""
+    return RKSOracle(A, k, m, d, which, tol, **kw).run(u0)

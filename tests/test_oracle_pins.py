@@ -1,0 +1,296 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test targets a mistake that could hide in the oracle: a wrong Philox
+round or key schedule (known-answer vectors), a biased or non-distinct sparse
+sign pattern (exact sampling distribution), a wrong projection or sketch
+update (exact identities of the sketch-orthonormal Krylov decomposition), a
+wrong eigenvalue selection or reordering (closed-form spectra, dense brute
+force), a wrong residual estimate (the two-sided bound of Section 4.1), and a
+wrong breakdown continuation (invariant subspace recovered exactly).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle.philox import box_muller, philox4x32_10, start_vector, uniform01
+from oracle.rks import RKSOracle, rks, which_key
+from oracle.sketch import sketch_matrix, sparse_sign_columns
+from tests.closed_form import convdiff_eigs
+from workloads import CSR, convdiff2d, convdiff3d, powerlaw_random
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            rows.append((int(v[0]), [int(x, 16) for x in v[1:5]], [int(x, 16) for x in v[5:7]],
+                         [int(x, 16) for x in v[7:11]]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _kat())
+def test_philox_known_answers(row):
+    rounds, ctr, key, out = row
+    assert rounds == 10
+    got = philox4x32_10(*ctr, *key)
+    assert [int(g) for g in got] == out
+
+
+def test_philox_vectorised_matches_scalar():
+    ctr = np.arange(1000, dtype=np.uint64)
+    a = philox4x32_10(ctr, ctr >> np.uint64(3), 7, 1, 123, 456)
+    for i in (0, 17, 999):
+        b = philox4x32_10(int(ctr[i]), int(ctr[i]) >> 3, 7, 1, 123, 456)
+        assert all(int(a[w][i]) == int(b[w]) for w in range(4))
+
+
+def test_uniform01_range_and_extremes():
+    assert uniform01(0, 0) == 2.0**-53
+    top = uniform01(0xFFFFFFFF, 0xFFFFFFFF)
+    assert top < 1.0 and top == 1.0 - 2.0**-53
+    assert uniform01(0x80000000, 0) == 0.5 + 2.0**-53
+    # the low 12 bits of the second word are not used
+    assert uniform01(7, 0xFFF) == uniform01(7, 0)
+
+
+def test_box_muller_exact_point_and_moments():
+    g0, g1 = box_muller(np.exp(-0.5), 0.0)
+    assert abs(g0 - 1.0) < 1e-15 and g1 == 0.0
+    g0, g1 = box_muller(np.exp(-2.0), 0.25)   # r = 2, angle pi/2
+    assert abs(g0) < 1e-15 and abs(g1 - 2.0) < 1e-15
+    x = start_vector(400_000, 9)
+    assert abs(x.mean()) < 5 * (1 / np.sqrt(x.size))
+    assert abs(x.var() - 1.0) < 5 * np.sqrt(2 / x.size)
+    # fourth moment of N(0,1) is 3
+    assert abs(np.mean(x**4) - 3.0) < 0.05
+
+
+def test_sparse_sign_distinct_and_uniform():
+    d, zeta = 24, 8
+    rows, signs = sparse_sign_columns(np.arange(60_000), d, zeta, 77)
+    srt = np.sort(rows, axis=1)
+    assert np.all(np.diff(srt, axis=1) > 0), "rows must be distinct within a column"
+    assert rows.min() >= 0 and rows.max() < d
+    assert set(np.unique(signs)) == {-1.0, 1.0}
+    counts = np.bincount(rows.ravel(), minlength=d)
+    expect = rows.size / d
+    chi2 = ((counts - expect) ** 2 / expect).sum()
+    assert chi2 < 60.0  # d-1 = 23 degrees of freedom, p ~ 3e-5 beyond 60
+    assert abs(signs.mean()) < 5 / np.sqrt(signs.size)
+
+
+def test_floyd_sampling_exact_distribution():
+    """d = 4, zeta = 2: Floyd's algorithm gives each of the 6 subsets with
+    probability 1/6 (exact, up to the 2^-32 resolution of the draws)."""
+    rows, _ = sparse_sign_columns(np.arange(120_000), 4, 2, 5)
+    keys = np.sort(rows, axis=1) @ np.array([4, 1])
+    _, counts = np.unique(keys, return_counts=True)
+    assert len(counts) == 6
+    p = counts / counts.sum()
+    assert np.all(np.abs(p - 1 / 6) < 5 * np.sqrt((1 / 6) * (5 / 6) / counts.sum()))
+
+
+@pytest.mark.parametrize("kind", ["gauss", "sparse"])
+def test_embedding_distortion(kind):
+    """Definition of an epsilon-embedding and its singular value corollary:
+    the singular values of Omega Q (Q orthonormal, k columns) lie inside the
+    Marchenko-Pastur edges 1 +- sqrt(k/d) of a unit-variance embedding (with
+    slack), so the distortion eps is below 1; a wrong entry scaling fails."""
+    n, k, d = 4000, 20, 160
+    om = sketch_matrix(n, d, kind, 3)
+    Q, _ = np.linalg.qr(np.random.default_rng(1).standard_normal((n, k)))
+    s = np.linalg.svd(np.asarray(om @ Q), compute_uv=False)
+    r = np.sqrt(k / d)
+    assert s.max() <= 1.1 * (1 + r) and s.min() >= 0.9 * (1 - r)
+    eps = max(abs(s.max() ** 2 - 1), abs(s.min() ** 2 - 1))
+    assert eps < 1.0
+    # norm preservation on average (scaling reading: unit-norm columns)
+    x = np.random.default_rng(2).standard_normal(n)
+    ratios = [np.linalg.norm(sketch_matrix(n, d, kind, s_) @ x) ** 2 / np.linalg.norm(x) ** 2 for s_ in range(8)]
+    assert abs(np.mean(ratios) - 1.0) < 0.1
+
+
+def test_which_key_ordering():
+    vals = [1 + 2j, 1 - 2j, 3.0, -4.0, 0.5j]
+    lm = sorted(vals, key=lambda z: which_key(z, "LM"), reverse=True)
+    assert lm[0] == -4.0 and lm[1] == 3.0 and lm[2] == 1 + 2j and lm[3] == 1 - 2j
+    sr = sorted(vals, key=lambda z: which_key(z, "SR"), reverse=True)
+    assert sr[0] == -4.0 and sr[1] == 0.5j
+    sm = sorted(vals, key=lambda z: which_key(z, "SM"), reverse=True)
+    assert sm[0] == 0.5j
+
+
+def _check_decomposition(o, ncols):
+    """Exact identities of a sketch-orthonormal Krylov decomposition."""
+    j = ncols - 1
+    U, S, B = o.U[:, :ncols], o.S[:, :ncols], o.B[:ncols, :j]
+    A = o.A
+    rel = np.linalg.norm(A @ U[:, :j] - U @ B) / (o.normA1 * np.linalg.norm(U[:, :j]))
+    OU = np.asarray(o.Om @ U)
+    orth = np.linalg.norm(OU.T @ OU - np.eye(ncols))
+    cons = np.linalg.norm(OU - S)
+    # Rayleigh quotient identity: B_j = (Omega U_j)^T Omega A U_j
+    rq = np.asarray(o.Om @ (A @ U[:, :j]))
+    rqe = np.linalg.norm(OU[:, :j].T @ rq - B[:j, :j]) / o.normA1
+    return rel, orth, cons, rqe
+
+
+@pytest.mark.parametrize("kind", ["gauss", "sparse"])
+def test_decomposition_identities_through_restarts(kind):
+    A = convdiff2d(30, (20.0, 10.0))
+    o = RKSOracle(A, 6, 24, 60, "LR", 1e-10, sketch=kind, sketch_seed=4, start_seed=1)
+    o.start()
+    o.extend()
+    for r in range(6):
+        rel, orth, cons, rqe = _check_decomposition(o, o.m + 1)
+        assert rel < 1e-14 and orth < 1e-12 and cons < 1e-12 and rqe < 1e-12, (rel, orth, cons, rqe)
+        o.contract()
+        rel, orth, cons, rqe = _check_decomposition(o, o.keff + 1)
+        assert rel < 1e-13 and orth < 1e-12 and cons < 1e-12 and rqe < 1e-12
+        # truncated factor is quasi-triangular (rKS decomposition)
+        T = o.B[:o.keff, :o.keff]
+        assert np.all(np.tril(T, -2) == 0)
+        # residual identity A x - lambda x = u b^T y for every Ritz pair
+        lam, Y, est = o.ritz()
+        X = o.U[:, :o.keff] @ Y
+        lhs = o.A @ X - X * lam[None, :]
+        rhs = np.outer(o.U[:, o.keff], o.B[o.keff, :o.keff] @ Y)
+        assert np.linalg.norm(lhs - rhs) <= 1e-12 * o.normA1 * np.linalg.norm(X)
+        o.lock_converged()
+        o.extend()
+
+
+def test_deterministic_special_case_is_arnoldi():
+    """Omega = I makes the sketch inner product the Euclidean one: B is the
+    textbook Arnoldi Hessenberg matrix (modified Gram-Schmidt) up to signs."""
+    A = convdiff2d(12, (5.0, 3.0))
+    n, m = A.n, 10
+    o = RKSOracle(A, 3, m, m + 1, "LM", 1e-10, sketch="sparse", sketch_seed=0)
+    o.Om = sp.identity(n, format="csr")
+    o.S = np.zeros((n, m + 1))
+    v0 = np.random.default_rng(3).standard_normal(n)
+    o.start(v0)
+    o.extend()
+    As = o.A
+    V = np.zeros((n, m + 1))
+    H = np.zeros((m + 1, m))
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    for j in range(m):
+        w = As @ V[:, j]
+        for i in range(j + 1):
+            H[i, j] = V[:, i] @ w
+            w = w - H[i, j] * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+    sgn = np.sign(np.sum(V * o.U, axis=0))
+    assert np.allclose(o.U * sgn, V, atol=1e-10)
+    assert np.allclose(o.B * np.outer(sgn, sgn[:m]), H, atol=1e-9 * o.normA1)
+
+
+def test_closed_form_convdiff_2d():
+    """Mildly non-normal 2D operator: the oracle's k = 6 wanted eigenvalues
+    (largest real part) equal the Kronecker-sum closed form to 1e-10."""
+    N, beta = 20, (20.0, 10.0)
+    A = convdiff2d(N, beta)
+    r = rks(A, 6, 30, 80, "LR", 1e-13, sketch="gauss", sketch_seed=1, start_seed=1, max_restarts=300)
+    assert r.converged
+    cf = np.sort(convdiff_eigs(N, beta))[::-1][:6]
+    got = np.sort(r.lam.real)[::-1]
+    assert np.max(np.abs(got - cf) / cf) < 1e-10
+    assert np.max(np.abs(r.lam.imag)) < 1e-8 * cf[0]
+
+
+def test_closed_form_convdiff_3d_brute_force():
+    """3D 7-point operator (n = 512): closed form, LAPACK dense eig and the
+    oracle agree on the 5 eigenvalues of largest real part."""
+    N, beta = 8, (4.0, 2.0, 1.0)
+    A = convdiff3d(N, beta)
+    cf = np.sort(convdiff_eigs(N, beta))[::-1]
+    dense = np.sort(np.linalg.eigvals(A.to_dense()).real)[::-1]
+    assert np.max(np.abs(dense - cf) / np.abs(cf).max()) < 1e-12
+    r = rks(A, 5, 30, 60, "LR", 1e-12, sketch="sparse", sketch_seed=2, start_seed=3, max_restarts=300)
+    assert r.converged
+    got = np.sort(r.lam.real)[::-1][:5]
+    # 3D spectrum has triple degeneracies; compare the sorted leading values
+    assert np.max(np.abs(got - cf[:5]) / cf[0]) < 1e-10
+
+
+def test_dense_brute_force_random_lm():
+    """Random non-symmetric n = 300 matrix: the oracle's LM pairs equal
+    LAPACK's eigenvalues of largest modulus."""
+    A = powerlaw_random(300, 7, mean_len=12.0, lmin=4, lmax=64)
+    lam_all = np.linalg.eigvals(A.to_dense())
+    order = sorted(range(len(lam_all)), key=lambda i: which_key(lam_all[i], "LM"), reverse=True)
+    r = rks(A, 6, 40, 100, "LM", 1e-12, sketch="sparse", sketch_seed=9, start_seed=2, max_restarts=300)
+    assert r.converged
+    want = lam_all[order[:len(r.lam)]]
+    for z in r.lam:
+        assert np.min(np.abs(want - z)) < 1e-10 * abs(z)
+    assert r.resid.max() < 1e-11
+
+
+def test_residual_estimate_bound():
+    """Section 4.1 (remark after eq. "rks_reserror_bound"): with eps the
+    distortion of Omega on span(U_k, u), the normalised Ritz residual lies in
+    [sqrt((1-eps)/(1+eps)), sqrt((1+eps)/(1-eps))] * |b^T y|."""
+    A = convdiff2d(25, (10.0, 5.0))
+    o = RKSOracle(A, 6, 20, 42, "LR", 1e-10, sketch="sparse", sketch_seed=8, start_seed=1)
+    o.start()
+    o.extend()
+    o.contract()
+    lam, Y, est = o.ritz()
+    ke = o.keff
+    Q, _ = np.linalg.qr(o.U[:, :ke + 1])
+    s = np.linalg.svd(np.asarray(o.Om @ Q), compute_uv=False)
+    eps = max(abs(s.max() ** 2 - 1), abs(s.min() ** 2 - 1))
+    assert eps < 1
+    lo, hi = np.sqrt((1 - eps) / (1 + eps)), np.sqrt((1 + eps) / (1 - eps))
+    bty = np.abs(o.B[ke, :ke] @ Y)
+    for i in range(ke):
+        x = o.U[:, :ke] @ Y[:, i]
+        true = np.linalg.norm(o.A @ x - lam[i] * x) / np.linalg.norm(x)
+        assert lo * bty[i] * (1 - 1e-10) <= true <= hi * bty[i] * (1 + 1e-10)
+
+
+def test_breakdown_recovers_invariant_subspace():
+    """A start vector supported on 5 coordinates of a diagonal matrix spans a
+    5-dimensional invariant subspace; the extension must continue past the
+    breakdown and the Ritz values must contain those 5 eigenvalues exactly."""
+    n = 200
+    diag = np.linspace(1.0, 2.0, n)
+    A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), diag, {"kind": "diag"})
+    u0 = np.zeros(n)
+    idx = [3, 50, 101, 150, 199]
+    u0[idx] = [1.0, -2.0, 0.5, 1.5, 1.0]
+    o = RKSOracle(A, 4, 12, 40, "LM", 1e-10, sketch="sparse", sketch_seed=1, start_seed=1)
+    o.start(u0)
+    o.extend()
+    assert o.breakdowns >= 1
+    assert o.B[5, 4] == 0.0
+    ev = np.linalg.eigvals(o.B[:o.m, :o.m])
+    for i in idx:
+        assert np.min(np.abs(ev - diag[i])) < 1e-12
+    rel, orth, cons, rqe = _check_decomposition(o, o.m + 1)
+    assert rel < 1e-13 and orth < 1e-12
+
+
+def test_scale_invariance_of_ritz_values():
+    """Omega -> 2 Omega (the sketch scaling reading) leaves the Ritz values
+    unchanged: U scales by 1/2 and B is untouched."""
+    A = convdiff2d(20, (10.0, 5.0))
+    o1 = RKSOracle(A, 5, 20, 50, "LR", 1e-10, sketch="sparse", sketch_seed=6, start_seed=1)
+    o2 = RKSOracle(A, 5, 20, 50, "LR", 1e-10, sketch="sparse", sketch_seed=6, start_seed=1)
+    o2.Om = 2.0 * o2.Om
+    for o in (o1, o2):
+        o.start()
+        o.extend()
+    assert np.allclose(o1.B, o2.B, rtol=0, atol=1e-12 * o1.normA1)
+    assert np.allclose(o1.U, 2.0 * o2.U, atol=1e-13)
