@@ -1,0 +1,185 @@
+/*
+ * rks.h -- C-ABI of the MI355X randomized Krylov-Schur (rKS) eigensolver.
+ *
+ * The solver computes k eigenpairs of a large sparse non-symmetric matrix A
+ * (Section 1, eq. "evp") with randomized Krylov-Schur: Algorithm 1 (rKS)
+ * driving Algorithm 2 (extension of an rKS factorisation), residual
+ * monitoring (Section 4.1), locking of converged Schur vectors (Sections
+ * 4.2-4.4) and whitening re-orthogonalisation (Section 3.3).
+ *
+ * Conventions for every entry point:
+ *   * Dense matrices are column-major.  "Host" pointers are ordinary CPU
+ *     memory; "device" pointers are HIP device memory of the current device.
+ *   * A call returns RKS_OK (0), RKS_ENOTCONV (1, results still valid for
+ *     the converged pairs) or a negative error code; rks_last_error() then
+ *     describes the failure.  No call aborts the process.
+ *   * The context owns every device buffer it allocates; caller buffers are
+ *     never retained after a call returns.  Calls on one context must not
+ *     overlap; distinct contexts are independent.
+ *   * All work is enqueued on the stream given in rks_opts (NULL = the
+ *     default stream); calls that return host data synchronise that stream.
+ */
+#ifndef RKS_H
+#define RKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define RKS_OK 0
+#define RKS_ENOTCONV 1       /* max_restarts reached before every estimate <= tol */
+#define RKS_EINVAL (-1)      /* invalid argument or malformed CSR */
+#define RKS_ENOMEM (-2)      /* device or host allocation failed */
+#define RKS_EHIP (-3)        /* a HIP runtime call failed */
+#define RKS_ENAN (-4)        /* NaN/Inf in A, in u0 or in the iteration */
+#define RKS_ESTATE (-5)      /* call order violated (e.g. eigpairs before solve) */
+#define RKS_EBREAKDOWN (-6)  /* an exact invariant subspace stopped the extension */
+#define RKS_EDENSE (-7)      /* small dense step failed (QR iteration / reordering) */
+
+/* Which part of the spectrum (Section 5: largest / smallest modulus; also
+ * largest / smallest real part).  Ties are broken by larger imaginary part. */
+typedef enum { RKS_LM = 0, RKS_SM = 1, RKS_LR = 2, RKS_SR = 3 } rks_which;
+
+/* Oblivious subspace embedding Omega (Section 2, "Preliminaries"):
+ *  GAUSS  -- dense, entries N(0, 1/d);
+ *  SPARSE -- zeta nonzeros +-1/sqrt(zeta) per column in distinct rows
+ *            (Section 5 uses zeta = 8).
+ * Omega is never stored: its entries are regenerated from Philox4x32-10
+ * counters (column index, slot) keyed by sketch_seed. */
+typedef enum { RKS_SKETCH_GAUSS = 0, RKS_SKETCH_SPARSE = 1 } rks_sketch_kind;
+
+/* Storage precision of the n-dimensional basis U (mixed precision is the
+ * paper's future-work direction of Section 6; sketch-space quantities, the
+ * Rayleigh quotient and all small dense steps stay FP64). */
+typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2 } rks_precision;
+
+/* Square CSR matrix: row_ptr[n+1] (monotone, row_ptr[0] = 0), col[nnz]
+ * (in [0, n), strictly increasing inside a row), val[nnz] FP64.
+ * on_device = 0: host arrays; 1: device arrays.  Copied by rks_create. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  int32_t on_device;
+} rks_csr;
+
+typedef struct {
+  int32_t sketch_kind;   /* rks_sketch_kind, default SPARSE */
+  int32_t zeta;          /* nonzeros per sparse-sign column, 1..8, default 8 */
+  uint64_t sketch_seed;  /* default 0 */
+  uint64_t start_seed;   /* seed of the N(0,1) start vector, default 1 */
+  int32_t precision;     /* rks_precision, default FP64 */
+  int32_t max_restarts;  /* contraction/extension cycles after the first extension, default 300 */
+  int32_t lock;          /* lock converged leading Schur vectors, default 1 */
+  int32_t profile;       /* 1: time the n-dimensional kernels with HIP events, default 0 */
+  double whiten_tol;     /* whiten when ||S_k^T S_k - I||_F exceeds this, default 1e-12 */
+  void* stream;          /* hipStream_t, NULL = default stream */
+} rks_opts;
+
+/* Fills *o with the defaults listed above. */
+void rks_opts_default(rks_opts* o);
+
+/* Per-solve statistics (filled by rks_solve when st != NULL). */
+typedef struct {
+  int32_t converged;     /* 1 if every estimate <= tol */
+  int32_t restarts;      /* contraction/extension cycles performed */
+  int64_t matvecs;       /* products with A */
+  int32_t locked;        /* locked (deflated) leading Schur vectors at exit */
+  int32_t keff;          /* effective number of pairs (k or k+1, Section 3.1) */
+  int32_t whitenings;    /* whitening steps applied */
+  int32_t dense_fail;    /* reorderings that had to stop early */
+  double max_est;        /* max |b^T y| / |lambda| at exit (eq. "rks_reserror_bound") */
+  double t_total;        /* seconds, host wall clock of the solve */
+  double t_host;         /* seconds spent in the host small dense steps */
+  /* kernel timings (only when opts.profile = 1), seconds summed over launches */
+  double t_spmv, t_reduce, t_ls, t_update, t_rotate;
+  int64_t n_spmv, n_update, n_rotate;     /* launches */
+  double bytes_spmv, bytes_update, bytes_rotate;  /* algorithmic HBM bytes moved */
+  double hist_est[512];  /* max estimate after contraction r (r < 512) */
+} rks_stats;
+
+/* Create a solver for k eigenpairs of A with Krylov dimension m and sketch
+ * size d, targeting `which`, with tolerance tol on the estimates
+ * |b^T y| / |lambda| (Section 4.1).  Requires 1 <= k, k + 2 <= m,
+ * m + 1 <= d <= n (Omega must embed the (m+1)-dimensional Krylov space,
+ * Algorithm 1 input), tol > 0, a valid CSR.  opts may be NULL (defaults).
+ * Allocates the basis U (n x (m+1)), the sketch S (d x (m+1)), the Rayleigh
+ * quotient B ((m+1) x m) and scratch on the device.
+ * Errors: RKS_EINVAL, RKS_ENAN (non-finite value in A), RKS_ENOMEM, RKS_EHIP. */
+int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which, double tol,
+               const rks_opts* opts, struct rks_ctx** out);
+
+/* Run Algorithm 1 from the start vector u0 (n FP64 values, host or device
+ * per u0_on_device; NULL = the seeded N(0,1) start), scaled so that
+ * ||Omega u1|| = 1.  Stops when every estimate is <= tol, or after
+ * max_restarts cycles (RKS_ENOTCONV).  Synchronises with the host once per
+ * restart.  Errors: RKS_EINVAL, RKS_ENAN, RKS_EBREAKDOWN, RKS_EDENSE, RKS_EHIP. */
+int rks_solve(struct rks_ctx* ctx, const double* u0, int32_t u0_on_device, rks_stats* st);
+
+/* Number of pairs rks_eigpairs returns (k, or k+1 to keep a conjugate pair). */
+int32_t rks_num_pairs(const struct rks_ctx* ctx);
+
+/* Eigenpairs after rks_solve, sorted by `which`: lam_re/lam_im[keff] (host),
+ * X (n x keff, column-major; real Ritz vectors, a conjugate pair packed as
+ * real part then imaginary part of the member with positive imaginary part,
+ * each of unit 2-norm; NULL to skip), resid[keff] (host, NULL to skip) with
+ * resid = ||A x - lambda x||_2 / (||A||_1 ||x||_2) computed in FP64 on the
+ * device (eq. "RitzError" side).  X_on_device selects where X lives.
+ * Errors: RKS_ESTATE before a solve, RKS_EHIP. */
+int rks_eigpairs(struct rks_ctx* ctx, double* lam_re, double* lam_im, double* X,
+                 int32_t X_on_device, double* resid);
+
+/* Free everything the context owns.  NULL is ignored. */
+void rks_destroy(struct rks_ctx* ctx);
+
+/* Static description of an error code. */
+const char* rks_strerror(int code);
+
+/* Description of the last failure on ctx (empty string if none). */
+const char* rks_last_error(const struct rks_ctx* ctx);
+
+/* ---- lower-level entry points (kernel-level checks and tools) ----------
+ * They run single steps of the hot path on the context's matrix and sketch. */
+
+/* z = Omega x for a device FP64 vector x (n) -> device z (d). */
+int rks_sketch(struct rks_ctx* ctx, const double* x_dev, double* z_dev);
+
+/* w = A x and z = Omega w (Algorithm 2, apply A and sketch) for device FP64
+ * x (n) -> device w (n), device z (d); the fused SpMV + sketch kernel. */
+int rks_spmv_sketch(struct rks_ctx* ctx, const double* x_dev, double* w_dev, double* z_dev);
+
+/* Start from u0 (as in rks_solve) and run Algorithm 2 from one to m+1 basis
+ * columns, leaving the extended sketch-orthonormal Krylov decomposition
+ * A U_m = U_{m+1} B in the context (no contraction). */
+int rks_arnoldi(struct rks_ctx* ctx, const double* u0, int32_t u0_on_device);
+
+/* Copy the current decomposition to the host: *ncols basis columns
+ * (j + 1), B ((m+1) x m, leading dimension m+1), S (d x (m+1), leading
+ * dimension d), U (n x (m+1), leading dimension n, normalised FP64 values;
+ * may be NULL).  Any output may be NULL. */
+int rks_get_state(struct rks_ctx* ctx, int32_t* ncols, double* B, double* S, double* U);
+
+/* Restart rotation U[:, out0:out0+kout] <- U[:, in0:in0+min] * Y on the
+ * device basis (Algorithm 1, truncation line), with Y (min x kout, host,
+ * column-major).  Output columns may overlap input columns. */
+int rks_rotate(struct rks_ctx* ctx, int32_t in0, int32_t min, int32_t out0, int32_t kout,
+               const double* Y);
+
+/* Host small dense FP64 helpers used by the contraction step (no device
+ * work): real Schur form of A (n x n, in place, lda = n) with Schur vectors
+ * Z; reordering of the `which`-wanted kw eigenvalues to the front
+ * (*p = kw or kw+1).  Return 0 on success. */
+int rks_host_schur(int32_t n, double* A, double* Z);
+int rks_host_order(int32_t n, double* T, double* Z, int32_t which, int32_t kw, int32_t* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKS_H */

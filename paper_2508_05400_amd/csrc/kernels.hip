@@ -1,0 +1,511 @@
+// HIP kernels of the rKS hot path.  See kernels.hpp for the step layout.
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace rks {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum over the block; every thread gets the total.  red holds >= 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < nw; ++q) t += red[q];
+  return t;
+}
+
+// Scatter v * Omega[:, i] into the block's LDS bins (unscaled).
+template <int KIND>
+__device__ __forceinline__ void sketch_add(double* bins, uint64_t i, double v, const SketchP& sp) {
+  if (KIND == 1) {
+    int rows[8];
+    float sg[8];
+    sparse_column(i, sp.d, sp.zeta, sp.k0, sp.k1, rows, sg);
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (t < sp.zeta) atomicAdd(&bins[rows[t]], (double)sg[t] * v);
+  } else {
+    const int np = (sp.d + 1) >> 1;
+    for (int p = 0; p < np; ++p) {
+      double g0, g1;
+      gauss_pair(i, (uint32_t)p, 0u, sp.k0, sp.k1, g0, g1);
+      atomicAdd(&bins[2 * p], g0 * v);
+      if (2 * p + 1 < sp.d) atomicAdd(&bins[2 * p + 1], g1 * v);
+    }
+  }
+}
+
+__device__ __forceinline__ void bins_zero(double* bins, int d) {
+  for (int b = threadIdx.x; b < d; b += blockDim.x) bins[b] = 0.0;
+}
+
+__device__ __forceinline__ void bins_store(const double* bins, double* part, int d, double scale) {
+  for (int b = threadIdx.x; b < d; b += blockDim.x) part[(size_t)blockIdx.x * d + b] = bins[b] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// w = A x (CSR, wave tiles staged through LDS) and partials of Omega w.
+// Each wave owns one tile of <= 64 rows / <= 512 nonzeros per iteration: the
+// nonzeros are loaded coalesced, multiplied by the gathered x and staged in
+// LDS; then 64/nr lanes per row reduce the row from LDS.  A tile that is a
+// single row longer than 512 nonzeros is reduced by the whole wave.
+template <typename TV, typename TW, typename TA, int KIND>
+__global__ __launch_bounds__(256) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
+                                                     const TA* __restrict__ val, const int* __restrict__ tiles,
+                                                     int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
+                                                     double* __restrict__ zpart, SketchP sp, int do_sketch) {
+  __shared__ double bins[kMaxD];
+  __shared__ TA prod[4][kTileNnz];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (do_sketch) bins_zero(bins, sp.d);
+  __syncthreads();
+  for (int base = blockIdx.x * 4; base < ntiles; base += gridDim.x * 4) {
+    const int t = base + wv;
+    int r0 = 0, nr = 0, e0 = 0, ne = 0;
+    if (t < ntiles) {
+      r0 = tiles[t];
+      nr = tiles[t + 1] - r0;
+      e0 = rp[r0];
+      ne = rp[r0 + nr] - e0;
+    }
+    const bool staged = (t < ntiles) && ne <= kTileNnz;
+    if (staged) {
+      for (int e = lane; e < ne; e += 64)
+        prod[wv][e] = val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
+    }
+    __syncthreads();
+    if (t < ntiles) {
+      TA s = 0;
+      int rr, sub;
+      if (staged) {
+        int lpr = 64;
+        while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
+        rr = lane / lpr;
+        sub = lane - rr * lpr;
+        if (rr < nr) {
+          const int a = rp[r0 + rr] - e0, b = rp[r0 + rr + 1] - e0;
+          for (int e = a + sub; e < b; e += lpr) s += prod[wv][e];
+        }
+        for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      } else {
+        rr = 0;
+        sub = lane;
+        for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      }
+      if (rr < nr && sub == 0) {
+        const int r = r0 + rr;
+        const TW ws = (TW)s;
+        w[r] = ws;
+        if (do_sketch) sketch_add<KIND>(bins, (uint64_t)r, (double)ws, sp);
+      }
+    }
+    __syncthreads();
+  }
+  if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
+}
+
+// Deterministic sum of G partial rows: block (x, y) sums 16 bins of array y.
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                int Ga, int Gb, int d, double* __restrict__ oa,
+                                                double* __restrict__ ob) {
+  const double* p = blockIdx.y ? pb : pa;
+  double* o = blockIdx.y ? ob : oa;
+  const int G = blockIdx.y ? Gb : Ga;
+  if (p == nullptr) return;
+  __shared__ double red[16][17];
+  const int lb = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int b = blockIdx.x * 16 + lb;
+  double s = 0.0;
+  if (b < d)
+    for (int g = sl; g < G; g += 16) s += p[(size_t)g * d + b];
+  red[sl][lb] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && b < d) {
+    double tot = 0.0;
+    for (int q = 0; q < 16; ++q) tot += red[q][lb];
+    o[b] = tot;
+  }
+}
+
+// Finalise column t when pending (beta = ||s~||, S(:,t) = s~/beta, scale
+// 1/beta, B(t, t-1) = beta, breakdown test), then the low-dimensional
+// projection h = S_t^+ z computed as h = S^T z plus one re-projection
+// h += S^T (z - S h).  Writes B(0:t, t) = h and the coefficients the update
+// needs: coef[l] = h_l * scale_l (l <= t), coef[t+1] = scale_t.
+__global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int finalize_only,
+                                             const double* __restrict__ zraw, const double* __restrict__ sraw,
+                                             double* __restrict__ S, double* __restrict__ B, int ldb,
+                                             double* __restrict__ cs, double* __restrict__ coef,
+                                             double* __restrict__ scal, int* __restrict__ flags, double bd_rel) {
+  __shared__ double snew[kMaxD];
+  __shared__ double zs[kMaxD];
+  __shared__ double rs[kMaxD];
+  __shared__ double hs[kMaxM + 2];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  double ct;
+  if (pending) {
+    double s = 0.0;
+    for (int b = tid; b < d; b += blockDim.x) {
+      const double v = sraw[b];
+      snew[b] = v;
+      s += v * v;
+    }
+    s = block_sum(s, red);
+    const double beta = sqrt(s);
+    const double inv = 1.0 / beta;
+    for (int b = tid; b < d; b += blockDim.x) {
+      const double v = snew[b] * inv;
+      snew[b] = v;
+      S[b + (size_t)t * d] = v;
+    }
+    if (tid == 0) {
+      cs[t] = inv;
+      if (t > 0) {
+        B[t + (size_t)(t - 1) * ldb] = beta;
+        if (!(beta > bd_rel * scal[0]) && flags[0] == 0) flags[0] = t;
+      }
+    }
+    ct = inv;
+  } else {
+    ct = cs[t];
+  }
+  if (finalize_only) return;
+  __syncthreads();
+  double s = 0.0;
+  for (int b = tid; b < d; b += blockDim.x) {
+    const double v = zraw[b] * ct;
+    zs[b] = v;
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (tid == 0) scal[0] = sqrt(s);
+  // h = S^T z
+  for (int l = wv; l <= t; l += nw) {
+    const double* Sl = S + (size_t)l * d;
+    const bool nu = pending && l == t;
+    double a = 0.0;
+    for (int b = lane; b < d; b += 64) a += (nu ? snew[b] : Sl[b]) * zs[b];
+    a = wave_sum(a);
+    if (lane == 0) hs[l] = a;
+  }
+  __syncthreads();
+  // r = z - S h
+  for (int b = tid; b < d; b += blockDim.x) {
+    double a = zs[b];
+    for (int l = 0; l <= t; ++l) a -= ((pending && l == t) ? snew[b] : S[b + (size_t)l * d]) * hs[l];
+    rs[b] = a;
+  }
+  __syncthreads();
+  // h += S^T r
+  for (int l = wv; l <= t; l += nw) {
+    const double* Sl = S + (size_t)l * d;
+    const bool nu = pending && l == t;
+    double a = 0.0;
+    for (int b = lane; b < d; b += 64) a += (nu ? snew[b] : Sl[b]) * rs[b];
+    a = wave_sum(a);
+    if (lane == 0) hs[l] += a;
+  }
+  __syncthreads();
+  for (int l = tid; l <= t; l += blockDim.x) {
+    const double h = hs[l];
+    B[l + (size_t)t * ldb] = h;
+    coef[l] = h * ((l == t) ? ct : cs[l]);
+  }
+  if (tid == 0) coef[t + 1] = ct;
+}
+
+// u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
+// basis precision) as the new column; partials of Omega of the stored value.
+template <typename TV, typename TW, int KIND>
+__global__ __launch_bounds__(256) void k_update(int64_t n, int ncol, const TV* __restrict__ U, int64_t ldu,
+                                                const TW* __restrict__ w, const double* __restrict__ coef,
+                                                TV* __restrict__ unew, double* __restrict__ spart, SketchP sp) {
+  __shared__ double bins[kMaxD];
+  __shared__ double cf[kMaxM + 2];
+  bins_zero(bins, sp.d);
+  for (int l = threadIdx.x; l <= ncol; l += blockDim.x) cf[l] = coef[l];
+  __syncthreads();
+  const double ws = cf[ncol];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double a[8];
+    a[0] = ws * (double)w[i];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) a[q] = 0.0;
+    int l = 0;
+    for (; l + 8 <= ncol; l += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] -= cf[l + q] * Conv<TV>::ld(U[i + (int64_t)(l + q) * ldu]);
+    }
+    for (; l < ncol; ++l) a[0] -= cf[l] * Conv<TV>::ld(U[i + (int64_t)l * ldu]);
+    const double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const TV st = Conv<TV>::st(v);
+    unew[i] = st;
+    sketch_add<KIND>(bins, (uint64_t)i, Conv<TV>::ld(st), sp);
+  }
+  __syncthreads();
+  bins_store(bins, spart, sp.d, sp.scale);
+}
+
+// First column: u0 (device FP64) or the seeded N(0,1) start, stored in the
+// basis precision when `store`; partials of Omega of the stored value.
+template <typename TV, int KIND>
+__global__ __launch_bounds__(256) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
+                                              uint32_t s0, uint32_t s1, double* __restrict__ spart, SketchP sp,
+                                              int store) {
+  __shared__ double bins[kMaxD];
+  bins_zero(bins, sp.d);
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double v;
+    if (u0) {
+      v = u0[i];
+    } else {
+      double g1;
+      gauss_pair((uint64_t)i, 0u, 2u, s0, s1, v, g1);
+    }
+    const TV st = Conv<TV>::st(v);
+    if (store) u[i] = st;
+    sketch_add<KIND>(bins, (uint64_t)i, Conv<TV>::ld(st), sp);
+  }
+  __syncthreads();
+  bins_store(bins, spart, sp.d, sp.scale);
+}
+
+// O(:, out0 + o) = sum_l U(:, in0 + l) Y(l, o) for o < kout, row by row so
+// the output columns may overlap the input columns; optionally also
+// U(:, xdst) = xscale * U(:, xsrc) (read before any write of the row).
+template <typename TI, typename TO, int KM>
+__global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
+                                                int64_t ldo, int out0, int kout, const double* __restrict__ Y,
+                                                int xsrc, int xdst, double xscale) {
+  extern __shared__ double Ys[];
+  for (int idx = threadIdx.x; idx < min * KM; idx += blockDim.x) {
+    const int l = idx / KM, o = idx - l * KM;
+    Ys[idx] = (o < kout) ? Y[l + (size_t)o * min] : 0.0;
+  }
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double acc[KM];
+#pragma unroll
+    for (int o = 0; o < KM; ++o) acc[o] = 0.0;
+    for (int l = 0; l < min; ++l) {
+      const double x = Conv<TI>::ld(U[i + (int64_t)(in0 + l) * ldu]);
+      const double* yr = Ys + l * KM;
+#pragma unroll
+      for (int o = 0; o < KM; ++o) acc[o] += x * yr[o];
+    }
+    double xe = 0.0;
+    if (xsrc >= 0) xe = Conv<TI>::ld(U[i + (int64_t)xsrc * ldu]) * xscale;
+#pragma unroll
+    for (int o = 0; o < KM; ++o)
+      if (o < kout) O[i + (int64_t)(out0 + o) * ldo] = Conv<TO>::st(acc[o]);
+    if (xsrc >= 0) ((TI*)U)[i + (int64_t)xdst * ldu] = Conv<TI>::st(xe);
+  }
+}
+
+// Residual pieces for one Ritz pair: with r = AX_a - re X_a + im X_b and, for
+// a complex pair, r2 = AX_b - re X_b - im X_a; per-block partial sums of
+// ||r||^2 + ||r2||^2 and ||X_a||^2 + ||X_b||^2.
+__global__ __launch_bounds__(256) void k_resid(int64_t n, const double* __restrict__ xa, const double* __restrict__ xb,
+                                               const double* __restrict__ axa, const double* __restrict__ axb,
+                                               double re, double im, double* __restrict__ part) {
+  __shared__ double red[16];
+  double rr = 0.0, xx = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = xa[i];
+    if (xb) {
+      const double b = xb[i];
+      const double r1 = axa[i] - re * a + im * b;
+      const double r2 = axb[i] - re * b - im * a;
+      rr += r1 * r1 + r2 * r2;
+      xx += a * a + b * b;
+    } else {
+      const double r1 = axa[i] - re * a;
+      rr += r1 * r1;
+      xx += a * a;
+    }
+  }
+  rr = block_sum(rr, red);
+  xx = block_sum(xx, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rr;
+    part[2 * blockIdx.x + 1] = xx;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scale(int64_t n, double* __restrict__ x, double s) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] *= s;
+}
+
+__global__ __launch_bounds__(256) void k_fill(int64_t n, double* __restrict__ x, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+inline int grid_for(int64_t work, int per_block, int cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+#define RKS_SKETCH_SWITCH(kind, ...) \
+  do {                               \
+    if ((kind) == 1) {               \
+      constexpr int KIND = 1;        \
+      __VA_ARGS__;                   \
+    } else {                         \
+      constexpr int KIND = 0;        \
+      __VA_ARGS__;                   \
+    }                                \
+  } while (0)
+
+int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
+  const int prec = prec_override >= 0 ? prec_override : e.prec;
+  const int G = grid_for(e.ntiles, 4, kMaxG);
+  dim3 grid(G), block(256);
+  if (prec == 0) {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<double, double, double, KIND><<<grid, block, 0, e.stream>>>(
+                                     e.rp, e.col, e.val, e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
+                                     e.sp, do_sketch)));
+  } else if (prec == 1) {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<float, float, float, KIND><<<grid, block, 0, e.stream>>>(
+                                     e.rp, e.col, e.val32, e.tiles, e.ntiles, (const float*)x, (float*)w, zpart,
+                                     e.sp, do_sketch)));
+  } else {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<bf16_t, float, float, KIND><<<grid, block, 0, e.stream>>>(
+                                     e.rp, e.col, e.val32, e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
+                                     e.sp, do_sketch)));
+  }
+  return G;
+}
+
+void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob) {
+  dim3 grid((e.sp.d + 15) / 16, 2), block(256);
+  k_reduce<<<grid, block, 0, e.stream>>>(pa, pb, Ga, Gb, e.sp.d, oa, ob);
+}
+
+void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
+               double* S, double* B, int ldb, double* cs, double* coef, double* scal, int* flags, double bd_rel) {
+  k_ls<<<1, 1024, 0, e.stream>>>(t, e.sp.d, pending, finalize_only, zraw, sraw, S, B, ldb, cs, coef, scal, flags,
+                                 bd_rel);
+}
+
+int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
+                  void* unew, double* spart) {
+  const int G = grid_for(e.n, 256, kMaxG);
+  dim3 grid(G), block(256);
+  if (e.prec == 0) {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_update<double, double, KIND><<<grid, block, 0, e.stream>>>(
+                                     e.n, ncol, (const double*)U, ldu, (const double*)w, coef, (double*)unew,
+                                     spart, e.sp)));
+  } else if (e.prec == 1) {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_update<float, float, KIND><<<grid, block, 0, e.stream>>>(
+                                     e.n, ncol, (const float*)U, ldu, (const float*)w, coef, (float*)unew, spart,
+                                     e.sp)));
+  } else {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_update<bf16_t, float, KIND><<<grid, block, 0, e.stream>>>(
+                                     e.n, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew,
+                                     spart, e.sp)));
+  }
+  return G;
+}
+
+int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
+                int prec_override) {
+  const int prec = prec_override >= 0 ? prec_override : e.prec;
+  const int G = grid_for(e.n, 256, kMaxG);
+  dim3 grid(G), block(256);
+  if (prec == 0) {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_init<double, KIND><<<grid, block, 0, e.stream>>>(e.n, (double*)u, u0, s0, s1,
+                                                                                     spart, e.sp, store)));
+  } else if (prec == 1) {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_init<float, KIND><<<grid, block, 0, e.stream>>>(e.n, (float*)u, u0, s0, s1,
+                                                                                    spart, e.sp, store)));
+  } else {
+    RKS_SKETCH_SWITCH(e.sp_kind, (k_init<bf16_t, KIND><<<grid, block, 0, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1,
+                                                                                     spart, e.sp, store)));
+  }
+  return G;
+}
+
+template <typename TI, typename TO>
+static void rotate_t(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
+                     int kout, const double* Y, int xsrc, int xdst, double xscale) {
+  const int G = grid_for(e.n, 256, 2048);
+  dim3 grid(G), block(256);
+  const size_t lds = (size_t)min * (kout <= 16 ? 16 : (kout <= 32 ? 32 : 64)) * 8;
+  if (lds > 65536) {
+    const void* fn = kout <= 16 ? (const void*)k_rotate<TI, TO, 16>
+                                : (kout <= 32 ? (const void*)k_rotate<TI, TO, 32> : (const void*)k_rotate<TI, TO, 64>);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  if (kout <= 16) {
+    k_rotate<TI, TO, 16><<<grid, block, (size_t)min * 16 * 8, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout,
+                                                                         Y, xsrc, xdst, xscale);
+  } else if (kout <= 32) {
+    k_rotate<TI, TO, 32><<<grid, block, (size_t)min * 32 * 8, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout,
+                                                                         Y, xsrc, xdst, xscale);
+  } else {
+    k_rotate<TI, TO, 64><<<grid, block, (size_t)min * 64 * 8, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout,
+                                                                         Y, xsrc, xdst, xscale);
+  }
+}
+
+void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,
+                   int kout, const double* Y, int xsrc, int xdst, double xscale, int out_fp64) {
+  if (e.prec == 0) {
+    rotate_t<double, double>(e, (const double*)U, ldu, in0, min, (double*)O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  } else if (e.prec == 1) {
+    if (out_fp64)
+      rotate_t<float, double>(e, (const float*)U, ldu, in0, min, (double*)O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+    else
+      rotate_t<float, float>(e, (const float*)U, ldu, in0, min, (float*)O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  } else {
+    if (out_fp64)
+      rotate_t<bf16_t, double>(e, (const bf16_t*)U, ldu, in0, min, (double*)O, ldo, out0, kout, Y, xsrc, xdst,
+                               xscale);
+    else
+      rotate_t<bf16_t, bf16_t>(e, (const bf16_t*)U, ldu, in0, min, (bf16_t*)O, ldo, out0, kout, Y, xsrc, xdst,
+                               xscale);
+  }
+}
+
+int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const double* axa, const double* axb,
+                 double re, double im, double* part) {
+  const int G = grid_for(e.n, 256, kMaxG);
+  k_resid<<<G, 256, 0, e.stream>>>(e.n, xa, xb, axa, axb, re, im, part);
+  return G;
+}
+
+void launch_scale(const LaunchEnv& e, double* x, double s) {
+  k_scale<<<grid_for(e.n, 256, kMaxG), 256, 0, e.stream>>>(e.n, x, s);
+}
+
+void launch_fill(const LaunchEnv& e, int64_t len, double* x, double v) {
+  k_fill<<<grid_for(len, 256, kMaxG), 256, 0, e.stream>>>(len, x, v);
+}
+
+}  // namespace rks

@@ -1,0 +1,41 @@
+// Host-side launchers of the hot-path kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace rks {
+
+// What every launch needs to know about the operator and the sketch.
+struct LaunchEnv {
+  hipStream_t stream;
+  int64_t n;
+  int prec;            // 0 FP64 basis, 1 FP32 basis, 2 BF16 basis
+  const int* rp;       // CSR row pointers (device)
+  const int* col;      // CSR columns (device)
+  const double* val;   // FP64 values (device)
+  const float* val32;  // FP32 values (device, mixed precision only)
+  const int* tiles;    // SpMV wave tiles: row starts, ntiles + 1 entries
+  int ntiles;
+  int sp_kind;         // 0 Gaussian, 1 sparse-sign
+  SketchP sp;
+};
+
+// w = A x, partials of Omega w (returns the number of partial rows).
+int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override);
+void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob);
+void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
+               double* S, double* B, int ldb, double* cs, double* coef, double* scal, int* flags, double bd_rel);
+int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
+                  void* unew, double* spart);
+int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
+                int prec_override);
+void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,
+                   int kout, const double* Y, int xsrc, int xdst, double xscale, int out_fp64);
+int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const double* axa, const double* axb,
+                 double re, double im, double* part);
+void launch_scale(const LaunchEnv& e, double* x, double s);
+void launch_fill(const LaunchEnv& e, int64_t len, double* x, double v);
+
+}  // namespace rks

@@ -1,0 +1,940 @@
+// C-ABI and host driver of the MI355X randomized Krylov-Schur solver.
+//
+// rks_solve runs Algorithm 1: the first extension (Algorithm 2 from one
+// column), then cycles of contraction (real Schur form of the active block,
+// reordering of the wanted Ritz values to the front, truncation; Algorithm 1,
+// lines 2-4), residual estimates (Section 4.1), locking (Section 4.4),
+// optional whitening (Section 3.3), the basis rotation on the device and a
+// new extension.  Each cycle crosses the host/device boundary once: the
+// Rayleigh quotient B and the sketch S (both FP64, at most a few hundred KB)
+// come to the host, the rotation Y and the truncated B, S go back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dense.h"
+#include "launch.hpp"
+#include "rks.h"
+
+using rks::cplx;
+
+namespace {
+
+constexpr double kUnitRoundoff = 0x1.0p-53;
+constexpr double kBreakdownRel = 1e-12;
+
+const char* code_str(int c) {
+  switch (c) {
+    case RKS_OK: return "ok";
+    case RKS_ENOTCONV: return "not converged within max_restarts";
+    case RKS_EINVAL: return "invalid argument";
+    case RKS_ENOMEM: return "out of memory";
+    case RKS_EHIP: return "HIP runtime error";
+    case RKS_ENAN: return "non-finite value";
+    case RKS_ESTATE: return "call order violated";
+    case RKS_EBREAKDOWN: return "breakdown: exact invariant subspace";
+    case RKS_EDENSE: return "small dense step failed";
+    default: return "unknown error";
+  }
+}
+
+struct EvPair {
+  int cat;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct rks_ctx {
+  int64_t n = 0, nnz = 0;
+  int k = 0, m = 0, d = 0, which = 0;
+  double tol = 0.0;
+  rks_opts o{};
+  double normA1 = 0.0;
+  rks::LaunchEnv env{};
+  int vbytes = 8, wbytes = 8;
+  int64_t ldu = 0;
+  // device buffers
+  int *rp = nullptr, *col = nullptr, *tiles = nullptr, *flags = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  void* U = nullptr;
+  void* w = nullptr;
+  double *S = nullptr, *B = nullptr, *cs = nullptr, *coef = nullptr, *z = nullptr, *sr = nullptr;
+  double *zpart = nullptr, *spart = nullptr, *scal = nullptr, *Yd = nullptr, *u0tmp = nullptr;
+  // pinned host mirrors
+  double *hB = nullptr, *hS = nullptr, *hcs = nullptr, *hY = nullptr;
+  int* hflags = nullptr;
+  // state
+  int j = 0, q = 0, keff = 0, pending = 0;
+  int G_z = 1, G_s = 1;
+  bool have_state = false, solved = false;
+  std::vector<double> Tk, bk;
+  std::string err;
+  // profiling
+  std::vector<hipEvent_t> pool;
+  std::vector<EvPair> open;
+  size_t pool_used = 0;
+  rks_stats* st = nullptr;
+};
+
+namespace {
+
+// Failures of rks_create (no context exists yet) are reported per thread.
+thread_local std::string g_create_err;
+
+int fail(rks_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->err = std::string(code_str(code)) + ": " + msg;
+  else
+    g_create_err = std::string(code_str(code)) + ": " + msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail((ctx), RKS_EHIP, std::string(#call) + " -> " + hipGetErrorString(e_)); \
+  } while (0)
+
+void* basis_col(rks_ctx* c, int l) { return (char*)c->U + (size_t)l * c->ldu * c->vbytes; }
+
+// ---- profiling -------------------------------------------------------------
+enum { CAT_SPMV = 0, CAT_REDUCE, CAT_LS, CAT_UPDATE, CAT_ROTATE };
+
+hipEvent_t get_event(rks_ctx* c) {
+  if (c->pool_used == c->pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->pool.push_back(e);
+  }
+  return c->pool[c->pool_used++];
+}
+
+struct Prof {
+  rks_ctx* c;
+  int cat;
+  hipEvent_t a = nullptr;
+  Prof(rks_ctx* c_, int cat_) : c(c_), cat(cat_) {
+    if (c->o.profile && c->st) {
+      a = get_event(c);
+      if (a) hipEventRecord(a, c->env.stream);
+    }
+  }
+  ~Prof() {
+    if (a) {
+      hipEvent_t b = get_event(c);
+      if (b) {
+        hipEventRecord(b, c->env.stream);
+        c->open.push_back({cat, a, b});
+      }
+    }
+  }
+};
+
+void flush_events(rks_ctx* c) {
+  if (!c->st) {
+    c->open.clear();
+    c->pool_used = 0;
+    return;
+  }
+  for (auto& p : c->open) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) continue;
+    double s = ms * 1e-3;
+    switch (p.cat) {
+      case CAT_SPMV: c->st->t_spmv += s; break;
+      case CAT_REDUCE: c->st->t_reduce += s; break;
+      case CAT_LS: c->st->t_ls += s; break;
+      case CAT_UPDATE: c->st->t_update += s; break;
+      default: c->st->t_rotate += s; break;
+    }
+  }
+  c->open.clear();
+  c->pool_used = 0;
+}
+
+double spmv_bytes(const rks_ctx* c) {
+  const double bval = (c->o.precision == RKS_PREC_FP64) ? 8.0 : 4.0;
+  return (bval + 4.0) * c->nnz + 4.0 * (c->n + 1) + (double)(c->vbytes + c->wbytes) * c->n;
+}
+
+// ---- one Arnoldi step (Algorithm 2 loop body) ------------------------------
+int arnoldi_step(rks_ctx* c, int t) {
+  const auto& e = c->env;
+  {
+    Prof p(c, CAT_SPMV);
+    c->G_z = rks::launch_spmv_sketch(e, basis_col(c, t), c->w, c->zpart, 1, -1);
+  }
+  {
+    Prof p(c, CAT_REDUCE);
+    rks::launch_reduce(e, c->zpart, c->G_z, c->pending ? c->spart : nullptr, c->G_s, c->z, c->sr);
+  }
+  {
+    Prof p(c, CAT_LS);
+    rks::launch_ls(e, t, c->pending, 0, c->z, c->sr, c->S, c->B, c->m + 1, c->cs, c->coef, c->scal, c->flags,
+                   kBreakdownRel);
+  }
+  {
+    Prof p(c, CAT_UPDATE);
+    c->G_s = rks::launch_update(e, t + 1, c->U, c->ldu, c->w, c->coef, basis_col(c, t + 1), c->spart);
+  }
+  if (c->st) {
+    c->st->n_spmv += 1;
+    c->st->bytes_spmv += spmv_bytes(c);
+    c->st->n_update += 1;
+    c->st->bytes_update += (double)(t + 2) * c->n * c->vbytes + (double)c->wbytes * c->n;
+    c->st->matvecs += 1;
+  }
+  c->pending = 1;
+  c->j = t + 1;
+  return RKS_OK;
+}
+
+int finalize_last(rks_ctx* c) {
+  const auto& e = c->env;
+  rks::launch_reduce(e, nullptr, 0, c->spart, c->G_s, c->z, c->sr);
+  rks::launch_ls(e, c->j, 1, 1, c->z, c->sr, c->S, c->B, c->m + 1, c->cs, c->coef, c->scal, c->flags,
+                 kBreakdownRel);
+  c->pending = 0;
+  return RKS_OK;
+}
+
+int extend(rks_ctx* c) {
+  for (int t = c->j; t < c->m; ++t) {
+    int r = arnoldi_step(c, t);
+    if (r) return r;
+  }
+  finalize_last(c);
+  HIPCHK(c, hipGetLastError());
+  return RKS_OK;
+}
+
+int start(rks_ctx* c, const double* u0, int u0_on_device) {
+  const double* u0d = nullptr;
+  if (u0) {
+    if (u0_on_device) {
+      u0d = u0;
+    } else {
+      for (int64_t i = 0; i < c->n; ++i)
+        if (!std::isfinite(u0[i])) return fail(c, RKS_ENAN, "u0 has a non-finite entry");
+      HIPCHK(c, hipMemcpyAsync(c->u0tmp, u0, (size_t)c->n * 8, hipMemcpyHostToDevice, c->env.stream));
+      u0d = c->u0tmp;
+    }
+  }
+  const uint64_t s = c->o.start_seed;
+  HIPCHK(c, hipMemsetAsync(c->B, 0, (size_t)(c->m + 1) * c->m * 8, c->env.stream));
+  HIPCHK(c, hipMemsetAsync(c->S, 0, (size_t)c->d * (c->m + 1) * 8, c->env.stream));
+  HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->env.stream));
+  HIPCHK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * 4, c->env.stream));
+  c->G_s = rks::launch_init(c->env, basis_col(c, 0), u0d, (uint32_t)s, (uint32_t)(s >> 32), c->spart, 1, -1);
+  HIPCHK(c, hipGetLastError());
+  c->pending = 1;
+  c->j = 0;
+  c->q = 0;
+  c->keff = 0;
+  c->have_state = true;
+  c->solved = false;
+  return RKS_OK;
+}
+
+int pull_state(rks_ctx* c) {
+  auto st = c->env.stream;
+  HIPCHK(c, hipMemcpyAsync(c->hB, c->B, (size_t)(c->m + 1) * c->m * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(c->hS, c->S, (size_t)c->d * (c->m + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(c->hcs, c->cs, (size_t)(c->m + 1) * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipMemcpyAsync(c->hflags, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(c, hipStreamSynchronize(st));
+  flush_events(c);
+  return RKS_OK;
+}
+
+// Ritz values/vectors of the truncated factor and the estimates.
+void ritz(const rks_ctx* c, std::vector<cplx>& lam, std::vector<cplx>& Y, std::vector<double>& est) {
+  const int ke = c->keff;
+  lam.assign(ke, 0.0);
+  Y.assign((size_t)ke * ke, 0.0);
+  est.assign(ke, 0.0);
+  rks::quasi_tri_eig(ke, c->Tk.data(), ke, lam.data(), Y.data());
+  for (int i = 0; i < ke; ++i) {
+    cplx s = 0.0;
+    for (int r = 0; r < ke; ++r) s += c->bk[r] * Y[(size_t)r + (size_t)i * ke];
+    est[i] = std::abs(s) / std::abs(lam[i]);
+  }
+}
+
+// Contraction on the host: Schur form of the active block, reordering,
+// truncation, whitening; fills Y for the device rotation and the new B, S.
+int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscale, int* whitened) {
+  const int m = c->m, q = c->q, k = c->k, d = c->d, ldb = m + 1;
+  const int ma = m - q;
+  double* hB = c->hB;
+  std::vector<double> Ta((size_t)ma * ma), Z((size_t)ma * ma);
+  for (int jj = 0; jj < ma; ++jj)
+    for (int i = 0; i < ma; ++i) Ta[i + (size_t)jj * ma] = hB[(q + i) + (size_t)(q + jj) * ldb];
+  for (double v : Ta)
+    if (!std::isfinite(v)) return fail(c, RKS_ENAN, "non-finite Rayleigh quotient");
+  if (rks::real_schur(ma, Ta.data(), ma, Z.data(), ma) != 0)
+    return fail(c, RKS_EDENSE, "QR iteration did not converge");
+  int p = 0;
+  if (rks::order_wanted(ma, Ta.data(), ma, Z.data(), ma, c->which, k - q, &p) != 0) {
+    if (c->st) c->st->dense_fail += 1;
+    if (p == 0) return fail(c, RKS_EDENSE, "reordering rejected every swap");
+  }
+  const int ke = q + p;
+  c->keff = ke;
+  // truncated factor T (ke x ke) and b
+  std::vector<double> T((size_t)ke * ke, 0.0), b(ke, 0.0);
+  for (int jj = 0; jj < q; ++jj)
+    for (int i = 0; i < q; ++i) T[i + (size_t)jj * ke] = hB[i + (size_t)jj * ldb];
+  for (int jj = 0; jj < p; ++jj) {
+    for (int i = 0; i < q; ++i) {
+      double s = 0.0;
+      for (int l = 0; l < ma; ++l) s += hB[i + (size_t)(q + l) * ldb] * Z[l + (size_t)jj * ma];
+      T[i + (size_t)(q + jj) * ke] = s;
+    }
+    for (int i = 0; i < p; ++i) T[(q + i) + (size_t)(q + jj) * ke] = Ta[i + (size_t)jj * ma];
+  }
+  for (int i = 0; i < q; ++i) b[i] = hB[m + (size_t)i * ldb];
+  for (int jj = 0; jj < p; ++jj) {
+    double s = 0.0;
+    for (int l = 0; l < ma; ++l) s += hB[m + (size_t)(q + l) * ldb] * Z[l + (size_t)jj * ma];
+    b[q + jj] = s;
+  }
+  // truncated sketch S_new = S Q(:, 1:ke); last column is s_{m+1}
+  std::vector<double> Sn((size_t)d * (ke + 1), 0.0);
+  for (int i = 0; i < q; ++i) std::memcpy(&Sn[(size_t)i * d], &c->hS[(size_t)i * d], (size_t)d * 8);
+  for (int jj = 0; jj < p; ++jj) {
+    double* dst = &Sn[(size_t)(q + jj) * d];
+    for (int l = 0; l < ma; ++l) {
+      const double zv = Z[l + (size_t)jj * ma];
+      if (zv == 0.0) continue;
+      const double* src = &c->hS[(size_t)(q + l) * d];
+      for (int r = 0; r < d; ++r) dst[r] += src[r] * zv;
+    }
+  }
+  std::memcpy(&Sn[(size_t)ke * d], &c->hS[(size_t)m * d], (size_t)d * 8);
+  // rotation matrix: Y = diag(cs) Q(:, 1:ke) (before whitening)
+  std::vector<double> Yf((size_t)m * ke, 0.0);
+  for (int i = 0; i < q; ++i) Yf[i + (size_t)i * m] = c->hcs[i];
+  for (int jj = 0; jj < p; ++jj)
+    for (int l = 0; l < ma; ++l) Yf[(q + l) + (size_t)(q + jj) * m] = c->hcs[q + l] * Z[l + (size_t)jj * ma];
+  // whitening (Section 3.3) when the truncated sketch lost orthonormality
+  double dev = 0.0;
+  for (int a = 0; a < ke; ++a)
+    for (int bcol = 0; bcol < ke; ++bcol) {
+      double s = 0.0;
+      for (int r = 0; r < d; ++r) s += Sn[r + (size_t)a * d] * Sn[r + (size_t)bcol * d];
+      s -= (a == bcol) ? 1.0 : 0.0;
+      dev += s * s;
+    }
+  dev = std::sqrt(dev);
+  *whitened = 0;
+  if (dev > c->o.whiten_tol) {
+    std::vector<double> Qs((size_t)d * ke), R((size_t)ke * ke), Ri((size_t)ke * ke);
+    rks::householder_qr(d, ke, Sn.data(), d, Qs.data(), d, R.data(), ke);
+    rks::upper_tri_inverse(ke, R.data(), ke, Ri.data(), ke);
+    std::memcpy(Sn.data(), Qs.data(), (size_t)d * ke * 8);
+    std::vector<double> T2((size_t)ke * ke, 0.0), T3((size_t)ke * ke, 0.0), b2(ke, 0.0), Y2((size_t)m * ke, 0.0);
+    for (int jj = 0; jj < ke; ++jj)  // T2 = T Ri
+      for (int l = 0; l <= jj; ++l) {
+        const double rv = Ri[l + (size_t)jj * ke];
+        for (int i = 0; i < ke; ++i) T2[i + (size_t)jj * ke] += T[i + (size_t)l * ke] * rv;
+      }
+    for (int jj = 0; jj < ke; ++jj)  // T3 = R T2
+      for (int i = 0; i < ke; ++i) {
+        double s = 0.0;
+        for (int l = i; l < ke; ++l) s += R[i + (size_t)l * ke] * T2[l + (size_t)jj * ke];
+        T3[i + (size_t)jj * ke] = s;
+      }
+    for (int jj = 0; jj < ke; ++jj) {
+      double s = 0.0;
+      for (int l = 0; l <= jj; ++l) s += b[l] * Ri[l + (size_t)jj * ke];
+      b2[jj] = s;
+    }
+    for (int jj = 0; jj < ke; ++jj)
+      for (int l = 0; l <= jj; ++l) {
+        const double rv = Ri[l + (size_t)jj * ke];
+        for (int i = 0; i < m; ++i) Y2[i + (size_t)jj * m] += Yf[i + (size_t)l * m] * rv;
+      }
+    T.swap(T3);
+    b.swap(b2);
+    Yf.swap(Y2);
+    *whitened = 1;
+    if (c->st) c->st->whitenings += 1;
+  }
+  // choose the rotation extent: skip untouched locked columns
+  bool lockedid = !*whitened;
+  for (int i = 0; i < q && lockedid; ++i) lockedid = (c->hcs[i] == 1.0);
+  if (lockedid) {
+    *in0 = q; *min = m - q; *out0 = q; *kout = p;
+    for (int jj = 0; jj < p; ++jj)
+      for (int l = 0; l < ma; ++l) c->hY[l + (size_t)jj * ma] = Yf[(q + l) + (size_t)(q + jj) * m];
+  } else {
+    *in0 = 0; *min = m; *out0 = 0; *kout = ke;
+    std::memcpy(c->hY, Yf.data(), (size_t)m * ke * 8);
+  }
+  *xscale = c->hcs[m];
+  // new device-side state (uploaded by the caller after locking)
+  std::fill(c->hB, c->hB + (size_t)(m + 1) * m, 0.0);
+  for (int jj = 0; jj < ke; ++jj) {
+    for (int i = 0; i < ke; ++i) hB[i + (size_t)jj * ldb] = T[i + (size_t)jj * ke];
+    hB[ke + (size_t)jj * ldb] = b[jj];
+  }
+  std::fill(c->hS, c->hS + (size_t)d * (m + 1), 0.0);
+  std::memcpy(c->hS, Sn.data(), (size_t)d * (ke + 1) * 8);
+  for (int i = 0; i <= m; ++i) c->hcs[i] = 1.0;
+  c->Tk = T;
+  c->bk = b;
+  return RKS_OK;
+}
+
+// Lock leading blocks whose b entries are small relative to their
+// eigenvalue (Section 4.4, with the relative test) and zero them.
+void lock_converged(rks_ctx* c) {
+  const int ke = c->keff, ldb = c->m + 1;
+  double tn = 0.0;
+  for (double v : c->Tk) tn += v * v;
+  tn = std::sqrt(tn);
+  std::vector<int> st, sz;
+  rks::blocks(ke, c->Tk.data(), ke, st, sz);
+  int q = c->q;
+  for (size_t bi = 0; bi < st.size(); ++bi) {
+    if (st[bi] < q) continue;
+    if (st[bi] != q) break;
+    const double lam = std::abs(rks::block_eig(c->Tk.data(), ke, st[bi], sz[bi]));
+    const double scale = std::max(lam, kUnitRoundoff * tn);
+    bool ok = true;
+    for (int i = st[bi]; i < st[bi] + sz[bi]; ++i) ok = ok && std::fabs(c->bk[i]) <= c->tol * scale;
+    if (!ok) break;
+    q = st[bi] + sz[bi];
+  }
+  for (int i = 0; i < q; ++i) {
+    c->bk[i] = 0.0;
+    c->hB[ke + (size_t)i * ldb] = 0.0;
+  }
+  c->q = q;
+}
+
+int push_state_and_rotate(rks_ctx* c, int in0, int min, int out0, int kout, double xscale) {
+  auto stm = c->env.stream;
+  HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)min * kout * 8, hipMemcpyHostToDevice, stm));
+  {
+    Prof p(c, CAT_ROTATE);
+    rks::launch_rotate(c->env, c->U, c->ldu, in0, min, c->U, c->ldu, out0, kout, c->Yd, c->m, c->keff, xscale, 0);
+  }
+  HIPCHK(c, hipGetLastError());
+  if (c->st) {
+    c->st->n_rotate += 1;
+    c->st->bytes_rotate += (double)(min + 1 + kout + 1) * c->n * c->vbytes;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->B, c->hB, (size_t)(c->m + 1) * c->m * 8, hipMemcpyHostToDevice, stm));
+  HIPCHK(c, hipMemcpyAsync(c->S, c->hS, (size_t)c->d * (c->m + 1) * 8, hipMemcpyHostToDevice, stm));
+  HIPCHK(c, hipMemcpyAsync(c->cs, c->hcs, (size_t)(c->m + 1) * 8, hipMemcpyHostToDevice, stm));
+  c->j = c->keff;
+  c->pending = 0;
+  return RKS_OK;
+}
+
+bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, std::string& why) {
+  if (rp[0] != 0) { why = "row_ptr[0] != 0"; return false; }
+  if (rp[n] != nnz) { why = "row_ptr[n] != nnz"; return false; }
+  for (int64_t i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) { why = "row_ptr not monotone"; return false; }
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n) { why = "column index out of range"; return false; }
+      if (e > rp[i] && col[e] <= col[e - 1]) { why = "columns not strictly increasing in a row"; return false; }
+    }
+  }
+  return true;
+}
+
+void free_all(rks_ctx* c) {
+  void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U, c->w, c->S, c->B, c->cs,
+                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  void* host[] = {c->hB, c->hS, c->hcs, c->hY, c->hflags};
+  for (void* p : host)
+    if (p) (void)hipHostFree(p);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+void rks_opts_default(rks_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sketch_kind = RKS_SKETCH_SPARSE;
+  o->zeta = 8;
+  o->sketch_seed = 0;
+  o->start_seed = 1;
+  o->precision = RKS_PREC_FP64;
+  o->max_restarts = 300;
+  o->lock = 1;
+  o->profile = 0;
+  o->whiten_tol = 1e-12;
+  o->stream = nullptr;
+}
+
+const char* rks_strerror(int code) { return code_str(code); }
+
+const char* rks_last_error(const rks_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which, double tol, const rks_opts* opts,
+               rks_ctx** out) {
+  g_create_err.clear();
+  if (!out) return fail(nullptr, RKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!A || !A->row_ptr || (A->nnz > 0 && (!A->col || !A->val))) return fail(nullptr, RKS_EINVAL, "CSR pointers");
+  const int64_t n = A->n, nnz = A->nnz;
+  rks_opts o;
+  if (opts) o = *opts; else rks_opts_default(&o);
+  if (n < 4 || nnz < 0 || nnz >= (int64_t)1 << 31 || n >= (int64_t)1 << 31)
+    return fail(nullptr, RKS_EINVAL, "need 4 <= n < 2^31 and nnz < 2^31");
+  if (k < 1 || k + 2 > m || m > rks::kMaxM || m + 1 > d || d > n || d > rks::kMaxD)
+    return fail(nullptr, RKS_EINVAL, "need 1 <= k, k+2 <= m <= 255, m+1 <= d <= min(n, 1024)");
+  if (k + 1 > rks::kRotMax) return fail(nullptr, RKS_EINVAL, "need k + 1 <= 64");
+  if (!(tol > 0.0) || which < 0 || which > 3) return fail(nullptr, RKS_EINVAL, "tol or which");
+  if (o.sketch_kind != RKS_SKETCH_GAUSS && o.sketch_kind != RKS_SKETCH_SPARSE)
+    return fail(nullptr, RKS_EINVAL, "sketch_kind");
+  if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
+    return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
+  if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0))
+    return fail(nullptr, RKS_EINVAL, "precision, max_restarts or whiten_tol");
+
+  rks_ctx* c = new (std::nothrow) rks_ctx();
+  if (!c) return fail(nullptr, RKS_ENOMEM, "context");
+  c->n = n; c->nnz = nnz; c->k = k; c->m = m; c->d = d; c->which = which; c->tol = tol; c->o = o;
+  hipStream_t stm = (hipStream_t)o.stream;
+  // host copies for validation, the 1-norm and the SpMV tiles
+  std::vector<int32_t> rp(n + 1), col(nnz);
+  std::vector<double> val(nnz);
+  if (A->on_device) {
+    if (hipMemcpy(rp.data(), A->row_ptr, (n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        (nnz && hipMemcpy(col.data(), A->col, nnz * 4, hipMemcpyDeviceToHost) != hipSuccess) ||
+        (nnz && hipMemcpy(val.data(), A->val, nnz * 8, hipMemcpyDeviceToHost) != hipSuccess)) {
+      delete c;
+      return fail(nullptr, RKS_EHIP, "copying the device CSR to the host");
+    }
+  } else {
+    std::memcpy(rp.data(), A->row_ptr, (n + 1) * 4);
+    if (nnz) {
+      std::memcpy(col.data(), A->col, nnz * 4);
+      std::memcpy(val.data(), A->val, nnz * 8);
+    }
+  }
+  std::string why;
+  if (!valid_csr(rp.data(), col.data(), n, nnz, why)) {
+    delete c;
+    return fail(nullptr, RKS_EINVAL, why);
+  }
+  std::vector<double> colsum(n, 0.0);
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (!std::isfinite(val[e])) {
+      delete c;
+      return fail(nullptr, RKS_ENAN, "non-finite value in A");
+    }
+    colsum[col[e]] += std::fabs(val[e]);
+  }
+  c->normA1 = n ? *std::max_element(colsum.begin(), colsum.end()) : 0.0;
+  // wave tiles: <= 64 rows and <= 512 nonzeros, or one long row
+  std::vector<int32_t> tiles;
+  tiles.push_back(0);
+  for (int64_t r = 0; r < n;) {
+    const int64_t s = r;
+    int64_t acc = 0;
+    if (rp[r + 1] - rp[r] > rks::kTileNnz) {
+      ++r;
+    } else {
+      while (r < n && r - s < rks::kTileRows && acc + (rp[r + 1] - rp[r]) <= rks::kTileNnz) {
+        acc += rp[r + 1] - rp[r];
+        ++r;
+      }
+    }
+    tiles.push_back((int32_t)r);
+  }
+  const int ntiles = (int)tiles.size() - 1;
+  c->vbytes = (o.precision == RKS_PREC_FP64) ? 8 : (o.precision == RKS_PREC_V32 ? 4 : 2);
+  c->wbytes = (o.precision == RKS_PREC_FP64) ? 8 : 4;
+  c->ldu = (n + 127) / 128 * 128;
+  bool ok = true;
+  std::string what;
+  auto dm = [&](void** p, size_t bytes) {
+    if (!ok) return;
+    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+    if (e != hipSuccess) {
+      ok = false;
+      what = "hipMalloc(" + std::to_string(bytes) + ") -> " + hipGetErrorString(e);
+    }
+  };
+  auto hm = [&](void** p, size_t bytes) {
+    if (!ok) return;
+    hipError_t e = hipHostMalloc(p, bytes ? bytes : 8, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      ok = false;
+      what = "hipHostMalloc(" + std::to_string(bytes) + ") -> " + hipGetErrorString(e);
+    }
+  };
+  dm((void**)&c->rp, (n + 1) * 4);
+  dm((void**)&c->col, nnz * 4);
+  dm((void**)&c->val, nnz * 8);
+  if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nnz * 4);
+  dm((void**)&c->tiles, tiles.size() * 4);
+  dm(&c->U, (size_t)c->ldu * (m + 1) * c->vbytes);
+  dm(&c->w, (size_t)n * 8);
+  dm((void**)&c->S, (size_t)d * (m + 1) * 8);
+  dm((void**)&c->B, (size_t)(m + 1) * m * 8);
+  dm((void**)&c->cs, (size_t)(m + 1) * 8);
+  dm((void**)&c->coef, (size_t)(m + 2) * 8);
+  dm((void**)&c->z, (size_t)d * 8);
+  dm((void**)&c->sr, (size_t)d * 8);
+  dm((void**)&c->zpart, (size_t)rks::kMaxG * d * 8);
+  dm((void**)&c->spart, (size_t)rks::kMaxG * d * 8);
+  dm((void**)&c->scal, 8 * 8);
+  dm((void**)&c->flags, 4 * 4);
+  dm((void**)&c->Yd, (size_t)(m + 1) * (m + 1) * 8);
+  dm((void**)&c->u0tmp, (size_t)n * 8);
+  hm((void**)&c->hB, (size_t)(m + 1) * m * 8);
+  hm((void**)&c->hS, (size_t)d * (m + 1) * 8);
+  hm((void**)&c->hcs, (size_t)(m + 1) * 8);
+  hm((void**)&c->hY, (size_t)(m + 1) * (m + 1) * 8);
+  hm((void**)&c->hflags, 4 * 4);
+  if (!ok) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, RKS_ENOMEM, what);
+  }
+  int rc = RKS_OK;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    if (rc == RKS_OK && bytes && hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) rc = RKS_EHIP;
+  };
+  cp(c->rp, rp.data(), (n + 1) * 4);
+  cp(c->col, col.data(), nnz * 4);
+  cp(c->val, val.data(), nnz * 8);
+  if (c->val32) {
+    std::vector<float> v32(val.begin(), val.end());
+    cp(c->val32, v32.data(), nnz * 4);
+  }
+  cp(c->tiles, tiles.data(), tiles.size() * 4);
+  if (rc == RKS_OK && hipMemset(c->U, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
+  if (rc != RKS_OK) {
+    free_all(c);
+    delete c;
+    return fail(nullptr, rc, "uploading the matrix");
+  }
+  auto& e = c->env;
+  e.stream = stm;
+  e.n = n;
+  e.prec = o.precision;
+  e.rp = c->rp;
+  e.col = c->col;
+  e.val = c->val;
+  e.val32 = c->val32;
+  e.tiles = c->tiles;
+  e.ntiles = ntiles;
+  e.sp_kind = o.sketch_kind;
+  e.sp.d = d;
+  e.sp.zeta = o.zeta;
+  e.sp.k0 = (uint32_t)o.sketch_seed;
+  e.sp.k1 = (uint32_t)(o.sketch_seed >> 32);
+  e.sp.scale = (o.sketch_kind == RKS_SKETCH_SPARSE) ? 1.0 / std::sqrt((double)o.zeta) : 1.0 / std::sqrt((double)d);
+  *out = c;
+  return RKS_OK;
+}
+
+void rks_destroy(rks_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->env.stream);
+  free_all(c);
+  delete c;
+}
+
+int32_t rks_num_pairs(const rks_ctx* c) { return c ? c->keff : 0; }
+
+int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st) {
+  if (!c) return RKS_EINVAL;
+  c->err.clear();
+  rks_stats local;
+  if (!st) st = &local;
+  std::memset(st, 0, sizeof(*st));
+  c->st = st;
+  const auto t0 = std::chrono::steady_clock::now();
+  double thost = 0.0;
+  int rc = start(c, u0, u0_on_device);
+  if (rc) { c->st = nullptr; return rc; }
+  rc = extend(c);
+  if (rc) { c->st = nullptr; return rc; }
+  int restarts = 0;
+  bool converged = false;
+  double maxest = 0.0;
+  while (true) {
+    rc = pull_state(c);
+    if (rc) break;
+    if (c->hflags[0] != 0) {
+      rc = fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(c->hflags[0]));
+      break;
+    }
+    const auto h0 = std::chrono::steady_clock::now();
+    int in0, min, out0, kout, wh;
+    double xscale;
+    rc = contract(c, &in0, &min, &out0, &kout, &xscale, &wh);
+    if (rc) break;
+    std::vector<cplx> lam, Y;
+    std::vector<double> est;
+    ritz(c, lam, Y, est);
+    maxest = 0.0;
+    bool allfinite = true;
+    for (double v : est) {
+      if (!std::isfinite(v)) allfinite = false;
+      maxest = std::max(maxest, v);
+    }
+    if (!allfinite) maxest = INFINITY;
+    if (restarts < 512) st->hist_est[restarts] = maxest;
+    converged = allfinite && maxest <= c->tol;
+    const bool stop = converged || restarts >= c->o.max_restarts;
+    if (!stop && c->o.lock) lock_converged(c);
+    thost += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+    rc = push_state_and_rotate(c, in0, min, out0, kout, xscale);
+    if (rc) break;
+    if (stop) break;
+    rc = extend(c);
+    if (rc) break;
+    ++restarts;
+  }
+  if (rc == RKS_OK) {
+    if (hipStreamSynchronize(c->env.stream) != hipSuccess) rc = fail(c, RKS_EHIP, "stream synchronize");
+    flush_events(c);
+  }
+  st->converged = converged ? 1 : 0;
+  st->restarts = restarts;
+  st->locked = c->q;
+  st->keff = c->keff;
+  st->max_est = maxest;
+  st->t_host = thost;
+  st->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  c->st = nullptr;
+  if (rc) return rc;
+  c->solved = true;
+  return converged ? RKS_OK : fail(c, RKS_ENOTCONV, "max_restarts reached");
+}
+
+int rks_eigpairs(rks_ctx* c, double* lam_re, double* lam_im, double* X, int32_t X_on_device, double* resid) {
+  if (!c) return RKS_EINVAL;
+  if (!c->solved) return fail(c, RKS_ESTATE, "rks_eigpairs before a successful rks_solve");
+  const int ke = c->keff;
+  const int64_t n = c->n;
+  std::vector<cplx> lam, Y;
+  std::vector<double> est;
+  ritz(c, lam, Y, est);
+  std::vector<int> ord(ke);
+  for (int i = 0; i < ke; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return rks::more_wanted(lam[a], lam[b], c->which); });
+  // packing matrix W (ke x ke): x = U_k W
+  std::vector<double> W((size_t)ke * ke, 0.0);
+  std::vector<int> pair_of(ke, 0);  // 0 real, 1 first of a pair, 2 second
+  std::vector<cplx> ls(ke);
+  for (int i = 0; i < ke; ++i) ls[i] = lam[ord[i]];
+  for (int i = 0; i < ke;) {
+    const cplx* y = &Y[(size_t)ord[i] * ke];
+    if (ls[i].imag() != 0.0 && i + 1 < ke) {
+      for (int r = 0; r < ke; ++r) {
+        W[r + (size_t)i * ke] = y[r].real();
+        W[r + (size_t)(i + 1) * ke] = y[r].imag();
+      }
+      pair_of[i] = 1;
+      pair_of[i + 1] = 2;
+      i += 2;
+    } else {
+      for (int r = 0; r < ke; ++r) W[r + (size_t)i * ke] = y[r].real();
+      i += 1;
+    }
+  }
+  const bool need_x = (X != nullptr) || (resid != nullptr);
+  if (need_x) {
+    auto stm = c->env.stream;
+    double* Xd = nullptr;
+    double *ax1 = nullptr, *ax2 = nullptr, *part = nullptr;
+    bool own = !(X && X_on_device);
+    int rc = RKS_OK;
+    if (own && hipMalloc(&Xd, (size_t)n * ke * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "X scratch");
+    if (!own) Xd = X;
+    if (hipMalloc(&ax1, (size_t)n * 8) != hipSuccess || hipMalloc(&ax2, (size_t)n * 8) != hipSuccess ||
+        hipMalloc(&part, (size_t)2 * rks::kMaxG * 8) != hipSuccess)
+      rc = fail(c, RKS_ENOMEM, "eigpairs scratch");
+    std::vector<double> hpart(2 * rks::kMaxG);
+    if (rc == RKS_OK) {
+      // X = U_k W in column chunks (out of place)
+      for (int c0 = 0; c0 < ke && rc == RKS_OK; c0 += rks::kRotMax) {
+        const int kc = std::min(rks::kRotMax, ke - c0);
+        for (int jj = 0; jj < kc; ++jj)
+          for (int r = 0; r < ke; ++r) c->hY[r + (size_t)jj * ke] = W[r + (size_t)(c0 + jj) * ke];
+        if (hipMemcpyAsync(c->Yd, c->hY, (size_t)ke * kc * 8, hipMemcpyHostToDevice, stm) != hipSuccess)
+          rc = fail(c, RKS_EHIP, "Y upload");
+        rks::launch_rotate(c->env, c->U, c->ldu, 0, ke, Xd, n, c0, kc, c->Yd, -1, 0, 0.0, 1);
+        if (hipStreamSynchronize(stm) != hipSuccess) rc = fail(c, RKS_EHIP, "rotation");
+      }
+      for (int i = 0; i < ke && rc == RKS_OK;) {
+        const bool cp = pair_of[i] == 1;
+        double* xa = Xd + (size_t)i * n;
+        double* xb = cp ? Xd + (size_t)(i + 1) * n : nullptr;
+        rks::launch_spmv_sketch(c->env, xa, ax1, nullptr, 0, 0);
+        if (cp) rks::launch_spmv_sketch(c->env, xb, ax2, nullptr, 0, 0);
+        const int G = rks::launch_resid(c->env, xa, xb, ax1, cp ? ax2 : nullptr, ls[i].real(), ls[i].imag(), part);
+        if (hipMemcpyAsync(hpart.data(), part, (size_t)2 * G * 8, hipMemcpyDeviceToHost, stm) != hipSuccess ||
+            hipStreamSynchronize(stm) != hipSuccess) {
+          rc = fail(c, RKS_EHIP, "residual");
+          break;
+        }
+        double rr = 0.0, xx = 0.0;
+        for (int g = 0; g < G; ++g) {
+          rr += hpart[2 * g];
+          xx += hpart[2 * g + 1];
+        }
+        const double res = std::sqrt(rr) / (c->normA1 * std::sqrt(xx));
+        const double sc = 1.0 / std::sqrt(xx);
+        rks::launch_scale(c->env, xa, sc);
+        if (cp) rks::launch_scale(c->env, xb, sc);
+        if (resid) {
+          resid[i] = res;
+          if (cp) resid[i + 1] = res;
+        }
+        i += cp ? 2 : 1;
+      }
+      if (rc == RKS_OK && X && !X_on_device) {
+        if (hipMemcpyAsync(X, Xd, (size_t)n * ke * 8, hipMemcpyDeviceToHost, stm) != hipSuccess)
+          rc = fail(c, RKS_EHIP, "X download");
+      }
+      if (rc == RKS_OK && hipStreamSynchronize(stm) != hipSuccess) rc = fail(c, RKS_EHIP, "synchronize");
+    }
+    if (own && Xd) (void)hipFree(Xd);
+    if (ax1) (void)hipFree(ax1);
+    if (ax2) (void)hipFree(ax2);
+    if (part) (void)hipFree(part);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < ke; ++i) {
+    if (lam_re) lam_re[i] = ls[i].real();
+    if (lam_im) lam_im[i] = ls[i].imag();
+  }
+  return RKS_OK;
+}
+
+int rks_sketch(rks_ctx* c, const double* x_dev, double* z_dev) {
+  if (!c || !x_dev || !z_dev) return RKS_EINVAL;
+  const int G = rks::launch_init(c->env, nullptr, x_dev, 0, 0, c->spart, 0, 0);
+  rks::launch_reduce(c->env, c->spart, G, nullptr, 0, z_dev, nullptr);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  return RKS_OK;
+}
+
+int rks_spmv_sketch(rks_ctx* c, const double* x_dev, double* w_dev, double* z_dev) {
+  if (!c || !x_dev || !w_dev || !z_dev) return RKS_EINVAL;
+  const int G = rks::launch_spmv_sketch(c->env, x_dev, w_dev, c->zpart, 1, 0);
+  rks::launch_reduce(c->env, c->zpart, G, nullptr, 0, z_dev, nullptr);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  return RKS_OK;
+}
+
+int rks_arnoldi(rks_ctx* c, const double* u0, int32_t u0_on_device) {
+  if (!c) return RKS_EINVAL;
+  c->err.clear();
+  c->st = nullptr;
+  int rc = start(c, u0, u0_on_device);
+  if (rc) return rc;
+  rc = extend(c);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  HIPCHK(c, hipMemcpy(c->hflags, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost));
+  if (c->hflags[0] != 0)
+    return fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(c->hflags[0]));
+  return RKS_OK;
+}
+
+int rks_get_state(rks_ctx* c, int32_t* ncols, double* B, double* S, double* U) {
+  if (!c) return RKS_EINVAL;
+  if (!c->have_state) return fail(c, RKS_ESTATE, "no decomposition yet");
+  int rc = pull_state(c);
+  if (rc) return rc;
+  const int nc = c->j + 1;
+  if (ncols) *ncols = nc;
+  if (B) std::memcpy(B, c->hB, (size_t)(c->m + 1) * c->m * 8);
+  if (S) std::memcpy(S, c->hS, (size_t)c->d * (c->m + 1) * 8);
+  if (U) {
+    const size_t colb = (size_t)c->ldu * c->vbytes;
+    std::vector<unsigned char> buf(colb);
+    for (int l = 0; l <= c->m; ++l) {
+      double* dst = U + (size_t)l * c->n;
+      if (l >= nc) {
+        std::fill(dst, dst + c->n, 0.0);
+        continue;
+      }
+      HIPCHK(c, hipMemcpy(buf.data(), basis_col(c, l), colb, hipMemcpyDeviceToHost));
+      const double s = c->hcs[l];
+      for (int64_t i = 0; i < c->n; ++i) {
+        double v;
+        if (c->vbytes == 8) {
+          std::memcpy(&v, &buf[i * 8], 8);
+        } else if (c->vbytes == 4) {
+          float f;
+          std::memcpy(&f, &buf[i * 4], 4);
+          v = f;
+        } else {
+          uint16_t h;
+          std::memcpy(&h, &buf[i * 2], 2);
+          uint32_t u = (uint32_t)h << 16;
+          float f;
+          std::memcpy(&f, &u, 4);
+          v = f;
+        }
+        dst[i] = v * s;
+      }
+    }
+  }
+  return RKS_OK;
+}
+
+int rks_rotate(rks_ctx* c, int32_t in0, int32_t min, int32_t out0, int32_t kout, const double* Y) {
+  if (!c || !Y) return RKS_EINVAL;
+  if (in0 < 0 || min < 1 || in0 + min > c->m + 1 || out0 < 0 || kout < 1 || kout > rks::kRotMax ||
+      out0 + kout > c->m + 1)
+    return RKS_EINVAL;
+  // the stored columns carry lazy scales: fold them into Y, then the
+  // outputs are normalised columns (scale 1)
+  HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  HIPCHK(c, hipMemcpy(c->hcs, c->cs, (size_t)(c->m + 1) * 8, hipMemcpyDeviceToHost));
+  for (int o = 0; o < kout; ++o)
+    for (int l = 0; l < min; ++l) c->hY[l + (size_t)o * min] = c->hcs[in0 + l] * Y[l + (size_t)o * min];
+  for (int o = 0; o < kout; ++o) c->hcs[out0 + o] = 1.0;
+  HIPCHK(c, hipMemcpy(c->Yd, c->hY, (size_t)min * kout * 8, hipMemcpyHostToDevice));
+  rks::launch_rotate(c->env, c->U, c->ldu, in0, min, c->U, c->ldu, out0, kout, c->Yd, -1, 0, 0.0, 0);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->cs, c->hcs, (size_t)(c->m + 1) * 8, hipMemcpyHostToDevice, c->env.stream));
+  HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  return RKS_OK;
+}
+
+int rks_host_schur(int32_t n, double* A, double* Z) {
+  if (n < 1 || !A || !Z) return RKS_EINVAL;
+  return rks::real_schur(n, A, n, Z, n) == 0 ? RKS_OK : RKS_EDENSE;
+}
+
+int rks_host_order(int32_t n, double* T, double* Z, int32_t which, int32_t kw, int32_t* p) {
+  if (n < 1 || !T || !Z || !p || which < 0 || which > 3 || kw < 0) return RKS_EINVAL;
+  int pp = 0;
+  const int r = rks::order_wanted(n, T, n, Z, n, which, kw, &pp);
+  *p = pp;
+  return r == 0 ? RKS_OK : RKS_EDENSE;
+}
+
+}  // extern "C"

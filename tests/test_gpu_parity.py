@@ -1,0 +1,238 @@
+"""GPU parity of the HIP hot path against the FP64 oracle (through the C-ABI).
+
+Tolerances follow from the arithmetic:
+  * a sum of N products computed in a different order differs by at most
+    about (log2 N + c) u sum|terms| (u = 2^-53); the kernels sum in blocks, so
+    elementwise checks use 64 u * sum|terms| (sketch, SpMV);
+  * the first extension is a sequence of projections whose rounding errors
+    the (sketched) Gram-Schmidt process keeps at O(j u ||A||) in the Krylov
+    relation; entrywise B is compared at 1e-9 relative to ||A||_1 and the
+    Ritz values at the paper-level bound 1e-10 relative (the oracle uses
+    Householder least squares, the GPU a projection with one re-projection).
+"""
+import numpy as np
+import pytest
+
+import paper_2508_05400_amd as P
+from oracle.rks import RKSOracle, rks as oracle_rks
+from oracle.sketch import sketch_matrix
+from workloads import convdiff2d, powerlaw_random, start_vector_normal, tridiag_noisy
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0**-53
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def sp_of(A):
+    import scipy.sparse as sp
+    return sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+
+
+SMALL = {
+    # ragged sizes: n not a multiple of the 64-row tile or the 256-thread block
+    "cd2d-37-gauss": (lambda: convdiff2d(37, (20.0, 10.0)), "gauss", 62),
+    "cd2d-37-sparse": (lambda: convdiff2d(37, (20.0, 10.0)), "sparse", 96),
+    "powerlaw-5003": (lambda: powerlaw_random(5003, 4), "sparse", 120),
+    "tridiag-4099": (lambda: tridiag_noisy(4099, "exponential", 5), "sparse", 64),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SMALL))
+def test_sketch_parity(lib, cuda, case):
+    mk, kind, d = SMALL[case]
+    A = mk()
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 4, 20, d, "LM", 1e-10,
+                       P.rks_opts_default(sketch_kind=kind, sketch_seed=11))
+    try:
+        x = start_vector_normal(A.n, 3)
+        z = cuda.zeros(d, dtype=cuda.float64, device="cuda")
+        P.rks_sketch(ctx, dev(cuda, x), z)
+        om = sketch_matrix(A.n, d, kind, 11)
+        ref = np.asarray(om @ x).ravel()
+        bound = np.asarray(abs(om) @ np.abs(x)).ravel()
+        err = np.abs(z.cpu().numpy() - ref)
+        assert np.all(err <= 64 * U64 * bound + 1e-300), (err.max(), bound.max())
+    finally:
+        P.rks_destroy(ctx)
+
+
+@pytest.mark.parametrize("case", sorted(SMALL))
+def test_spmv_sketch_parity(lib, cuda, case):
+    mk, kind, d = SMALL[case]
+    A = mk()
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 4, 20, d, "LM", 1e-10,
+                       P.rks_opts_default(sketch_kind=kind, sketch_seed=5))
+    try:
+        x = start_vector_normal(A.n, 9)
+        w = cuda.zeros(A.n, dtype=cuda.float64, device="cuda")
+        z = cuda.zeros(d, dtype=cuda.float64, device="cuda")
+        P.rks_spmv_sketch(ctx, dev(cuda, x), w, z)
+        S = sp_of(A)
+        wref = S @ x
+        wb = abs(S) @ np.abs(x)
+        assert np.all(np.abs(w.cpu().numpy() - wref) <= 64 * U64 * wb + 1e-300)
+        om = sketch_matrix(A.n, d, kind, 5)
+        zref = np.asarray(om @ wref).ravel()
+        zb = np.asarray(abs(om) @ wb).ravel()
+        assert np.all(np.abs(z.cpu().numpy() - zref) <= 64 * U64 * zb + 1e-300)
+    finally:
+        P.rks_destroy(ctx)
+
+
+ARN = {
+    "cd2d-37-gauss": (lambda: convdiff2d(37, (20.0, 10.0)), "gauss", 8, 30, 62),
+    "cd2d-37-sparse": (lambda: convdiff2d(37, (20.0, 10.0)), "sparse", 8, 30, 96),
+    "powerlaw-5003": (lambda: powerlaw_random(5003, 4), "sparse", 10, 40, 120),
+}
+
+
+@pytest.mark.parametrize("case", sorted(ARN))
+def test_arnoldi_parity(lib, cuda, case):
+    """First extension (Algorithm 2 from one column) vs the oracle: B, S, U."""
+    mk, kind, k, m, d = ARN[case]
+    A = mk()
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
+                       P.rks_opts_default(sketch_kind=kind, sketch_seed=2, start_seed=1))
+    try:
+        P.rks_arnoldi(ctx, None)          # seeded start generated on the device
+        B = np.zeros((m + 1, m), order="F")
+        S = np.zeros((d, m + 1), order="F")
+        U = np.zeros((A.n, m + 1), order="F")
+        nc = P.rks_get_state(ctx, B, S, U)
+        assert nc == m + 1
+        o = RKSOracle(A, k, m, d, "LM", 1e-10, sketch=kind, sketch_seed=2, start_seed=1)
+        o.start(None)
+        o.extend()
+        nA = o.normA1
+        # start vector (counter-based generator, both sides from its definition)
+        assert np.allclose(U[:, 0], o.U[:, 0], rtol=1e-13, atol=1e-15 * np.abs(o.U[:, 0]).max())
+        assert np.abs(B - o.B).max() <= 1e-9 * nA, np.abs(B - o.B).max() / nA
+        assert np.abs(S - o.S).max() <= 1e-9
+        assert np.abs(U - o.U).max() <= 1e-9 * np.abs(o.U).max()
+        # exact identities of the decomposition, on the GPU's own output
+        Sp = sp_of(A)
+        rel = np.linalg.norm(Sp @ U[:, :m] - U @ B) / (nA * np.linalg.norm(U[:, :m]))
+        assert rel < 1e-14
+        om = sketch_matrix(A.n, d, kind, 2)
+        OU = np.asarray(om @ U)
+        assert np.linalg.norm(OU.T @ OU - np.eye(m + 1)) < 1e-12
+        assert np.linalg.norm(OU - S) < 1e-12
+    finally:
+        P.rks_destroy(ctx)
+
+
+def test_rotate_parity(lib, cuda):
+    """In-place restart rotation U[:, out] <- U[:, in] Y, overlapping columns."""
+    A = convdiff2d(45, (20.0, 10.0))
+    m, d = 40, 90
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 10, m, d, "LR", 1e-10,
+                       P.rks_opts_default(sketch_kind="sparse"))
+    try:
+        P.rks_arnoldi(ctx, None)
+        U0 = np.zeros((A.n, m + 1), order="F")
+        P.rks_get_state(ctx, None, None, U0)
+        rng = np.random.default_rng(4)
+        for (in0, mi, out0, ko) in [(0, 40, 0, 11), (3, 37, 3, 17), (0, 40, 5, 33), (2, 30, 0, 64 - 30)]:
+            Y = rng.standard_normal((mi, ko))
+            P.rks_get_state(ctx, None, None, U0)
+            before = U0.copy()
+            P.rks_rotate(ctx, in0, mi, out0, ko, Y)
+            after = np.zeros_like(U0)
+            P.rks_get_state(ctx, None, None, after)
+            ref = before.copy()
+            ref[:, out0:out0 + ko] = before[:, in0:in0 + mi] @ Y
+            bound = np.abs(before[:, in0:in0 + mi]) @ np.abs(Y)
+            err = np.abs(after[:, out0:out0 + ko] - ref[:, out0:out0 + ko])
+            assert np.all(err <= 64 * U64 * bound + 1e-300)
+            untouched = [c for c in range(m + 1) if not (out0 <= c < out0 + ko)]
+            assert np.array_equal(after[:, untouched], ref[:, untouched])
+    finally:
+        P.rks_destroy(ctx)
+
+
+CONV = {
+    # mildly non-normal operators on which rKS converges within the cap
+    "cd2d-40-LR-sparse": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse"),
+    "cd2d-40-LM-gauss": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LM", "gauss"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CONV))
+def test_solve_parity_converged(lib, cuda, case):
+    mk, k, m, d, which, kind = CONV[case]
+    A = mk()
+    ref = oracle_rks(A, k, m, d, which, 1e-10, sketch=kind, sketch_seed=3, start_seed=1)
+    assert ref.converged
+    s = P.Solver.from_csr(A, k=k, m=m, d=d, which=which, tol=1e-10, sketch_kind=kind, sketch_seed=3,
+                          start_seed=1)
+    try:
+        code = s.solve()
+        assert code == 0, P.rks_last_error(s.ctx)
+        lam, X, res = s.eigpairs()
+        assert len(lam) == len(ref.lam)
+        rel = np.abs(lam - ref.lam) / np.abs(ref.lam)
+        assert rel.max() <= 1e-10, rel
+        assert res.max() <= 1e-8
+        assert abs(s.stats.restarts - ref.restarts) <= 1
+        # the returned vectors really are eigenvectors of A (independent check)
+        Sp = sp_of(A)
+        i = 0
+        while i < len(lam):
+            if lam[i].imag != 0:
+                x = X[:, i] + 1j * X[:, i + 1]
+                step = 2
+            else:
+                x = X[:, i]
+                step = 1
+            normA1 = abs(Sp).sum(axis=0).max()
+            r = np.linalg.norm(Sp @ x - lam[i] * x) / (normA1 * np.linalg.norm(x))
+            assert abs(r - res[i]) <= 1e-6 * max(r, 1e-30) + 1e-15
+            assert abs(np.linalg.norm(x) - 1.0) < 1e-12
+            i += step
+    finally:
+        s.close()
+
+
+def test_solve_parity_fixed_restarts(lib, cuda):
+    """The 100^2 convection-diffusion workload (Gaussian sketch d = 80): both
+    sides run 6 restarts from the same start; the leading Ritz values agree."""
+    A = convdiff2d(100, (20.0, 10.0))
+    k, m, d = 10, 40, 80
+    ref = oracle_rks(A, k, m, d, "LR", 1e-10, sketch="gauss", sketch_seed=0, start_seed=1, max_restarts=6)
+    s = P.Solver.from_csr(A, k=k, m=m, d=d, which="LR", tol=1e-10, sketch_kind="gauss", sketch_seed=0,
+                          start_seed=1, max_restarts=6)
+    try:
+        code = s.solve()
+        assert code in (0, 1)
+        lam, _, res = s.eigpairs(want_vectors=False, want_resid=True)
+        assert s.stats.restarts == ref.restarts
+        hist = np.array(s.stats.hist_est[:ref.restarts + 1])
+        np.testing.assert_allclose(hist, ref.history, rtol=1e-3)
+        # the five leading (best converged) Ritz values
+        rel = np.abs(lam[:5] - ref.lam[:5]) / np.abs(ref.lam[:5])
+        assert rel.max() <= 1e-10, rel
+    finally:
+        s.close()
+
+
+def test_error_paths(lib, cuda):
+    A = convdiff2d(20)
+    s = P.Solver.from_csr(A, k=4, m=12, d=30, which="LR", tol=1e-14, max_restarts=1)
+    try:
+        with pytest.raises(P.RksError) as ei:
+            P.rks_eigpairs(s.ctx, np.zeros(4), np.zeros(4), None, None)
+        assert ei.value.code == -5  # RKS_ESTATE
+        assert s.solve() == 1       # RKS_ENOTCONV, results still usable
+        lam, X, res = s.eigpairs()
+        assert np.all(np.isfinite(lam))
+        with pytest.raises(P.RksError) as ei:
+            bad = np.zeros(A.n)
+            bad[3] = np.nan
+            s.solve(bad)
+        assert ei.value.code == -4  # RKS_ENAN
+    finally:
+        s.close()

@@ -1,0 +1,129 @@
+"""CPU tests of the C-ABI library: exported symbols, host small dense code
+(real Schur form and reordering, Algorithm 1 lines 2-3) against LAPACK, and
+argument validation that rejects bad input before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import paper_2508_05400_amd as P
+from oracle.rks import which_key
+from workloads import convdiff2d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)   # drop comments
+            names |= set(re.findall(r"\b(rks_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+    # and the binding knows all of them
+    from paper_2508_05400_amd._binding import SIGNATURES
+    assert set(declared) == set(SIGNATURES)
+
+
+def test_strerror_and_defaults(lib):
+    assert P.rks_strerror(0) == "ok"
+    assert "invalid" in P.rks_strerror(-1)
+    o = P.rks_opts_default()
+    assert (o.zeta, o.max_restarts, o.lock, o.sketch_kind, o.precision) == (8, 300, 1, 1, 0)
+    assert o.whiten_tol == 1e-12 and o.start_seed == 1
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_host_schur_matches_lapack(lib, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 90))
+    A = rng.standard_normal((n, n))
+    if seed % 3 == 1:
+        A += 8 * np.triu(A, 1)            # strongly non-normal
+    if seed % 3 == 2:
+        A = np.diag(rng.standard_normal(n)) + 1e-6 * A
+    T, Z = P.rks_host_schur(A)
+    assert np.linalg.norm(Z @ T @ Z.T - A) <= 1e-13 * n * max(np.linalg.norm(A), 1)
+    assert np.linalg.norm(Z.T @ Z - np.eye(n)) <= 1e-13 * n
+    assert np.all(np.tril(T, -2) == 0)
+    ev = np.sort_complex(np.linalg.eigvals(A))
+    got = np.sort_complex(sla.eigvals(T))
+    assert np.allclose(got, ev, atol=1e-9 * max(np.abs(ev).max(), 1))
+
+
+@pytest.mark.parametrize("which", ["LM", "SM", "LR", "SR"])
+@pytest.mark.parametrize("seed", range(10))
+def test_host_order_selects_wanted(lib, which, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(8, 70))
+    A = rng.standard_normal((n, n)) + (3 * np.triu(rng.standard_normal((n, n)), 1) if seed % 2 else 0)
+    T, Z = P.rks_host_schur(A)
+    kw = max(1, n // 4)
+    T2, Z2, p = P.rks_host_order(T, Z, which, kw)
+    assert p in (kw, kw + 1)
+    assert np.linalg.norm(Z2 @ T2 @ Z2.T - A) <= 1e-12 * n * np.linalg.norm(A)
+    lead = sla.eigvals(T2[:p, :p])
+    allv = np.linalg.eigvals(A)
+    order = sorted(allv, key=lambda z: which_key(z, which), reverse=True)
+    want = np.array(order[:p])
+    assert np.allclose(np.sort_complex(lead), np.sort_complex(want), atol=1e-8 * np.abs(allv).max())
+    # same invariant subspace as LAPACK's reordering (dtrsen) of the same set
+    Tl, Zl = sla.schur(A, output="real")
+    sel = np.zeros(n, dtype=np.int32)
+    diag_ev = sla.eigvals(Tl)
+    for z in want:
+        sel[np.argmin(np.abs(diag_ev - z) + 1e9 * sel)] = 1
+    Ts, Zs, *_ = sla.lapack.dtrsen(sel, Tl, Zl, job="N")
+    s = np.linalg.svd(Zs[:, :p].T @ Z2[:, :p], compute_uv=False)
+    assert s.min() > 1 - 1e-8
+
+
+def test_create_rejects_bad_arguments(lib):
+    A = convdiff2d(10)
+    bad = [
+        dict(k=0, m=10, d=20), dict(k=9, m=10, d=20), dict(k=3, m=10, d=10),   # k, m, d relation
+        dict(k=3, m=10, d=200), dict(k=3, m=300, d=400),                      # d > n, m too large
+    ]
+    for b in bad:
+        with pytest.raises(P.RksError) as ei:
+            P.rks_create(A.row_ptr, A.col, A.val, A.n, b["k"], b["m"], b["d"], "LM", 1e-10)
+        assert ei.value.code == -1
+    with pytest.raises(P.RksError):
+        P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 0.0)
+    with pytest.raises(P.RksError):
+        P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 1e-10, P.rks_opts_default(zeta=9))
+    # malformed CSR: decreasing row pointer, column out of range, unsorted row
+    rp = A.row_ptr.copy(); rp[5] = rp[4] - 1
+    with pytest.raises(P.RksError):
+        P.rks_create(rp, A.col, A.val, A.n, 3, 10, 20, "LM", 1e-10)
+    col = A.col.copy(); col[7] = A.n
+    with pytest.raises(P.RksError):
+        P.rks_create(A.row_ptr, col, A.val, A.n, 3, 10, 20, "LM", 1e-10)
+    col = A.col.copy(); col[[10, 11]] = col[[11, 10]]
+    with pytest.raises(P.RksError):
+        P.rks_create(A.row_ptr, col, A.val, A.n, 3, 10, 20, "LM", 1e-10)
+    val = A.val.copy(); val[3] = np.inf
+    with pytest.raises(P.RksError) as ei:
+        P.rks_create(A.row_ptr, A.col, val, A.n, 3, 10, 20, "LM", 1e-10)
+    assert ei.value.code == -4
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The library package must not import the oracle or fall back to the CPU."""
+    pkg = os.path.join(ROOT, "paper_2508_05400_amd")
+    for dp, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                txt = open(os.path.join(dp, fn)).read()
+                assert "oracle" not in txt.lower(), fn
