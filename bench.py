@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--max-restarts", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--resid-tol", type=float, default=1e-8,
+                    help="verified FP64 residual target of the metric (0 = paper's estimate test only)")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP events")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block "
@@ -96,7 +99,8 @@ def main():
     solver = P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
-                               max_restarts=cfg.get("max_restarts", 300), profile=1, stream=stream)
+                               max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else 1,
+                               resid_tol=args.resid_tol, stream=stream)
     for _ in range(args.warmup):
         solver.solve()
     torch.cuda.synchronize()
@@ -140,6 +144,9 @@ def main():
                    "n": A.n, "nnz": A.nnz, "k": cfg["k"], "m": cfg["m"], "d": cfg["d"],
                    "which": cfg["which"], "tol": cfg["tol"], "precision": cfg["precision"]},
         "converged": bool(st["converged"]),
+        "stop_reason": {0: "restart cap", 1: "estimates <= tol", 2: "verified residual <= resid_tol"}[st["stop_reason"]],
+        "resid_tol": args.resid_tol,
+        "resid_checks": st["resid_checks"],
         "restarts": st["restarts"],
         "matvecs": st["matvecs"],
         "locked": st["locked"],

@@ -80,6 +80,10 @@ typedef struct {
   int32_t profile;       /* 1: time the n-dimensional kernels with HIP events, default 0 */
   double whiten_tol;     /* whiten when ||S_k^T S_k - I||_F exceeds this, default 1e-12 */
   void* stream;          /* hipStream_t, NULL = default stream */
+  double resid_tol;      /* > 0: also stop once every pair's FP64 residual
+                            ||A x - lambda x|| / (||A||_1 ||x||) is verified on the
+                            device to be <= resid_tol (checked only when the
+                            estimates predict it); default 0 = off */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -95,6 +99,9 @@ typedef struct {
   int32_t whitenings;    /* whitening steps applied */
   int32_t dense_fail;    /* reorderings that had to stop early */
   double max_est;        /* max |b^T y| / |lambda| at exit (eq. "rks_reserror_bound") */
+  int32_t stop_reason;   /* 0 restart cap, 1 estimates <= tol, 2 verified residuals <= resid_tol */
+  int32_t resid_checks;  /* device residual verifications performed */
+  double max_resid;      /* largest verified residual at exit (0 if never verified) */
   double t_total;        /* seconds, host wall clock of the solve */
   double t_host;         /* seconds spent in the host small dense steps */
   /* kernel timings (only when opts.profile = 1), seconds summed over launches */
@@ -117,18 +124,21 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
 
 /* Run Algorithm 1 from the start vector u0 (n FP64 values, host or device
  * per u0_on_device; NULL = the seeded N(0,1) start), scaled so that
- * ||Omega u1|| = 1.  Stops when every estimate is <= tol, or after
- * max_restarts cycles (RKS_ENOTCONV).  Synchronises with the host once per
- * restart.  Errors: RKS_EINVAL, RKS_ENAN, RKS_EBREAKDOWN, RKS_EDENSE, RKS_EHIP. */
+ * ||Omega u1|| = 1.  Stops when every estimate is <= tol (the paper's test,
+ * Section 5), when opts.resid_tol > 0 and every FP64 residual is verified to
+ * be <= resid_tol, or after max_restarts cycles (RKS_ENOTCONV).  Synchronises
+ * with the host once per restart.
+ * Errors: RKS_EINVAL, RKS_ENAN, RKS_EBREAKDOWN, RKS_EDENSE, RKS_EHIP. */
 int rks_solve(struct rks_ctx* ctx, const double* u0, int32_t u0_on_device, rks_stats* st);
 
 /* Number of pairs rks_eigpairs returns (k, or k+1 to keep a conjugate pair). */
 int32_t rks_num_pairs(const struct rks_ctx* ctx);
 
 /* Eigenpairs after rks_solve, sorted by `which`: lam_re/lam_im[keff] (host),
- * X (n x keff, column-major; real Ritz vectors, a conjugate pair packed as
- * real part then imaginary part of the member with positive imaginary part,
- * each of unit 2-norm; NULL to skip), resid[keff] (host, NULL to skip) with
+ * X (n x keff, column-major; real Ritz vectors of unit 2-norm, a conjugate
+ * pair packed as real part then imaginary part of the member with positive
+ * imaginary part, that complex vector of unit 2-norm; NULL to skip),
+ * resid[keff] (host, NULL to skip) with
  * resid = ||A x - lambda x||_2 / (||A||_1 ||x||_2) computed in FP64 on the
  * device (eq. "RitzError" side).  X_on_device selects where X lives.
  * Errors: RKS_ESTATE before a solve, RKS_EHIP. */

@@ -29,14 +29,17 @@ class RksOpts(ctypes.Structure):
                 ("sketch_seed", ctypes.c_uint64), ("start_seed", ctypes.c_uint64),
                 ("precision", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("lock", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("whiten_tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("whiten_tol", ctypes.c_double), ("stream", ctypes.c_void_p),
+                ("resid_tol", ctypes.c_double)]
 
 
 class RksStats(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("matvecs", ctypes.c_int64), ("locked", ctypes.c_int32), ("keff", ctypes.c_int32),
                 ("whitenings", ctypes.c_int32), ("dense_fail", ctypes.c_int32),
-                ("max_est", ctypes.c_double), ("t_total", ctypes.c_double), ("t_host", ctypes.c_double),
+                ("max_est", ctypes.c_double), ("stop_reason", ctypes.c_int32),
+                ("resid_checks", ctypes.c_int32), ("max_resid", ctypes.c_double),
+                ("t_total", ctypes.c_double), ("t_host", ctypes.c_double),
                 ("t_spmv", ctypes.c_double), ("t_reduce", ctypes.c_double), ("t_ls", ctypes.c_double),
                 ("t_update", ctypes.c_double), ("t_rotate", ctypes.c_double),
                 ("n_spmv", ctypes.c_int64), ("n_update", ctypes.c_int64), ("n_rotate", ctypes.c_int64),

@@ -55,85 +55,111 @@ __device__ __forceinline__ void bins_store(const double* bins, double* part, int
 
 // ---------------------------------------------------------------------------
 // w = A x (CSR, wave tiles staged through LDS) and partials of Omega w.
-// Each wave owns one tile of <= 64 rows / <= 512 nonzeros per iteration: the
-// nonzeros are loaded coalesced, multiplied by the gathered x and staged in
-// LDS; then 64/nr lanes per row reduce the row from LDS.  A tile that is a
-// single row longer than 512 nonzeros is reduced by the whole wave.
+// Each wave owns one tile of <= 64 rows / <= 512 nonzeros at a time: a lane
+// loads up to 8 nonzeros (coalesced, all loads issued before any use), gathers
+// x for them, and stages the products in the wave's own LDS slice; then
+// 64/nr lanes per row reduce the row from LDS.  LDS operations of one wave
+// complete in program order, so the wave needs no block-level barrier.  A
+// tile that is a single row longer than 512 nonzeros is reduced by the wave.
 template <typename TV, typename TW, typename TA, int KIND>
-__global__ __launch_bounds__(256) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
+__global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
                                                      const TA* __restrict__ val, const int* __restrict__ tiles,
                                                      int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
                                                      double* __restrict__ zpart, SketchP sp, int do_sketch) {
   __shared__ double bins[kMaxD];
-  __shared__ TA prod[4][kTileNnz];
+  __shared__ TA prod[8][kTileNnz];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
-  for (int base = blockIdx.x * 4; base < ntiles; base += gridDim.x * 4) {
-    const int t = base + wv;
-    int r0 = 0, nr = 0, e0 = 0, ne = 0;
-    if (t < ntiles) {
-      r0 = tiles[t];
-      nr = tiles[t + 1] - r0;
-      e0 = rp[r0];
-      ne = rp[r0 + nr] - e0;
-    }
-    const bool staged = (t < ntiles) && ne <= kTileNnz;
-    if (staged) {
-      for (int e = lane; e < ne; e += 64)
-        prod[wv][e] = val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
-    }
-    __syncthreads();
-    if (t < ntiles) {
-      TA s = 0;
-      int rr, sub;
-      if (staged) {
-        int lpr = 64;
-        while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
-        rr = lane / lpr;
-        sub = lane - rr * lpr;
-        if (rr < nr) {
-          const int a = rp[r0 + rr] - e0, b = rp[r0 + rr + 1] - e0;
-          for (int e = a + sub; e < b; e += lpr) s += prod[wv][e];
+  TA* pw = prod[wv];
+  for (int t = blockIdx.x * 8 + wv; t < ntiles; t += gridDim.x * 8) {
+    const int r0 = tiles[t], r1 = tiles[t + 1];
+    const int nr = r1 - r0;
+    const int e0 = rp[r0];
+    const int ne = rp[r1] - e0;
+    TA s = 0;
+    int rr, sub;
+    if (ne <= kTileNnz) {
+      int lpr = 64;
+      while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
+      rr = lane / lpr;
+      sub = lane - rr * lpr;
+      int ra = 0, rb = 0;
+      if (rr < nr) {
+        ra = rp[r0 + rr] - e0;
+        rb = rp[r0 + rr + 1] - e0;
+      }
+      int ci[kTileNnz / 64];
+      TA vv[kTileNnz / 64];
+#pragma unroll
+      for (int u = 0; u < kTileNnz / 64; ++u) {
+        const int e = lane + 64 * u;
+        if (e < ne) {
+          ci[u] = col[e0 + e];
+          vv[u] = val[e0 + e];
         }
-        for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
-      } else {
-        rr = 0;
-        sub = lane;
-        for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
       }
-      if (rr < nr && sub == 0) {
-        const int r = r0 + rr;
-        const TW ws = (TW)s;
-        w[r] = ws;
-        if (do_sketch) sketch_add<KIND>(bins, (uint64_t)r, (double)ws, sp);
+      TA xv[kTileNnz / 64];
+#pragma unroll
+      for (int u = 0; u < kTileNnz / 64; ++u) {
+        const int e = lane + 64 * u;
+        if (e < ne) xv[u] = (TA)Conv<TV>::ld(x[ci[u]]);
       }
+#pragma unroll
+      for (int u = 0; u < kTileNnz / 64; ++u) {
+        const int e = lane + 64 * u;
+        if (e < ne) pw[e] = vv[u] * xv[u];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (rr < nr)
+        for (int e = ra + sub; e < rb; e += lpr) s += pw[e];
+      for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      rr = 0;
+      sub = lane;
+      for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     }
-    __syncthreads();
+    if (rr < nr && sub == 0) {
+      const int r = r0 + rr;
+      const TW ws = (TW)s;
+      w[r] = ws;
+      if (do_sketch) sketch_add<KIND>(bins, (uint64_t)r, (double)ws, sp);
+    }
   }
+  __syncthreads();
   if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
 }
 
-// Deterministic sum of G partial rows: block (x, y) sums 16 bins of array y.
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pa, const double* __restrict__ pb,
-                                                int Ga, int Gb, int d, double* __restrict__ oa,
-                                                double* __restrict__ ob) {
+// Deterministic sum of G partial rows: block (x, y) sums 32 bins of array y;
+// 32 slices of rows per bin, each slice summed with 4 independent chains.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ pa, const double* __restrict__ pb,
+                                                 int Ga, int Gb, int d, double* __restrict__ oa,
+                                                 double* __restrict__ ob) {
   const double* p = blockIdx.y ? pb : pa;
   double* o = blockIdx.y ? ob : oa;
   const int G = blockIdx.y ? Gb : Ga;
   if (p == nullptr) return;
-  __shared__ double red[16][17];
-  const int lb = threadIdx.x & 15, sl = threadIdx.x >> 4;
-  const int b = blockIdx.x * 16 + lb;
-  double s = 0.0;
-  if (b < d)
-    for (int g = sl; g < G; g += 16) s += p[(size_t)g * d + b];
-  red[sl][lb] = s;
+  __shared__ double red[32][33];
+  const int lb = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int b = blockIdx.x * 32 + lb;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (b < d) {
+    int g = sl;
+    for (; g + 96 < G; g += 128) {
+      a0 += p[(size_t)g * d + b];
+      a1 += p[(size_t)(g + 32) * d + b];
+      a2 += p[(size_t)(g + 64) * d + b];
+      a3 += p[(size_t)(g + 96) * d + b];
+    }
+    for (; g < G; g += 32) a0 += p[(size_t)g * d + b];
+  }
+  red[sl][lb] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (threadIdx.x < 16 && b < d) {
+  if (threadIdx.x < 32 && b < d) {
     double tot = 0.0;
-    for (int q = 0; q < 16; ++q) tot += red[q][lb];
+    for (int q = 0; q < 32; ++q) tot += red[q][lb];
     o[b] = tot;
   }
 }
@@ -143,16 +169,20 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ pa, c
 // projection h = S_t^+ z computed as h = S^T z plus one re-projection
 // h += S^T (z - S h).  Writes B(0:t, t) = h and the coefficients the update
 // needs: coef[l] = h_l * scale_l (l <= t), coef[t+1] = scale_t.
-__global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int finalize_only,
+// When it fits, S(:, 0:t) is staged in LDS once and all three products read
+// it from there; otherwise they read it from L2 with unrolled loops.
+__global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int finalize_only, int use_lds,
                                              const double* __restrict__ zraw, const double* __restrict__ sraw,
                                              double* __restrict__ S, double* __restrict__ B, int ldb,
                                              double* __restrict__ cs, double* __restrict__ coef,
                                              double* __restrict__ scal, int* __restrict__ flags, double bd_rel) {
-  __shared__ double snew[kMaxD];
-  __shared__ double zs[kMaxD];
-  __shared__ double rs[kMaxD];
-  __shared__ double hs[kMaxM + 2];
-  __shared__ double red[16];
+  extern __shared__ double sm[];
+  double* snew = sm;
+  double* zs = snew + d;
+  double* rs = zs + d;
+  double* hs = rs + d;             // kMaxM + 2
+  double* red = hs + kMaxM + 2;    // 16
+  double* Ssh = red + 16;          // d * (t + 1) when use_lds
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   double ct;
   if (pending) {
@@ -183,37 +213,63 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   }
   if (finalize_only) return;
   __syncthreads();
+  const int ncol = t + 1;
+  if (use_lds) {
+    const int tot = d * t;
+    int idx = tid;
+    for (; idx + 3 * 1024 < tot; idx += 4 * 1024) {
+      const double v0 = S[idx], v1 = S[idx + 1024], v2 = S[idx + 2048], v3 = S[idx + 3072];
+      Ssh[idx] = v0;
+      Ssh[idx + 1024] = v1;
+      Ssh[idx + 2048] = v2;
+      Ssh[idx + 3072] = v3;
+    }
+    for (; idx < tot; idx += 1024) Ssh[idx] = S[idx];
+    for (int b = tid; b < d; b += blockDim.x) Ssh[(size_t)t * d + b] = pending ? snew[b] : S[(size_t)t * d + b];
+  }
+  const double* Sc = use_lds ? Ssh : S;
   double s = 0.0;
   for (int b = tid; b < d; b += blockDim.x) {
     const double v = zraw[b] * ct;
     zs[b] = v;
     s += v * v;
   }
-  s = block_sum(s, red);
+  s = block_sum(s, red);  // also publishes Ssh and zs
   if (tid == 0) scal[0] = sqrt(s);
-  // h = S^T z
-  for (int l = wv; l <= t; l += nw) {
-    const double* Sl = S + (size_t)l * d;
-    const bool nu = pending && l == t;
+  // h = S^T z: one wave per column, lanes over the sketch rows
+  for (int l = wv; l < ncol; l += nw) {
+    const bool nu = !use_lds && pending && l == t;
+    const double* Sl = nu ? snew : Sc + (size_t)l * d;
     double a = 0.0;
-    for (int b = lane; b < d; b += 64) a += (nu ? snew[b] : Sl[b]) * zs[b];
+#pragma unroll 4
+    for (int b = lane; b < d; b += 64) a += Sl[b] * zs[b];
     a = wave_sum(a);
     if (lane == 0) hs[l] = a;
   }
   __syncthreads();
-  // r = z - S h
+  // r = z - S h: one thread per sketch row, 4 independent chains over columns
   for (int b = tid; b < d; b += blockDim.x) {
-    double a = zs[b];
-    for (int l = 0; l <= t; ++l) a -= ((pending && l == t) ? snew[b] : S[b + (size_t)l * d]) * hs[l];
-    rs[b] = a;
+    double a0 = zs[b], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int l = 0;
+    const int lim = (!use_lds && pending) ? t : ncol;
+    for (; l + 4 <= lim; l += 4) {
+      a0 -= Sc[b + (size_t)l * d] * hs[l];
+      a1 -= Sc[b + (size_t)(l + 1) * d] * hs[l + 1];
+      a2 -= Sc[b + (size_t)(l + 2) * d] * hs[l + 2];
+      a3 -= Sc[b + (size_t)(l + 3) * d] * hs[l + 3];
+    }
+    for (; l < lim; ++l) a0 -= Sc[b + (size_t)l * d] * hs[l];
+    if (lim == t) a0 -= snew[b] * hs[t];
+    rs[b] = (a0 + a1) + (a2 + a3);
   }
   __syncthreads();
   // h += S^T r
-  for (int l = wv; l <= t; l += nw) {
-    const double* Sl = S + (size_t)l * d;
-    const bool nu = pending && l == t;
+  for (int l = wv; l < ncol; l += nw) {
+    const bool nu = !use_lds && pending && l == t;
+    const double* Sl = nu ? snew : Sc + (size_t)l * d;
     double a = 0.0;
-    for (int b = lane; b < d; b += 64) a += (nu ? snew[b] : Sl[b]) * rs[b];
+#pragma unroll 4
+    for (int b = lane; b < d; b += 64) a += Sl[b] * rs[b];
     a = wave_sum(a);
     if (lane == 0) hs[l] += a;
   }
@@ -229,7 +285,7 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
 // u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
 // basis precision) as the new column; partials of Omega of the stored value.
 template <typename TV, typename TW, int KIND>
-__global__ __launch_bounds__(256) void k_update(int64_t n, int ncol, const TV* __restrict__ U, int64_t ldu,
+__global__ __launch_bounds__(512) void k_update(int64_t n, int ncol, const TV* __restrict__ U, int64_t ldu,
                                                 const TW* __restrict__ w, const double* __restrict__ coef,
                                                 TV* __restrict__ unew, double* __restrict__ spart, SketchP sp) {
   __shared__ double bins[kMaxD];
@@ -262,7 +318,7 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, int ncol, const TV* _
 // First column: u0 (device FP64) or the seeded N(0,1) start, stored in the
 // basis precision when `store`; partials of Omega of the stored value.
 template <typename TV, int KIND>
-__global__ __launch_bounds__(256) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
+__global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
                                               uint32_t s0, uint32_t s1, double* __restrict__ spart, SketchP sp,
                                               int store) {
   __shared__ double bins[kMaxD];
@@ -384,8 +440,8 @@ inline int grid_for(int64_t work, int per_block, int cap) {
 
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
   const int prec = prec_override >= 0 ? prec_override : e.prec;
-  const int G = grid_for(e.ntiles, 4, kMaxG);
-  dim3 grid(G), block(256);
+  const int G = grid_for(e.ntiles, 8, kMaxG);
+  dim3 grid(G), block(512);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<double, double, double, KIND><<<grid, block, 0, e.stream>>>(
                                      e.rp, e.col, e.val, e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
@@ -403,20 +459,30 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
 }
 
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob) {
-  dim3 grid((e.sp.d + 15) / 16, 2), block(256);
+  dim3 grid((e.sp.d + 31) / 32, 2), block(1024);
   k_reduce<<<grid, block, 0, e.stream>>>(pa, pb, Ga, Gb, e.sp.d, oa, ob);
 }
 
 void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
                double* S, double* B, int ldb, double* cs, double* coef, double* scal, int* flags, double bd_rel) {
-  k_ls<<<1, 1024, 0, e.stream>>>(t, e.sp.d, pending, finalize_only, zraw, sraw, S, B, ldb, cs, coef, scal, flags,
-                                 bd_rel);
+  const int d = e.sp.d;
+  const size_t base = (size_t)(3 * d + kMaxM + 2 + 16) * 8;
+  const size_t full = base + (size_t)d * (t + 1) * 8;
+  const int use_lds = (!finalize_only && full <= kLsLdsMax) ? 1 : 0;
+  const size_t lds = use_lds ? full : base;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_ls, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLsLdsMax);
+    attr = true;
+  }
+  k_ls<<<1, 1024, lds, e.stream>>>(t, d, pending, finalize_only, use_lds, zraw, sraw, S, B, ldb, cs, coef, scal,
+                                   flags, bd_rel);
 }
 
 int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
                   void* unew, double* spart) {
-  const int G = grid_for(e.n, 256, kMaxG);
-  dim3 grid(G), block(256);
+  const int G = grid_for(e.n, 512, kMaxG);
+  dim3 grid(G), block(512);
   if (e.prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_update<double, double, KIND><<<grid, block, 0, e.stream>>>(
                                      e.n, ncol, (const double*)U, ldu, (const double*)w, coef, (double*)unew,
@@ -436,8 +502,8 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
                 int prec_override) {
   const int prec = prec_override >= 0 ? prec_override : e.prec;
-  const int G = grid_for(e.n, 256, kMaxG);
-  dim3 grid(G), block(256);
+  const int G = grid_for(e.n, 512, kMaxG);
+  dim3 grid(G), block(512);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_init<double, KIND><<<grid, block, 0, e.stream>>>(e.n, (double*)u, u0, s0, s1,
                                                                                      spart, e.sp, store)));

@@ -19,10 +19,11 @@ namespace rks {
 
 constexpr int kMaxD = 1024;      // largest sketch size (LDS bins)
 constexpr int kMaxM = 255;       // largest Krylov dimension
-constexpr int kMaxG = 1024;      // largest number of partial-sum rows
+constexpr int kMaxG = 512;       // largest number of partial-sum rows (producer blocks)
 constexpr int kTileRows = 64;    // rows per SpMV wave tile
 constexpr int kTileNnz = 512;    // nonzeros staged per SpMV wave tile
 constexpr int kRotMax = 64;      // output columns per rotation pass
+constexpr size_t kLsLdsMax = 150 * 1024;  // LDS budget of the least-squares kernel
 
 struct bf16_t {
   uint16_t b;

@@ -68,6 +68,7 @@ struct rks_ctx {
   void* w = nullptr;
   double *S = nullptr, *B = nullptr, *cs = nullptr, *coef = nullptr, *z = nullptr, *sr = nullptr;
   double *zpart = nullptr, *spart = nullptr, *scal = nullptr, *Yd = nullptr, *u0tmp = nullptr;
+  double *Xr = nullptr, *ax1 = nullptr, *ax2 = nullptr, *rpart = nullptr;  // residual scratch (lazy)
   // pinned host mirrors
   double *hB = nullptr, *hS = nullptr, *hcs = nullptr, *hY = nullptr;
   int* hflags = nullptr;
@@ -422,7 +423,7 @@ void lock_converged(rks_ctx* c) {
   c->q = q;
 }
 
-int push_state_and_rotate(rks_ctx* c, int in0, int min, int out0, int kout, double xscale) {
+int rotate_basis(rks_ctx* c, int in0, int min, int out0, int kout, double xscale) {
   auto stm = c->env.stream;
   HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)min * kout * 8, hipMemcpyHostToDevice, stm));
   {
@@ -434,11 +435,110 @@ int push_state_and_rotate(rks_ctx* c, int in0, int min, int out0, int kout, doub
     c->st->n_rotate += 1;
     c->st->bytes_rotate += (double)(min + 1 + kout + 1) * c->n * c->vbytes;
   }
+  return RKS_OK;
+}
+
+int push_state(rks_ctx* c) {
+  auto stm = c->env.stream;
   HIPCHK(c, hipMemcpyAsync(c->B, c->hB, (size_t)(c->m + 1) * c->m * 8, hipMemcpyHostToDevice, stm));
   HIPCHK(c, hipMemcpyAsync(c->S, c->hS, (size_t)c->d * (c->m + 1) * 8, hipMemcpyHostToDevice, stm));
   HIPCHK(c, hipMemcpyAsync(c->cs, c->hcs, (size_t)(c->m + 1) * 8, hipMemcpyHostToDevice, stm));
   c->j = c->keff;
   c->pending = 0;
+  return RKS_OK;
+}
+
+// Ritz pairs sorted by `which` and the real packing matrix W (ke x ke) with
+// x = U_k W: a conjugate pair occupies two columns (real, imaginary part).
+struct Packed {
+  std::vector<cplx> lam;
+  std::vector<double> W;
+  std::vector<int> pair_of;  // 0 real, 1 first of a pair, 2 second
+};
+
+Packed pack_ritz(const rks_ctx* c) {
+  const int ke = c->keff;
+  std::vector<cplx> lam, Y;
+  std::vector<double> est;
+  ritz(c, lam, Y, est);
+  std::vector<int> ord(ke);
+  for (int i = 0; i < ke; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return rks::more_wanted(lam[a], lam[b], c->which); });
+  Packed P;
+  P.lam.resize(ke);
+  P.W.assign((size_t)ke * ke, 0.0);
+  P.pair_of.assign(ke, 0);
+  for (int i = 0; i < ke; ++i) P.lam[i] = lam[ord[i]];
+  for (int i = 0; i < ke;) {
+    const cplx* y = &Y[(size_t)ord[i] * ke];
+    if (P.lam[i].imag() != 0.0 && i + 1 < ke) {
+      for (int r = 0; r < ke; ++r) {
+        P.W[r + (size_t)i * ke] = y[r].real();
+        P.W[r + (size_t)(i + 1) * ke] = y[r].imag();
+      }
+      P.pair_of[i] = 1;
+      P.pair_of[i + 1] = 2;
+      i += 2;
+    } else {
+      for (int r = 0; r < ke; ++r) P.W[r + (size_t)i * ke] = y[r].real();
+      i += 1;
+    }
+  }
+  return P;
+}
+
+int ensure_resid_scratch(rks_ctx* c) {
+  const size_t cols = (size_t)c->k + 1;
+  if (!c->Xr && hipMalloc(&c->Xr, (size_t)c->n * cols * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "residual X");
+  if (!c->ax1 && hipMalloc(&c->ax1, (size_t)c->n * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "residual AX");
+  if (!c->ax2 && hipMalloc(&c->ax2, (size_t)c->n * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "residual AX");
+  if (!c->rpart && hipMalloc(&c->rpart, (size_t)2 * rks::kMaxG * 8) != hipSuccess)
+    return fail(c, RKS_ENOMEM, "residual partials");
+  return RKS_OK;
+}
+
+// X = U_k W on the device (FP64, n x ke, leading dimension n), then the FP64
+// residual of every pair; optionally X columns are normalised to unit norm.
+int device_residuals(rks_ctx* c, const Packed& P, double* Xd, double* resid, bool normalise) {
+  auto stm = c->env.stream;
+  const int ke = c->keff;
+  const int64_t n = c->n;
+  HIPCHK(c, hipStreamSynchronize(stm));  // the pinned staging buffer hY may still be in flight
+  for (int c0 = 0; c0 < ke; c0 += rks::kRotMax) {
+    const int kc = std::min(rks::kRotMax, ke - c0);
+    for (int jj = 0; jj < kc; ++jj)
+      for (int r = 0; r < ke; ++r) c->hY[r + (size_t)jj * ke] = P.W[r + (size_t)(c0 + jj) * ke];
+    HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)ke * kc * 8, hipMemcpyHostToDevice, stm));
+    rks::launch_rotate(c->env, c->U, c->ldu, 0, ke, Xd, n, c0, kc, c->Yd, -1, 0, 0.0, 1);
+    HIPCHK(c, hipStreamSynchronize(stm));  // hY is reused by the next chunk
+  }
+  std::vector<double> hpart(2 * rks::kMaxG);
+  for (int i = 0; i < ke;) {
+    const bool cp = P.pair_of[i] == 1;
+    double* xa = Xd + (size_t)i * n;
+    double* xb = cp ? Xd + (size_t)(i + 1) * n : nullptr;
+    rks::launch_spmv_sketch(c->env, xa, c->ax1, nullptr, 0, 0);
+    if (cp) rks::launch_spmv_sketch(c->env, xb, c->ax2, nullptr, 0, 0);
+    const int G = rks::launch_resid(c->env, xa, xb, c->ax1, cp ? c->ax2 : nullptr, P.lam[i].real(),
+                                    P.lam[i].imag(), c->rpart);
+    HIPCHK(c, hipMemcpyAsync(hpart.data(), c->rpart, (size_t)2 * G * 8, hipMemcpyDeviceToHost, stm));
+    HIPCHK(c, hipStreamSynchronize(stm));
+    double rr = 0.0, xx = 0.0;
+    for (int g = 0; g < G; ++g) {
+      rr += hpart[2 * g];
+      xx += hpart[2 * g + 1];
+    }
+    const double res = std::sqrt(rr) / (c->normA1 * std::sqrt(xx));
+    if (normalise) {
+      const double sc = 1.0 / std::sqrt(xx);
+      rks::launch_scale(c->env, xa, sc);
+      if (cp) rks::launch_scale(c->env, xb, sc);
+    }
+    resid[i] = res;
+    if (cp) resid[i + 1] = res;
+    i += cp ? 2 : 1;
+  }
+  HIPCHK(c, hipGetLastError());
   return RKS_OK;
 }
 
@@ -457,7 +557,8 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 
 void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U, c->w, c->S, c->B, c->cs,
-                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp};
+                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp,
+                 c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {c->hB, c->hS, c->hcs, c->hY, c->hflags};
@@ -483,6 +584,7 @@ void rks_opts_default(rks_opts* o) {
   o->profile = 0;
   o->whiten_tol = 1e-12;
   o->stream = nullptr;
+  o->resid_tol = 0.0;
 }
 
 const char* rks_strerror(int code) { return code_str(code); }
@@ -508,8 +610,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "sketch_kind");
   if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
-  if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0))
-    return fail(nullptr, RKS_EINVAL, "precision, max_restarts or whiten_tol");
+  if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
+      !(o.resid_tol >= 0.0))
+    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol or resid_tol");
 
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");
@@ -675,7 +778,8 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   if (rc) { c->st = nullptr; return rc; }
   int restarts = 0;
   bool converged = false;
-  double maxest = 0.0;
+  int reason = 0;
+  double maxest = 0.0, maxres = 0.0, last_fail_pred = INFINITY;
   while (true) {
     rc = pull_state(c);
     if (rc) break;
@@ -692,18 +796,42 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
     std::vector<double> est;
     ritz(c, lam, Y, est);
     maxest = 0.0;
+    double pred = 0.0;  // estimated backward residual relative to ||A||_1
     bool allfinite = true;
-    for (double v : est) {
-      if (!std::isfinite(v)) allfinite = false;
-      maxest = std::max(maxest, v);
+    for (int i = 0; i < (int)est.size(); ++i) {
+      if (!std::isfinite(est[i])) allfinite = false;
+      maxest = std::max(maxest, est[i]);
+      pred = std::max(pred, est[i] * std::abs(lam[i]) / c->normA1);
     }
-    if (!allfinite) maxest = INFINITY;
+    if (!allfinite) maxest = pred = INFINITY;
     if (restarts < 512) st->hist_est[restarts] = maxest;
     converged = allfinite && maxest <= c->tol;
-    const bool stop = converged || restarts >= c->o.max_restarts;
-    if (!stop && c->o.lock) lock_converged(c);
     thost += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
-    rc = push_state_and_rotate(c, in0, min, out0, kout, xscale);
+    rc = rotate_basis(c, in0, min, out0, kout, xscale);
+    if (rc) break;
+    if (converged) {
+      reason = 1;
+    } else if (c->o.resid_tol > 0.0 && allfinite && pred <= c->o.resid_tol && pred <= 0.5 * last_fail_pred) {
+      // the estimates predict the target residual: verify it in FP64 on the device
+      rc = ensure_resid_scratch(c);
+      if (rc) break;
+      Packed P = pack_ritz(c);
+      std::vector<double> res(c->keff, 0.0);
+      rc = device_residuals(c, P, c->Xr, res.data(), false);
+      if (rc) break;
+      st->resid_checks += 1;
+      double mr = 0.0;
+      for (double v : res) mr = std::max(mr, v);
+      if (mr <= c->o.resid_tol) {
+        reason = 2;
+        maxres = mr;
+      } else {
+        last_fail_pred = pred;
+      }
+    }
+    const bool stop = reason != 0 || restarts >= c->o.max_restarts;
+    if (!stop && c->o.lock) lock_converged(c);
+    rc = push_state(c);
     if (rc) break;
     if (stop) break;
     rc = extend(c);
@@ -714,7 +842,9 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
     if (hipStreamSynchronize(c->env.stream) != hipSuccess) rc = fail(c, RKS_EHIP, "stream synchronize");
     flush_events(c);
   }
-  st->converged = converged ? 1 : 0;
+  st->converged = reason != 0 ? 1 : 0;
+  st->stop_reason = reason;
+  st->max_resid = maxres;
   st->restarts = restarts;
   st->locked = c->q;
   st->keff = c->keff;
@@ -724,106 +854,29 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   c->st = nullptr;
   if (rc) return rc;
   c->solved = true;
-  return converged ? RKS_OK : fail(c, RKS_ENOTCONV, "max_restarts reached");
+  return reason != 0 ? RKS_OK : fail(c, RKS_ENOTCONV, "max_restarts reached");
 }
 
 int rks_eigpairs(rks_ctx* c, double* lam_re, double* lam_im, double* X, int32_t X_on_device, double* resid) {
   if (!c) return RKS_EINVAL;
   if (!c->solved) return fail(c, RKS_ESTATE, "rks_eigpairs before a successful rks_solve");
   const int ke = c->keff;
-  const int64_t n = c->n;
-  std::vector<cplx> lam, Y;
-  std::vector<double> est;
-  ritz(c, lam, Y, est);
-  std::vector<int> ord(ke);
-  for (int i = 0; i < ke; ++i) ord[i] = i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return rks::more_wanted(lam[a], lam[b], c->which); });
-  // packing matrix W (ke x ke): x = U_k W
-  std::vector<double> W((size_t)ke * ke, 0.0);
-  std::vector<int> pair_of(ke, 0);  // 0 real, 1 first of a pair, 2 second
-  std::vector<cplx> ls(ke);
-  for (int i = 0; i < ke; ++i) ls[i] = lam[ord[i]];
-  for (int i = 0; i < ke;) {
-    const cplx* y = &Y[(size_t)ord[i] * ke];
-    if (ls[i].imag() != 0.0 && i + 1 < ke) {
-      for (int r = 0; r < ke; ++r) {
-        W[r + (size_t)i * ke] = y[r].real();
-        W[r + (size_t)(i + 1) * ke] = y[r].imag();
-      }
-      pair_of[i] = 1;
-      pair_of[i + 1] = 2;
-      i += 2;
-    } else {
-      for (int r = 0; r < ke; ++r) W[r + (size_t)i * ke] = y[r].real();
-      i += 1;
-    }
-  }
-  const bool need_x = (X != nullptr) || (resid != nullptr);
-  if (need_x) {
-    auto stm = c->env.stream;
-    double* Xd = nullptr;
-    double *ax1 = nullptr, *ax2 = nullptr, *part = nullptr;
-    bool own = !(X && X_on_device);
-    int rc = RKS_OK;
-    if (own && hipMalloc(&Xd, (size_t)n * ke * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "X scratch");
-    if (!own) Xd = X;
-    if (hipMalloc(&ax1, (size_t)n * 8) != hipSuccess || hipMalloc(&ax2, (size_t)n * 8) != hipSuccess ||
-        hipMalloc(&part, (size_t)2 * rks::kMaxG * 8) != hipSuccess)
-      rc = fail(c, RKS_ENOMEM, "eigpairs scratch");
-    std::vector<double> hpart(2 * rks::kMaxG);
-    if (rc == RKS_OK) {
-      // X = U_k W in column chunks (out of place)
-      for (int c0 = 0; c0 < ke && rc == RKS_OK; c0 += rks::kRotMax) {
-        const int kc = std::min(rks::kRotMax, ke - c0);
-        for (int jj = 0; jj < kc; ++jj)
-          for (int r = 0; r < ke; ++r) c->hY[r + (size_t)jj * ke] = W[r + (size_t)(c0 + jj) * ke];
-        if (hipMemcpyAsync(c->Yd, c->hY, (size_t)ke * kc * 8, hipMemcpyHostToDevice, stm) != hipSuccess)
-          rc = fail(c, RKS_EHIP, "Y upload");
-        rks::launch_rotate(c->env, c->U, c->ldu, 0, ke, Xd, n, c0, kc, c->Yd, -1, 0, 0.0, 1);
-        if (hipStreamSynchronize(stm) != hipSuccess) rc = fail(c, RKS_EHIP, "rotation");
-      }
-      for (int i = 0; i < ke && rc == RKS_OK;) {
-        const bool cp = pair_of[i] == 1;
-        double* xa = Xd + (size_t)i * n;
-        double* xb = cp ? Xd + (size_t)(i + 1) * n : nullptr;
-        rks::launch_spmv_sketch(c->env, xa, ax1, nullptr, 0, 0);
-        if (cp) rks::launch_spmv_sketch(c->env, xb, ax2, nullptr, 0, 0);
-        const int G = rks::launch_resid(c->env, xa, xb, ax1, cp ? ax2 : nullptr, ls[i].real(), ls[i].imag(), part);
-        if (hipMemcpyAsync(hpart.data(), part, (size_t)2 * G * 8, hipMemcpyDeviceToHost, stm) != hipSuccess ||
-            hipStreamSynchronize(stm) != hipSuccess) {
-          rc = fail(c, RKS_EHIP, "residual");
-          break;
-        }
-        double rr = 0.0, xx = 0.0;
-        for (int g = 0; g < G; ++g) {
-          rr += hpart[2 * g];
-          xx += hpart[2 * g + 1];
-        }
-        const double res = std::sqrt(rr) / (c->normA1 * std::sqrt(xx));
-        const double sc = 1.0 / std::sqrt(xx);
-        rks::launch_scale(c->env, xa, sc);
-        if (cp) rks::launch_scale(c->env, xb, sc);
-        if (resid) {
-          resid[i] = res;
-          if (cp) resid[i + 1] = res;
-        }
-        i += cp ? 2 : 1;
-      }
-      if (rc == RKS_OK && X && !X_on_device) {
-        if (hipMemcpyAsync(X, Xd, (size_t)n * ke * 8, hipMemcpyDeviceToHost, stm) != hipSuccess)
-          rc = fail(c, RKS_EHIP, "X download");
-      }
-      if (rc == RKS_OK && hipStreamSynchronize(stm) != hipSuccess) rc = fail(c, RKS_EHIP, "synchronize");
-    }
-    if (own && Xd) (void)hipFree(Xd);
-    if (ax1) (void)hipFree(ax1);
-    if (ax2) (void)hipFree(ax2);
-    if (part) (void)hipFree(part);
+  Packed P = pack_ritz(c);
+  if (X || resid) {
+    int rc = ensure_resid_scratch(c);
     if (rc) return rc;
+    double* Xd = (X && X_on_device) ? X : c->Xr;
+    std::vector<double> res(ke, 0.0);
+    rc = device_residuals(c, P, Xd, res.data(), true);
+    if (rc) return rc;
+    if (X && !X_on_device)
+      HIPCHK(c, hipMemcpyAsync(X, Xd, (size_t)c->n * ke * 8, hipMemcpyDeviceToHost, c->env.stream));
+    HIPCHK(c, hipStreamSynchronize(c->env.stream));
+    if (resid) std::memcpy(resid, res.data(), (size_t)ke * 8);
   }
   for (int i = 0; i < ke; ++i) {
-    if (lam_re) lam_re[i] = ls[i].real();
-    if (lam_im) lam_im[i] = ls[i].imag();
+    if (lam_re) lam_re[i] = P.lam[i].real();
+    if (lam_im) lam_im[i] = P.lam[i].imag();
   }
   return RKS_OK;
 }
