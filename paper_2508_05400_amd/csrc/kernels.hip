@@ -63,20 +63,19 @@ __device__ __forceinline__ void bins_store(const double* bins, double* part, int
 // tile that is a single row longer than 512 nonzeros is reduced by the wave.
 template <typename TV, typename TW, typename TA, int KIND>
 __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
-                                                     const TA* __restrict__ val, const int* __restrict__ tiles,
+                                                     const TA* __restrict__ val, const int4* __restrict__ tdesc,
                                                      int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
                                                      double* __restrict__ zpart, SketchP sp, int do_sketch) {
   __shared__ double bins[kMaxD];
   __shared__ TA prod[8][kTileNnz];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
   TA* pw = prod[wv];
   for (int t = blockIdx.x * 8 + wv; t < ntiles; t += gridDim.x * 8) {
-    const int r0 = tiles[t], r1 = tiles[t + 1];
-    const int nr = r1 - r0;
-    const int e0 = rp[r0];
-    const int ne = rp[r1] - e0;
+    const int4 dsc = tdesc[t];  // {first row, rows, first nonzero, nonzeros}, wave-uniform
+    const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
     TA s = 0;
     int rr, sub;
     if (ne <= kTileNnz) {
@@ -169,8 +168,11 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ pa, 
 // projection h = S_t^+ z computed as h = S^T z plus one re-projection
 // h += S^T (z - S h).  Writes B(0:t, t) = h and the coefficients the update
 // needs: coef[l] = h_l * scale_l (l <= t), coef[t+1] = scale_t.
-// When it fits, S(:, 0:t) is staged in LDS once and all three products read
-// it from there; otherwise they read it from L2 with unrolled loops.
+// When S(:, 0:t) fits in LDS, every global load of the kernel (S, the two raw
+// sketches) is issued in one round at entry and the three products then run
+// from LDS; otherwise they read S from L2 with unrolled loops.
+constexpr int kLsPre = 20;  // S values per thread staged through registers (LDS path)
+
 __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int finalize_only, int use_lds,
                                              const double* __restrict__ zraw, const double* __restrict__ sraw,
                                              double* __restrict__ S, double* __restrict__ B, int ldb,
@@ -184,21 +186,32 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   double* red = hs + kMaxM + 2;    // 16
   double* Ssh = red + 16;          // d * (t + 1) when use_lds
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  // ---- every global load up front ----
+  const int tot = use_lds ? d * t : 0;
+  double sv[kLsPre];
+#pragma unroll
+  for (int u = 0; u < kLsPre; ++u) {
+    const int idx = tid + 1024 * u;
+    sv[u] = (idx < tot) ? S[idx] : 0.0;
+  }
+  double srv = 0.0, zrv = 0.0, stv = 0.0, ctg = 0.0;
+  if (tid < d) {
+    if (pending) srv = sraw[tid];
+    else if (use_lds) stv = S[(size_t)t * d + tid];
+    if (!finalize_only) zrv = zraw[tid];
+  }
+  if (!pending) ctg = cs[t];
+  // ---- finalise the pending column ----
   double ct;
   if (pending) {
-    double s = 0.0;
-    for (int b = tid; b < d; b += blockDim.x) {
-      const double v = sraw[b];
-      snew[b] = v;
-      s += v * v;
-    }
-    s = block_sum(s, red);
+    const double s = block_sum(srv * srv, red);
     const double beta = sqrt(s);
     const double inv = 1.0 / beta;
-    for (int b = tid; b < d; b += blockDim.x) {
-      const double v = snew[b] * inv;
-      snew[b] = v;
-      S[b + (size_t)t * d] = v;
+    if (tid < d) {
+      const double v = srv * inv;
+      snew[tid] = v;
+      S[tid + (size_t)t * d] = v;
+      stv = v;
     }
     if (tid == 0) {
       cs[t] = inv;
@@ -209,33 +222,26 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
     }
     ct = inv;
   } else {
-    ct = cs[t];
+    ct = ctg;
   }
   if (finalize_only) return;
-  __syncthreads();
   const int ncol = t + 1;
   if (use_lds) {
-    const int tot = d * t;
-    int idx = tid;
-    for (; idx + 3 * 1024 < tot; idx += 4 * 1024) {
-      const double v0 = S[idx], v1 = S[idx + 1024], v2 = S[idx + 2048], v3 = S[idx + 3072];
-      Ssh[idx] = v0;
-      Ssh[idx + 1024] = v1;
-      Ssh[idx + 2048] = v2;
-      Ssh[idx + 3072] = v3;
+#pragma unroll
+    for (int u = 0; u < kLsPre; ++u) {
+      const int idx = tid + 1024 * u;
+      if (idx < tot) Ssh[idx] = sv[u];
     }
-    for (; idx < tot; idx += 1024) Ssh[idx] = S[idx];
-    for (int b = tid; b < d; b += blockDim.x) Ssh[(size_t)t * d + b] = pending ? snew[b] : S[(size_t)t * d + b];
+    if (tid < d) Ssh[(size_t)t * d + tid] = stv;
   }
   const double* Sc = use_lds ? Ssh : S;
-  double s = 0.0;
-  for (int b = tid; b < d; b += blockDim.x) {
-    const double v = zraw[b] * ct;
-    zs[b] = v;
-    s += v * v;
+  double zv = 0.0;
+  if (tid < d) {
+    zv = zrv * ct;
+    zs[tid] = zv;
   }
-  s = block_sum(s, red);  // also publishes Ssh and zs
-  if (tid == 0) scal[0] = sqrt(s);
+  const double s2 = block_sum(zv * zv, red);  // also publishes Ssh, snew and zs
+  if (tid == 0) scal[0] = sqrt(s2);
   // h = S^T z: one wave per column, lanes over the sketch rows
   for (int l = wv; l < ncol; l += nw) {
     const bool nu = !use_lds && pending && l == t;
@@ -282,34 +288,72 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   if (tid == 0) coef[t + 1] = ct;
 }
 
+// 16-byte packets of the basis: V = 16 / sizeof(TV) consecutive rows.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+union Pack16 {
+  u32x4 raw;
+  T v[16 / sizeof(T)];
+};
+
 // u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
 // basis precision) as the new column; partials of Omega of the stored value.
+// Each thread owns V consecutive rows and streams every basis column once
+// with one 16-byte non-temporal load per column; the coefficients are
+// wave-uniform and come through the scalar path.  Padding rows (>= n, < ldu)
+// are zero in U and w, so packets may run past n; they stay zero and are
+// left out of the sketch.
 template <typename TV, typename TW, int KIND>
-__global__ __launch_bounds__(512) void k_update(int64_t n, int ncol, const TV* __restrict__ U, int64_t ldu,
-                                                const TW* __restrict__ w, const double* __restrict__ coef,
-                                                TV* __restrict__ unew, double* __restrict__ spart, SketchP sp) {
+__global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U,
+                                                int64_t ldu, const TW* __restrict__ w,
+                                                const double* __restrict__ coef, TV* __restrict__ unew,
+                                                double* __restrict__ spart, SketchP sp) {
+  constexpr int V = 16 / sizeof(TV);
+  constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
   __shared__ double bins[kMaxD];
-  __shared__ double cf[kMaxM + 2];
   bins_zero(bins, sp.d);
-  for (int l = threadIdx.x; l <= ncol; l += blockDim.x) cf[l] = coef[l];
   __syncthreads();
-  const double ws = cf[ncol];
+  const double ws = coef[ncol];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double a[8];
-    a[0] = ws * (double)w[i];
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < npk; g += stride) {
+    const int64_t i0 = g * V;
+    double a[V];
+    {
+      Pack16<TW> wp[WCH];
 #pragma unroll
-    for (int q = 1; q < 8; ++q) a[q] = 0.0;
+      for (int c = 0; c < WCH; ++c) wp[c].raw = *(const u32x4*)(w + i0 + c * (16 / sizeof(TW)));
+#pragma unroll
+      for (int c = 0; c < WCH; ++c)
+#pragma unroll
+        for (int r = 0; r < 16 / (int)sizeof(TW); ++r) a[c * (16 / sizeof(TW)) + r] = ws * (double)wp[c].v[r];
+    }
+    const TV* col0 = U + i0;
     int l = 0;
     for (; l + 8 <= ncol; l += 8) {
+      Pack16<TV> p[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[q] -= cf[l + q] * Conv<TV>::ld(U[i + (int64_t)(l + q) * ldu]);
+      for (int q = 0; q < 8; ++q) p[q].raw = __builtin_nontemporal_load((const u32x4*)(col0 + (int64_t)(l + q) * ldu));
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double cq = coef[l + q];
+#pragma unroll
+        for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p[q].v[r]);
+      }
     }
-    for (; l < ncol; ++l) a[0] -= cf[l] * Conv<TV>::ld(U[i + (int64_t)l * ldu]);
-    const double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    const TV st = Conv<TV>::st(v);
-    unew[i] = st;
-    sketch_add<KIND>(bins, (uint64_t)i, Conv<TV>::ld(st), sp);
+    for (; l < ncol; ++l) {
+      Pack16<TV> p;
+      p.raw = __builtin_nontemporal_load((const u32x4*)(col0 + (int64_t)l * ldu));
+      const double cq = coef[l];
+#pragma unroll
+      for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p.v[r]);
+    }
+    Pack16<TV> o;
+#pragma unroll
+    for (int r = 0; r < V; ++r) o.v[r] = Conv<TV>::st(a[r]);
+    __builtin_nontemporal_store(o.raw, (u32x4*)(unew + i0));
+#pragma unroll
+    for (int r = 0; r < V; ++r)
+      if (i0 + r < n) sketch_add<KIND>(bins, (uint64_t)(i0 + r), Conv<TV>::ld(o.v[r]), sp);
   }
   __syncthreads();
   bins_store(bins, spart, sp.d, sp.scale);
@@ -341,36 +385,64 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
   bins_store(bins, spart, sp.d, sp.scale);
 }
 
-// O(:, out0 + o) = sum_l U(:, in0 + l) Y(l, o) for o < kout, row by row so
-// the output columns may overlap the input columns; optionally also
-// U(:, xdst) = xscale * U(:, xsrc) (read before any write of the row).
-template <typename TI, typename TO, int KM>
+// O(:, out0 + o) = sum_l U(:, in0 + l) Y(l, o) for o < kout on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64).  A wave owns a 16-row tile: lane
+// (r, k) = (lane % 16, lane / 16) feeds A(r, k) = U(row0 + r, in0 + k0 + k) and
+// B(k, c) = Y(k0 + k, 16 nt + c) for c = lane % 16; the accumulator holds
+// D(lane / 16 + 4 i, lane % 16), i < 4.  The wave reads every input column
+// of its rows before it writes any output, so outputs may overlap inputs
+// (in-place restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename TI, typename TO, int NT>
 __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
                                                 int64_t ldo, int out0, int kout, const double* __restrict__ Y,
                                                 int xsrc, int xdst, double xscale) {
-  extern __shared__ double Ys[];
-  for (int idx = threadIdx.x; idx < min * KM; idx += blockDim.x) {
-    const int l = idx / KM, o = idx - l * KM;
-    Ys[idx] = (o < kout) ? Y[l + (size_t)o * min] : 0.0;
+  extern __shared__ double Ys[];  // minp x (16 NT), zero padded
+  constexpr int KC = 16 * NT;
+  const int minp = (min + 15) & ~15;
+  for (int idx = threadIdx.x; idx < minp * KC; idx += blockDim.x) {
+    const int l = idx / KC, o = idx - l * KC;
+    Ys[idx] = (l < min && o < kout) ? Y[l + (size_t)o * min] : 0.0;
   }
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double acc[KM];
-#pragma unroll
-    for (int o = 0; o < KM; ++o) acc[o] = 0.0;
-    for (int l = 0; l < min; ++l) {
-      const double x = Conv<TI>::ld(U[i + (int64_t)(in0 + l) * ldu]);
-      const double* yr = Ys + l * KM;
-#pragma unroll
-      for (int o = 0; o < KM; ++o) acc[o] += x * yr[o];
-    }
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t ntile = (n + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += (int64_t)gridDim.x * 4) {
+    const int64_t row = tile * 16 + lr;
+    const bool rin = row < n;
     double xe = 0.0;
-    if (xsrc >= 0) xe = Conv<TI>::ld(U[i + (int64_t)xsrc * ldu]) * xscale;
+    if (xsrc >= 0 && lk == 0 && rin) xe = Conv<TI>::ld(U[row + (int64_t)xsrc * ldu]) * xscale;
+    f64x4 acc[NT];
 #pragma unroll
-    for (int o = 0; o < KM; ++o)
-      if (o < kout) O[i + (int64_t)(out0 + o) * ldo] = Conv<TO>::st(acc[o]);
-    if (xsrc >= 0) ((TI*)U)[i + (int64_t)xdst * ldu] = Conv<TI>::st(xe);
+    for (int t = 0; t < NT; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    const TI* urow = U + row + (int64_t)in0 * ldu;
+    for (int k0 = 0; k0 < minp; k0 += 16) {
+      double a[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = k0 + 4 * s + lk;
+        a[s] = (rin && kk < min) ? Conv<TI>::ld(urow[(int64_t)kk * ldu]) : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double* yk = Ys + (size_t)(k0 + 4 * s + lk) * KC + lr;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], yk[16 * t], acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int oc = 16 * t + lr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t orow = tile * 16 + lk + 4 * i;
+        if (orow < n && oc < kout) O[orow + (int64_t)(out0 + oc) * ldo] = Conv<TO>::st(acc[t][i]);
+      }
+    }
+    if (xsrc >= 0 && lk == 0 && rin) ((TI*)U)[row + (int64_t)xdst * ldu] = Conv<TI>::st(xe);
   }
 }
 
@@ -444,15 +516,15 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
   dim3 grid(G), block(512);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<double, double, double, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.rp, e.col, e.val, e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
+                                     e.rp, e.col, e.val, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
                                      e.sp, do_sketch)));
   } else if (prec == 1) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<float, float, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.rp, e.col, e.val32, e.tiles, e.ntiles, (const float*)x, (float*)w, zpart,
+                                     e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w, zpart,
                                      e.sp, do_sketch)));
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<bf16_t, float, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.rp, e.col, e.val32, e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
+                                     e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
                                      e.sp, do_sketch)));
   }
   return G;
@@ -468,7 +540,7 @@ void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const 
   const int d = e.sp.d;
   const size_t base = (size_t)(3 * d + kMaxM + 2 + 16) * 8;
   const size_t full = base + (size_t)d * (t + 1) * 8;
-  const int use_lds = (!finalize_only && full <= kLsLdsMax) ? 1 : 0;
+  const int use_lds = (!finalize_only && full <= kLsLdsMax && (size_t)d * t <= (size_t)kLsPre * 1024) ? 1 : 0;
   const size_t lds = use_lds ? full : base;
   static bool attr = false;
   if (!attr) {
@@ -481,19 +553,21 @@ void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const 
 
 int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
                   void* unew, double* spart) {
-  const int G = grid_for(e.n, 512, kMaxG);
-  dim3 grid(G), block(512);
+  const int V = 16 / e.vbytes();
+  const int64_t npk = (e.n + V - 1) / V;
+  const int G = grid_for(npk, 1024, kMaxG);
+  dim3 grid(G), block(1024);
   if (e.prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_update<double, double, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.n, ncol, (const double*)U, ldu, (const double*)w, coef, (double*)unew,
+                                     e.n, npk, ncol, (const double*)U, ldu, (const double*)w, coef, (double*)unew,
                                      spart, e.sp)));
   } else if (e.prec == 1) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_update<float, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.n, ncol, (const float*)U, ldu, (const float*)w, coef, (float*)unew, spart,
-                                     e.sp)));
+                                     e.n, npk, ncol, (const float*)U, ldu, (const float*)w, coef, (float*)unew,
+                                     spart, e.sp)));
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_update<bf16_t, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.n, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew,
+                                     e.n, npk, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew,
                                      spart, e.sp)));
   }
   return G;
@@ -517,27 +591,29 @@ int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint
   return G;
 }
 
+template <typename TI, typename TO, int NT>
+static void rotate_nt(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
+                      int kout, const double* Y, int xsrc, int xdst, double xscale) {
+  const int64_t ntile = (e.n + 15) / 16;
+  const int G = grid_for(ntile, 4, 2048);
+  const size_t lds = (size_t)((min + 15) & ~15) * 16 * NT * 8;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_rotate<TI, TO, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  k_rotate<TI, TO, NT><<<G, 256, lds, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+}
+
 template <typename TI, typename TO>
 static void rotate_t(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
                      int kout, const double* Y, int xsrc, int xdst, double xscale) {
-  const int G = grid_for(e.n, 256, 2048);
-  dim3 grid(G), block(256);
-  const size_t lds = (size_t)min * (kout <= 16 ? 16 : (kout <= 32 ? 32 : 64)) * 8;
-  if (lds > 65536) {
-    const void* fn = kout <= 16 ? (const void*)k_rotate<TI, TO, 16>
-                                : (kout <= 32 ? (const void*)k_rotate<TI, TO, 32> : (const void*)k_rotate<TI, TO, 64>);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-  if (kout <= 16) {
-    k_rotate<TI, TO, 16><<<grid, block, (size_t)min * 16 * 8, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout,
-                                                                         Y, xsrc, xdst, xscale);
-  } else if (kout <= 32) {
-    k_rotate<TI, TO, 32><<<grid, block, (size_t)min * 32 * 8, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout,
-                                                                         Y, xsrc, xdst, xscale);
-  } else {
-    k_rotate<TI, TO, 64><<<grid, block, (size_t)min * 64 * 8, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout,
-                                                                         Y, xsrc, xdst, xscale);
-  }
+  if (kout <= 16)
+    rotate_nt<TI, TO, 1>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  else if (kout <= 32)
+    rotate_nt<TI, TO, 2>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  else if (kout <= 48)
+    rotate_nt<TI, TO, 3>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  else
+    rotate_nt<TI, TO, 4>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
 }
 
 void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,

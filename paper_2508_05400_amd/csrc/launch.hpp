@@ -16,10 +16,12 @@ struct LaunchEnv {
   const int* col;      // CSR columns (device)
   const double* val;   // FP64 values (device)
   const float* val32;  // FP32 values (device, mixed precision only)
-  const int* tiles;    // SpMV wave tiles: row starts, ntiles + 1 entries
+  const int* tiles;    // SpMV wave tiles: {first row, rows, first nonzero, nonzeros} per tile
   int ntiles;
+  int64_t ldu;         // basis leading dimension (n rounded up to 128; padding rows are zero)
   int sp_kind;         // 0 Gaussian, 1 sparse-sign
   SketchP sp;
+  int vbytes() const { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 };
 
 // w = A x, partials of Omega w (returns the number of partial rows).

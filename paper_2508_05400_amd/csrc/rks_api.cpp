@@ -666,6 +666,13 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     tiles.push_back((int32_t)r);
   }
   const int ntiles = (int)tiles.size() - 1;
+  std::vector<int32_t> tdesc((size_t)ntiles * 4);
+  for (int t = 0; t < ntiles; ++t) {
+    tdesc[4 * t + 0] = tiles[t];
+    tdesc[4 * t + 1] = tiles[t + 1] - tiles[t];
+    tdesc[4 * t + 2] = rp[tiles[t]];
+    tdesc[4 * t + 3] = rp[tiles[t + 1]] - rp[tiles[t]];
+  }
   c->vbytes = (o.precision == RKS_PREC_FP64) ? 8 : (o.precision == RKS_PREC_V32 ? 4 : 2);
   c->wbytes = (o.precision == RKS_PREC_FP64) ? 8 : 4;
   c->ldu = (n + 127) / 128 * 128;
@@ -691,9 +698,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->col, nnz * 4);
   dm((void**)&c->val, nnz * 8);
   if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nnz * 4);
-  dm((void**)&c->tiles, tiles.size() * 4);
+  dm((void**)&c->tiles, tdesc.size() * 4);
   dm(&c->U, (size_t)c->ldu * (m + 1) * c->vbytes);
-  dm(&c->w, (size_t)n * 8);
+  dm(&c->w, (size_t)c->ldu * 8);
   dm((void**)&c->S, (size_t)d * (m + 1) * 8);
   dm((void**)&c->B, (size_t)(m + 1) * m * 8);
   dm((void**)&c->cs, (size_t)(m + 1) * 8);
@@ -727,8 +734,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     std::vector<float> v32(val.begin(), val.end());
     cp(c->val32, v32.data(), nnz * 4);
   }
-  cp(c->tiles, tiles.data(), tiles.size() * 4);
+  cp(c->tiles, tdesc.data(), tdesc.size() * 4);
   if (rc == RKS_OK && hipMemset(c->U, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
+  // padding rows of U and w stay zero for the whole life of the context
+  if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
   if (rc != RKS_OK) {
     free_all(c);
     delete c;
@@ -744,6 +753,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.val32 = c->val32;
   e.tiles = c->tiles;
   e.ntiles = ntiles;
+  e.ldu = c->ldu;
   e.sp_kind = o.sketch_kind;
   e.sp.d = d;
   e.sp.zeta = o.zeta;
