@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--resid-tol", type=float, default=1e-8,
                     help="verified FP64 residual target of the metric (0 = paper's estimate test only)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP events")
+    ap.add_argument("--compare", default="", help="comma list of extra basis precisions to time on the "
+                    "same workload after the main run (e.g. fp32,bf16); reported under 'precisions'")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block "
@@ -159,6 +161,29 @@ def main():
                      "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": None,
                      "avg_launch_us": upd_avg * 1e6, "bytes_per_launch": upd_bytes},
     }
+    extra = {}
+    for prec in [p for p in args.compare.split(",") if p]:
+        with P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
+                               sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
+                               start_seed=cfg["start_seed"], precision=prec, lock=int(cfg["lock"]),
+                               max_restarts=cfg.get("max_restarts", 300), resid_tol=args.resid_tol,
+                               stream=stream) as s2:
+            s2.solve()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(max(1, args.steps)):
+                t0 = time.perf_counter()
+                s2.solve()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            st2 = s2.stats.as_dict()
+            _, _, res2 = s2.eigpairs(want_vectors=False, want_resid=True)
+            extra[prec] = {"time_to_k_s": float(np.mean(ts)), "restarts": st2["restarts"],
+                           "restarts_low_precision": st2["restarts_lo"], "refined": bool(st2["refined"]),
+                           "low_precision_phase_s": st2["t_lo"], "max_resid": float(np.max(res2)),
+                           "converged": bool(st2["converged"])}
+    if extra:
+        out["precisions"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, cfg, st["restarts"])
     print(json.dumps(out))

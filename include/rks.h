@@ -84,6 +84,12 @@ typedef struct {
                             ||A x - lambda x|| / (||A||_1 ||x||) is verified on the
                             device to be <= resid_tol (checked only when the
                             estimates predict it); default 0 = off */
+  int32_t refine;        /* low-precision basis only: 1 = after the low-precision
+                            phase reaches refine_tol, continue in FP64 from a
+                            combination of its Schur vectors; default 1 */
+  double refine_tol;     /* verified-residual target of the low-precision phase
+                            (it also stops when its estimates reach it);
+                            0 = 1e-6 for an FP32 basis, 1e-3 for BF16 */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -102,6 +108,9 @@ typedef struct {
   int32_t stop_reason;   /* 0 restart cap, 1 estimates <= tol, 2 verified residuals <= resid_tol */
   int32_t resid_checks;  /* device residual verifications performed */
   double max_resid;      /* largest verified residual at exit (0 if never verified) */
+  int32_t restarts_lo;   /* restarts of the low-precision phase (mixed precision) */
+  int32_t refined;       /* 1 if an FP64 refinement phase ran */
+  double t_lo;           /* seconds of the low-precision phase */
   double t_total;        /* seconds, host wall clock of the solve */
   double t_host;         /* seconds spent in the host small dense steps */
   /* kernel timings (only when opts.profile = 1), seconds summed over launches */

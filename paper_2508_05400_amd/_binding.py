@@ -30,7 +30,8 @@ class RksOpts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("lock", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("whiten_tol", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("resid_tol", ctypes.c_double)]
+                ("resid_tol", ctypes.c_double), ("refine", ctypes.c_int32),
+                ("refine_tol", ctypes.c_double)]
 
 
 class RksStats(ctypes.Structure):
@@ -39,6 +40,7 @@ class RksStats(ctypes.Structure):
                 ("whitenings", ctypes.c_int32), ("dense_fail", ctypes.c_int32),
                 ("max_est", ctypes.c_double), ("stop_reason", ctypes.c_int32),
                 ("resid_checks", ctypes.c_int32), ("max_resid", ctypes.c_double),
+                ("restarts_lo", ctypes.c_int32), ("refined", ctypes.c_int32), ("t_lo", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("t_host", ctypes.c_double),
                 ("t_spmv", ctypes.c_double), ("t_reduce", ctypes.c_double), ("t_ls", ctypes.c_double),
                 ("t_update", ctypes.c_double), ("t_rotate", ctypes.c_double),

@@ -64,8 +64,11 @@ struct rks_ctx {
   int *rp = nullptr, *col = nullptr, *tiles = nullptr, *flags = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
-  void* U = nullptr;
+  void* U = nullptr;      // basis in use (U_lo or U64)
+  void* U_lo = nullptr;   // basis in the requested precision (allocated at create)
+  void* U64 = nullptr;    // FP64 basis of the refinement phase (lazy)
   void* w = nullptr;
+  double phase_tol = 0.0;
   double *S = nullptr, *B = nullptr, *cs = nullptr, *coef = nullptr, *z = nullptr, *sr = nullptr;
   double *zpart = nullptr, *spart = nullptr, *scal = nullptr, *Yd = nullptr, *u0tmp = nullptr;
   double *Xr = nullptr, *ax1 = nullptr, *ax2 = nullptr, *rpart = nullptr;  // residual scratch (lazy)
@@ -412,7 +415,7 @@ void lock_converged(rks_ctx* c) {
     const double lam = std::abs(rks::block_eig(c->Tk.data(), ke, st[bi], sz[bi]));
     const double scale = std::max(lam, kUnitRoundoff * tn);
     bool ok = true;
-    for (int i = st[bi]; i < st[bi] + sz[bi]; ++i) ok = ok && std::fabs(c->bk[i]) <= c->tol * scale;
+    for (int i = st[bi]; i < st[bi] + sz[bi]; ++i) ok = ok && std::fabs(c->bk[i]) <= c->phase_tol * scale;
     if (!ok) break;
     q = st[bi] + sz[bi];
   }
@@ -542,6 +545,126 @@ int device_residuals(rks_ctx* c, const Packed& P, double* Xd, double* resid, boo
   return RKS_OK;
 }
 
+// Switch the basis in use between the requested precision and FP64.
+int set_basis(rks_ctx* c, int prec) {
+  c->env.prec = prec;
+  c->vbytes = (prec == RKS_PREC_FP64) ? 8 : (prec == RKS_PREC_V32 ? 4 : 2);
+  c->wbytes = (prec == RKS_PREC_FP64) ? 8 : 4;
+  if (prec == c->o.precision) {
+    c->U = c->U_lo;
+  } else {
+    if (!c->U64) {
+      const size_t bytes = (size_t)c->ldu * (c->m + 1) * 8;
+      if (hipMalloc(&c->U64, bytes) != hipSuccess) {
+        c->U64 = nullptr;
+        return fail(c, RKS_ENOMEM, "FP64 refinement basis");
+      }
+      HIPCHK(c, hipMemsetAsync(c->U64, 0, bytes, c->env.stream));
+    }
+    c->U = c->U64;
+  }
+  return RKS_OK;
+}
+
+struct PhaseOut {
+  int restarts;
+  int reason;
+  int resid_checks;
+  double maxest, maxres, thost;
+};
+
+// Algorithm 1 from u0 until the estimates reach tol, the verified residual
+// reaches resid_tol (> 0), or max_restarts cycles.
+int run_phase(rks_ctx* c, const double* u0, int u0_on_device, double tol, double resid_tol, int max_restarts,
+              int hist_off, PhaseOut* out) {
+  rks_stats* st = c->st;
+  c->phase_tol = tol;
+  *out = PhaseOut{0, 0, 0, 0.0, 0.0, 0.0};
+  int rc = start(c, u0, u0_on_device);
+  if (rc) return rc;
+  rc = extend(c);
+  if (rc) return rc;
+  int restarts = 0, reason = 0;
+  double maxest = 0.0, maxres = 0.0, last_fail_pred = INFINITY, thost = 0.0;
+  while (true) {
+    rc = pull_state(c);
+    if (rc) break;
+    if (c->hflags[0] != 0) {
+      rc = fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(c->hflags[0]));
+      break;
+    }
+    const auto h0 = std::chrono::steady_clock::now();
+    int in0, min, out0, kout, wh;
+    double xscale;
+    rc = contract(c, &in0, &min, &out0, &kout, &xscale, &wh);
+    if (rc) break;
+    std::vector<cplx> lam, Y;
+    std::vector<double> est;
+    ritz(c, lam, Y, est);
+    maxest = 0.0;
+    double pred = 0.0;  // estimated backward residual relative to ||A||_1
+    bool allfinite = true;
+    for (int i = 0; i < (int)est.size(); ++i) {
+      if (!std::isfinite(est[i])) allfinite = false;
+      maxest = std::max(maxest, est[i]);
+      pred = std::max(pred, est[i] * std::abs(lam[i]) / c->normA1);
+    }
+    if (!allfinite) maxest = pred = INFINITY;
+    if (hist_off + restarts < 512) st->hist_est[hist_off + restarts] = maxest;
+    const bool converged = allfinite && maxest <= tol;
+    thost += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+    rc = rotate_basis(c, in0, min, out0, kout, xscale);
+    if (rc) break;
+    if (converged) {
+      reason = 1;
+    } else if (resid_tol > 0.0 && allfinite && pred <= resid_tol && pred <= 0.5 * last_fail_pred) {
+      // the estimates predict the target residual: verify it in FP64 on the device
+      rc = ensure_resid_scratch(c);
+      if (rc) break;
+      Packed P = pack_ritz(c);
+      std::vector<double> res(c->keff, 0.0);
+      rc = device_residuals(c, P, c->Xr, res.data(), false);
+      if (rc) break;
+      out->resid_checks += 1;
+      double mr = 0.0;
+      for (double v : res) mr = std::max(mr, v);
+      if (mr <= resid_tol) {
+        reason = 2;
+        maxres = mr;
+      } else {
+        last_fail_pred = pred;
+      }
+    }
+    const bool stop = reason != 0 || restarts >= max_restarts;
+    if (!stop && c->o.lock) lock_converged(c);
+    rc = push_state(c);
+    if (rc) break;
+    if (stop) break;
+    rc = extend(c);
+    if (rc) break;
+    ++restarts;
+  }
+  out->restarts = restarts;
+  out->reason = reason;
+  out->maxest = maxest;
+  out->maxres = maxres;
+  out->thost = thost;
+  return rc;
+}
+
+// Start vector of the FP64 phase: a fixed combination of the low-precision
+// Schur vectors U_k (which span the approximate wanted invariant subspace),
+// formed in FP64 on the device into u0tmp; then switch the basis to FP64.
+int refine_start(rks_ctx* c) {
+  const int ke = c->keff;
+  HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  for (int i = 0; i < ke; ++i) c->hY[i] = 1.0 + 0.25 * (i % 3);
+  HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)ke * 8, hipMemcpyHostToDevice, c->env.stream));
+  rks::launch_rotate(c->env, c->U, c->ldu, 0, ke, c->u0tmp, c->n, 0, 1, c->Yd, -1, 0, 0.0, 1);
+  HIPCHK(c, hipGetLastError());
+  return set_basis(c, RKS_PREC_FP64);
+}
+
 bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, std::string& why) {
   if (rp[0] != 0) { why = "row_ptr[0] != 0"; return false; }
   if (rp[n] != nnz) { why = "row_ptr[n] != nnz"; return false; }
@@ -556,7 +679,7 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 }
 
 void free_all(rks_ctx* c) {
-  void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U, c->w, c->S, c->B, c->cs,
+  void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U_lo, c->U64, c->w, c->S, c->B, c->cs,
                  c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp,
                  c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
@@ -585,6 +708,8 @@ void rks_opts_default(rks_opts* o) {
   o->whiten_tol = 1e-12;
   o->stream = nullptr;
   o->resid_tol = 0.0;
+  o->refine = 1;
+  o->refine_tol = 0.0;
 }
 
 const char* rks_strerror(int code) { return code_str(code); }
@@ -611,8 +736,8 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
-      !(o.resid_tol >= 0.0))
-    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol or resid_tol");
+      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0))
+    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol or refine_tol");
 
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");
@@ -699,7 +824,8 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->val, nnz * 8);
   if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nnz * 4);
   dm((void**)&c->tiles, tdesc.size() * 4);
-  dm(&c->U, (size_t)c->ldu * (m + 1) * c->vbytes);
+  dm(&c->U_lo, (size_t)c->ldu * (m + 1) * c->vbytes);
+  c->U = c->U_lo;
   dm(&c->w, (size_t)c->ldu * 8);
   dm((void**)&c->S, (size_t)d * (m + 1) * 8);
   dm((void**)&c->B, (size_t)(m + 1) * m * 8);
@@ -735,7 +861,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     cp(c->val32, v32.data(), nnz * 4);
   }
   cp(c->tiles, tdesc.data(), tdesc.size() * 4);
-  if (rc == RKS_OK && hipMemset(c->U, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
+  if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
   // padding rows of U and w stay zero for the whole life of the context
   if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
   if (rc != RKS_OK) {
@@ -781,90 +907,55 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   std::memset(st, 0, sizeof(*st));
   c->st = st;
   const auto t0 = std::chrono::steady_clock::now();
-  double thost = 0.0;
-  int rc = start(c, u0, u0_on_device);
-  if (rc) { c->st = nullptr; return rc; }
-  rc = extend(c);
-  if (rc) { c->st = nullptr; return rc; }
-  int restarts = 0;
-  bool converged = false;
-  int reason = 0;
-  double maxest = 0.0, maxres = 0.0, last_fail_pred = INFINITY;
-  while (true) {
-    rc = pull_state(c);
-    if (rc) break;
-    if (c->hflags[0] != 0) {
-      rc = fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(c->hflags[0]));
-      break;
-    }
-    const auto h0 = std::chrono::steady_clock::now();
-    int in0, min, out0, kout, wh;
-    double xscale;
-    rc = contract(c, &in0, &min, &out0, &kout, &xscale, &wh);
-    if (rc) break;
-    std::vector<cplx> lam, Y;
-    std::vector<double> est;
-    ritz(c, lam, Y, est);
-    maxest = 0.0;
-    double pred = 0.0;  // estimated backward residual relative to ||A||_1
-    bool allfinite = true;
-    for (int i = 0; i < (int)est.size(); ++i) {
-      if (!std::isfinite(est[i])) allfinite = false;
-      maxest = std::max(maxest, est[i]);
-      pred = std::max(pred, est[i] * std::abs(lam[i]) / c->normA1);
-    }
-    if (!allfinite) maxest = pred = INFINITY;
-    if (restarts < 512) st->hist_est[restarts] = maxest;
-    converged = allfinite && maxest <= c->tol;
-    thost += std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
-    rc = rotate_basis(c, in0, min, out0, kout, xscale);
-    if (rc) break;
-    if (converged) {
-      reason = 1;
-    } else if (c->o.resid_tol > 0.0 && allfinite && pred <= c->o.resid_tol && pred <= 0.5 * last_fail_pred) {
-      // the estimates predict the target residual: verify it in FP64 on the device
-      rc = ensure_resid_scratch(c);
-      if (rc) break;
-      Packed P = pack_ritz(c);
-      std::vector<double> res(c->keff, 0.0);
-      rc = device_residuals(c, P, c->Xr, res.data(), false);
-      if (rc) break;
-      st->resid_checks += 1;
-      double mr = 0.0;
-      for (double v : res) mr = std::max(mr, v);
-      if (mr <= c->o.resid_tol) {
-        reason = 2;
-        maxres = mr;
-      } else {
-        last_fail_pred = pred;
+  set_basis(c, c->o.precision);
+  const bool mixed = c->o.precision != RKS_PREC_FP64;
+  const bool refine = mixed && c->o.refine;
+  PhaseOut p1{};
+  int rc;
+  if (refine) {
+    double rtol = c->o.refine_tol;
+    if (rtol <= 0.0) rtol = (c->o.precision == RKS_PREC_V32) ? 1e-6 : 1e-3;
+    rtol = std::max(rtol, c->o.resid_tol);
+    const double etol = std::max(c->tol, rtol);
+    const int cap = std::max(1, c->o.max_restarts / 2);
+    rc = run_phase(c, u0, u0_on_device, etol, rtol, cap, 0, &p1);
+    st->restarts_lo = p1.restarts;
+    st->t_lo = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc == RKS_OK) {
+      // FP64 refinement from a fixed combination of the low-precision Schur vectors
+      rc = refine_start(c);
+      if (rc == RKS_OK) {
+        PhaseOut p2{};
+        st->refined = 1;
+        const int left = std::max(1, c->o.max_restarts - p1.restarts);
+        rc = run_phase(c, c->u0tmp, 1, c->tol, c->o.resid_tol, left, p1.restarts + 1, &p2);
+        p2.restarts += p1.restarts + 1;
+        p2.thost += p1.thost;
+        p2.resid_checks += p1.resid_checks;
+        p1 = p2;
       }
     }
-    const bool stop = reason != 0 || restarts >= c->o.max_restarts;
-    if (!stop && c->o.lock) lock_converged(c);
-    rc = push_state(c);
-    if (rc) break;
-    if (stop) break;
-    rc = extend(c);
-    if (rc) break;
-    ++restarts;
+  } else {
+    rc = run_phase(c, u0, u0_on_device, c->tol, c->o.resid_tol, c->o.max_restarts, 0, &p1);
   }
   if (rc == RKS_OK) {
     if (hipStreamSynchronize(c->env.stream) != hipSuccess) rc = fail(c, RKS_EHIP, "stream synchronize");
     flush_events(c);
   }
-  st->converged = reason != 0 ? 1 : 0;
-  st->stop_reason = reason;
-  st->max_resid = maxres;
-  st->restarts = restarts;
+  st->converged = p1.reason != 0 ? 1 : 0;
+  st->stop_reason = p1.reason;
+  st->max_resid = p1.maxres;
+  st->resid_checks = p1.resid_checks;
+  st->restarts = p1.restarts;
   st->locked = c->q;
   st->keff = c->keff;
-  st->max_est = maxest;
-  st->t_host = thost;
+  st->max_est = p1.maxest;
+  st->t_host = p1.thost;
   st->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   c->st = nullptr;
   if (rc) return rc;
   c->solved = true;
-  return reason != 0 ? RKS_OK : fail(c, RKS_ENOTCONV, "max_restarts reached");
+  return p1.reason != 0 ? RKS_OK : fail(c, RKS_ENOTCONV, "max_restarts reached");
 }
 
 int rks_eigpairs(rks_ctx* c, double* lam_re, double* lam_im, double* X, int32_t X_on_device, double* resid) {
@@ -913,6 +1004,8 @@ int rks_arnoldi(rks_ctx* c, const double* u0, int32_t u0_on_device) {
   if (!c) return RKS_EINVAL;
   c->err.clear();
   c->st = nullptr;
+  int rb = set_basis(c, c->o.precision);
+  if (rb) return rb;
   int rc = start(c, u0, u0_on_device);
   if (rc) return rc;
   rc = extend(c);

@@ -260,3 +260,73 @@ def test_verified_residual_stop(lib, cuda):
         assert res.max() <= 1e-8 and abs(res.max() - s1.stats.max_resid) <= 1e-12 + 1e-3 * res.max()
         s2.solve()
         assert s1.stats.restarts <= s2.stats.restarts
+
+
+LOWP = {"fp32": (2.0**-24, 1e-6), "bf16": (2.0**-8, 1e-3)}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_extension(lib, cuda, prec):
+    """Low-precision basis: the stored (rounded) columns are what the sketch
+    sees, so S = Omega U holds to FP64 accuracy; sketch-orthonormality and the
+    Krylov relation hold to the storage unit roundoff (each stored column is
+    the rounded projection, whose sketch is orthogonal only up to that)."""
+    u_low = LOWP[prec][0]
+    A = convdiff2d(45, (20.0, 10.0))
+    k, m, d = 8, 30, 90
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LR", 1e-10,
+                       P.rks_opts_default(sketch_kind="sparse", sketch_seed=2, precision=prec))
+    try:
+        P.rks_arnoldi(ctx, None)
+        B = np.zeros((m + 1, m), order="F")
+        S = np.zeros((d, m + 1), order="F")
+        U = np.zeros((A.n, m + 1), order="F")
+        P.rks_get_state(ctx, B, S, U)
+        om = sketch_matrix(A.n, d, "sparse", 2)
+        OU = np.asarray(om @ U)
+        assert np.linalg.norm(OU - S) < 1e-12
+        assert np.linalg.norm(OU.T @ OU - np.eye(m + 1)) < 10 * u_low * (m + 1)
+        Sp = sp_of(A)
+        nA = abs(Sp).sum(axis=0).max()
+        rel = np.linalg.norm(Sp @ U[:, :m] - U @ B) / (nA * np.linalg.norm(U[:, :m]))
+        assert rel < 50 * u_low, rel
+        # the FP64 oracle's first extension from the same start: B agrees to the storage precision
+        o = RKSOracle(A, k, m, d, "LR", 1e-10, sketch="sparse", sketch_seed=2, start_seed=1)
+        o.start(None)
+        o.extend()
+        assert np.abs(B[:3, :2] - o.B[:3, :2]).max() <= 100 * u_low * nA
+    finally:
+        P.rks_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_refined_solve(lib, cuda, prec):
+    """Low-precision phase then FP64 refinement: the answer equals the FP64
+    oracle's to the paper-level 1e-10 and every residual is <= 1e-8."""
+    A = convdiff2d(40, (2.0, 1.0))
+    k, m, d = 6, 24, 50
+    ref = oracle_rks(A, k, m, d, "LR", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1)
+    with P.Solver.from_csr(A, k=k, m=m, d=d, which="LR", tol=1e-10, sketch_kind="sparse", sketch_seed=3,
+                           start_seed=1, precision=prec) as s:
+        assert s.solve() == 0, P.rks_last_error(s.ctx)
+        assert s.stats.refined == 1 and s.stats.stop_reason == 1
+        lam, X, res = s.eigpairs()
+    rel = np.abs(np.sort_complex(lam) - np.sort_complex(ref.lam)) / np.abs(np.sort_complex(ref.lam))
+    assert rel.max() <= 1e-10, rel
+    assert res.max() <= 1e-8
+
+
+def test_mixed_precision_unrefined_error_reported(lib, cuda):
+    """FP32 basis without refinement stops at its own verified residual; its
+    error against the FP64 oracle is of that order."""
+    A = convdiff2d(40, (2.0, 1.0))
+    k, m, d = 6, 24, 50
+    ref = oracle_rks(A, k, m, d, "LR", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1)
+    with P.Solver.from_csr(A, k=k, m=m, d=d, which="LR", tol=1e-10, sketch_kind="sparse", sketch_seed=3,
+                           start_seed=1, precision="fp32", refine=0, resid_tol=1e-6) as s:
+        assert s.solve() == 0, P.rks_last_error(s.ctx)
+        assert s.stats.refined == 0 and s.stats.stop_reason == 2
+        lam, X, res = s.eigpairs()
+    assert res.max() <= 1e-6
+    rel = np.abs(np.sort_complex(lam) - np.sort_complex(ref.lam)) / np.abs(np.sort_complex(ref.lam))
+    assert rel.max() <= 1e-4
