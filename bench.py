@@ -53,6 +53,68 @@ def cpu_baseline(A, cfg, restarts_gpu: int, budget_s: float = 25.0):
             "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
+KERNEL_SOURCES = ("paper_2508_05400_amd/csrc/kernels.hip", "paper_2508_05400_amd/csrc/kernels.hpp",
+                  "paper_2508_05400_amd/csrc/philox.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str, precision: str):
+    """HBM bytes per k_update launch from the committed FETCH_SIZE/WRITE_SIZE
+    counter summary of this workload, or None when there is none or the kernel
+    sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_update_{workload}_{precision}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(kv["k_update_traffic_bytes_per_launch"])
+
+
+def _loop_gbs(st):
+    """Algorithmic bytes of the Arnoldi loop kernels / their summed event times."""
+    loop_t = st["t_spmv"] + st["t_reduce"] + st["t_ls"] + st["t_update"]
+    loop_bytes = st["bytes_timed_spmv"] + st["bytes_timed_update"]
+    return loop_bytes / loop_t / 1e9 if loop_t > 0 else None
+
+
+def _kernel_avg_us(st):
+    """Average duration (us) of each kernel of the Arnoldi step, and of the rotation."""
+    ns, nr = max(st["n_timed_steps"], 1), max(st["n_timed_rotate"], 1)
+    return {"k_spmv_sketch": st["t_spmv"] / ns * 1e6, "k_reduce": st["t_reduce"] / ns * 1e6,
+            "k_ls": st["t_ls"] / ns * 1e6, "k_update": st["t_update"] / ns * 1e6,
+            "k_rotate": st["t_rotate"] / nr * 1e6}
+
+
+def _error_vs(lam_ref, X_ref, lam, X):
+    """Error of a solve against the FP64 run of the same workload: largest
+    relative distance of each eigenvalue to the nearest reference eigenvalue,
+    and the sine of the largest principal angle between the two invariant
+    subspaces (real and imaginary parts of the eigenvectors span them)."""
+    import numpy as np
+    rel = max(float(np.min(np.abs(lam_ref - l)) / abs(l)) for l in lam)
+    out = {"max_rel_eig_diff": rel}
+    if X_ref is not None and X is not None:
+        q = min(X_ref.shape[1], X.shape[1])
+        Q1, _ = np.linalg.qr(X_ref[:, :q])
+        Q2, _ = np.linalg.qr(X[:, :q])
+        out["subspace_sin_angle"] = float(np.linalg.norm(Q2 - Q1 @ (Q1.T @ Q2), 2))
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -76,6 +138,9 @@ def main():
     ap.add_argument("--resid-tol", type=float, default=1e-8,
                     help="verified FP64 residual target of the metric (0 = paper's estimate test only)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP events")
+    ap.add_argument("--profile-every", type=int, default=7,
+                    help="time the kernels of every P-th Arnoldi step with HIP events (event records "
+                         "cost a few microseconds each, so timing every launch would slow the solve)")
     ap.add_argument("--compare", default="", help="comma list of extra basis precisions to time on the "
                     "same workload after the main run (e.g. fp32,bf16); reported under 'precisions'")
     args = ap.parse_args()
@@ -101,7 +166,7 @@ def main():
     solver = P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
-                               max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else 1,
+                               max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else args.profile_every,
                                resid_tol=args.resid_tol, stream=stream)
     for _ in range(args.warmup):
         solver.solve()
@@ -116,17 +181,21 @@ def main():
         stats.append(solver.stats.as_dict())
         print(f"step {len(times)}: {times[-1]:.3f}s code={code} restarts={stats[-1]['restarts']}",
               file=sys.stderr, flush=True)
-    lam, _, res = solver.eigpairs(want_vectors=False, want_resid=True)
+    want_x = bool(args.compare)
+    lam, X64, res = solver.eigpairs(want_vectors=want_x, want_resid=True)
     solver.close()
 
+    # achievable-bandwidth reference: a plain 2 GB device copy
+    buf = torch.empty(2 * 1024**3 // 8, dtype=torch.float64, device="cuda")
+    buf2 = torch.empty_like(buf)
+    copy_gbs = P.rks_copy_probe(buf, buf2, buf.numel() * 8, 10, stream)
+    del buf, buf2
     st = stats[-1]
     t_mean = float(np.mean(times))
-    upd_avg = st["t_update"] / max(st["n_update"], 1)
-    upd_bytes = st["bytes_update"] / max(st["n_update"], 1)
+    upd_avg = st["t_update"] / max(st["n_timed_steps"], 1)
+    upd_bytes = st["bytes_timed_update"] / max(st["n_timed_steps"], 1)
     achieved = upd_bytes / upd_avg / 1e9 if upd_avg > 0 else None
-    loop_t = st["t_spmv"] + st["t_reduce"] + st["t_ls"] + st["t_update"]
-    loop_bytes = st["bytes_spmv"] + st["bytes_update"]
-    loop_gbs = loop_bytes / loop_t / 1e9 if loop_t > 0 else None
+    loop_gbs = _loop_gbs(st)
     out = {
         "metric": "time-to-k-eigpairs @resid 1e-8 (s) + HBM GB/s of Arnoldi loop, mixed vs FP64",
         "value": t_mean,
@@ -155,11 +224,16 @@ def main():
         "max_resid": float(np.max(res)),
         "max_est": st["max_est"],
         "loop_gbs": loop_gbs,
-        "phase_s": {k: st[k] for k in ("t_spmv", "t_reduce", "t_ls", "t_update", "t_rotate", "t_host")},
+        "kernel_avg_us": _kernel_avg_us(st),
+        "timed_sample": (f"HIP events around the kernels of every {args.profile_every}th Arnoldi step "
+                         f"({st['n_timed_steps']} of {st['n_update']}) and every rotation, inside the timed solves"),
+        "host_dense_s": st["t_host"],
         "roofline": {"bound": "hbm", "kernel": "k_update (V*h update + re-sketch)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": None,
-                     "avg_launch_us": upd_avg * 1e6, "bytes_per_launch": upd_bytes},
+                     "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+                     "traffic": counter_traffic(args.workload, cfg["precision"]),
+                     "avg_launch_us": upd_avg * 1e6, "bytes_per_launch": upd_bytes,
+                     "copy_probe_gbs": copy_gbs},
     }
     extra = {}
     for prec in [p for p in args.compare.split(",") if p]:
@@ -167,7 +241,7 @@ def main():
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=prec, lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), resid_tol=args.resid_tol,
-                               stream=stream) as s2:
+                               profile=0 if args.no_profile else args.profile_every, stream=stream) as s2:
             s2.solve()
             torch.cuda.synchronize()
             ts = []
@@ -176,12 +250,15 @@ def main():
                 s2.solve()
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
+                print(f"{prec} step {len(ts)}: {ts[-1]:.3f}s restarts={s2.stats.as_dict()['restarts']}",
+                      file=sys.stderr, flush=True)
             st2 = s2.stats.as_dict()
-            _, _, res2 = s2.eigpairs(want_vectors=False, want_resid=True)
+            lam2, X2, res2 = s2.eigpairs(want_vectors=True, want_resid=True)
             extra[prec] = {"time_to_k_s": float(np.mean(ts)), "restarts": st2["restarts"],
                            "restarts_low_precision": st2["restarts_lo"], "refined": bool(st2["refined"]),
                            "low_precision_phase_s": st2["t_lo"], "max_resid": float(np.max(res2)),
-                           "converged": bool(st2["converged"])}
+                           "converged": bool(st2["converged"]), "loop_gbs": _loop_gbs(st2),
+                           "vs_fp64_run": _error_vs(lam, X64, lam2, X2)}
     if extra:
         out["precisions"] = extra
     if not args.no_cpu_baseline:

@@ -77,7 +77,9 @@ typedef struct {
   int32_t precision;     /* rks_precision, default FP64 */
   int32_t max_restarts;  /* contraction/extension cycles after the first extension, default 300 */
   int32_t lock;          /* lock converged leading Schur vectors, default 1 */
-  int32_t profile;       /* 1: time the n-dimensional kernels with HIP events, default 0 */
+  int32_t profile;       /* P > 0: time the kernels of every P-th Arnoldi step and every
+                            rotation with HIP events on the solver's stream (each timed
+                            launch adds two event records); 0 = off (default) */
   double whiten_tol;     /* whiten when ||S_k^T S_k - I||_F exceeds this, default 1e-12 */
   void* stream;          /* hipStream_t, NULL = default stream */
   double resid_tol;      /* > 0: also stop once every pair's FP64 residual
@@ -113,10 +115,12 @@ typedef struct {
   double t_lo;           /* seconds of the low-precision phase */
   double t_total;        /* seconds, host wall clock of the solve */
   double t_host;         /* seconds spent in the host small dense steps */
-  /* kernel timings (only when opts.profile = 1), seconds summed over launches */
+  /* kernel timings (only when opts.profile > 0), seconds summed over the timed launches */
   double t_spmv, t_reduce, t_ls, t_update, t_rotate;
   int64_t n_spmv, n_update, n_rotate;     /* launches */
-  double bytes_spmv, bytes_update, bytes_rotate;  /* algorithmic HBM bytes moved */
+  double bytes_spmv, bytes_update, bytes_rotate;  /* algorithmic HBM bytes moved, all launches */
+  int64_t n_timed_steps, n_timed_rotate;  /* timed Arnoldi steps (4 launches each) and rotations */
+  double bytes_timed_spmv, bytes_timed_update, bytes_timed_rotate;  /* algorithmic bytes of the timed launches */
   double hist_est[512];  /* max estimate after contraction r (r < 512) */
 } rks_stats;
 
@@ -190,12 +194,46 @@ int rks_get_state(struct rks_ctx* ctx, int32_t* ncols, double* B, double* S, dou
 int rks_rotate(struct rks_ctx* ctx, int32_t in0, int32_t min, int32_t out0, int32_t kout,
                const double* Y);
 
+/* Bandwidth reference: copies nbytes (multiple of 16) from src to dst
+ * (device) iters times with a plain streaming kernel and returns the
+ * achieved GB/s (bytes read + written) in *gbs. */
+int rks_copy_probe(const void* src, void* dst, int64_t nbytes, int32_t iters, double* gbs, void* stream);
+
 /* Host small dense FP64 helpers used by the contraction step (no device
  * work): real Schur form of A (n x n, in place, lda = n) with Schur vectors
  * Z; reordering of the `which`-wanted kw eigenvalues to the front
  * (*p = kw or kw+1).  Return 0 on success. */
 int rks_host_schur(int32_t n, double* A, double* Z);
 int rks_host_order(int32_t n, double* T, double* Z, int32_t which, int32_t kw, int32_t* p);
+
+/* ---- learned start (FP32 network kernels, device pointers, stream may be NULL) ----
+ * The start vector u1 of Algorithm 1 is a free input (Section 2.1 takes it
+ * random).  These entry points train and run a small network that proposes
+ * it from the operator's coarse velocity field.  Tensors are row-major:
+ * activations B x C x H x W, weights O x C x 3 x 3.  Return RKS_OK,
+ * RKS_EINVAL (bad sizes or NULL) or RKS_EHIP. */
+
+/* y = conv3x3(x; w, b, dilation dil), zero padding, optional ReLU. */
+int rks_net_conv3x3_forward(const float* x, const float* w, const float* b, float* y, int32_t B, int32_t Cin,
+                            int32_t Cout, int32_t H, int32_t W, int32_t dil, int32_t relu, void* stream);
+
+/* Gradients of a layer: dy is the gradient at the layer output y (masked by
+ * y > 0 when relu), giving dw, db and, if dx != NULL, the input gradient. */
+int rks_net_conv3x3_backward(const float* x, const float* w, const float* y, const float* dy, float* dx, float* dw,
+                             float* db, int32_t B, int32_t Cin, int32_t Cout, int32_t H, int32_t W, int32_t dil,
+                             int32_t relu, void* stream);
+
+/* loss[b] = 1 - ||V_b^T u_b||^2 / ||u_b||^2 (V_b: P x K orthonormal, K <= 32)
+ * and du = gradient of the batch mean of loss with respect to u. */
+int rks_net_subspace_loss(const float* u, const float* V, float* loss, float* du, int32_t B, int32_t P, int32_t K,
+                          void* stream);
+
+/* One Adam step (bias-corrected, step index t >= 1) on n parameters. */
+int rks_net_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 int32_t t, void* stream);
+
+/* Bilinear resampling (half-pixel centres) of u (h x w, FP32) to out (H x W, FP64). */
+int rks_net_upsample(const float* u, int32_t h, int32_t w, double* out, int32_t H, int32_t W, void* stream);
 
 #ifdef __cplusplus
 }

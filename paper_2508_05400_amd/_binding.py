@@ -46,7 +46,10 @@ class RksStats(ctypes.Structure):
                 ("t_update", ctypes.c_double), ("t_rotate", ctypes.c_double),
                 ("n_spmv", ctypes.c_int64), ("n_update", ctypes.c_int64), ("n_rotate", ctypes.c_int64),
                 ("bytes_spmv", ctypes.c_double), ("bytes_update", ctypes.c_double),
-                ("bytes_rotate", ctypes.c_double), ("hist_est", ctypes.c_double * 512)]
+                ("bytes_rotate", ctypes.c_double), ("n_timed_steps", ctypes.c_int64),
+                ("n_timed_rotate", ctypes.c_int64), ("bytes_timed_spmv", ctypes.c_double),
+                ("bytes_timed_update", ctypes.c_double), ("bytes_timed_rotate", ctypes.c_double),
+                ("hist_est", ctypes.c_double * 512)]
 
     def as_dict(self) -> dict:
         out = {f: getattr(self, f) for f, _ in self._fields_ if f != "hist_est"}
@@ -75,6 +78,14 @@ SIGNATURES = {
     "rks_rotate": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
     "rks_host_schur": (ctypes.c_int, [_I32, _P, _P]),
     "rks_host_order": (ctypes.c_int, [_I32, _P, _P, _I32, _I32, ctypes.POINTER(_I32)]),
+    "rks_net_conv3x3_forward": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32, _I32, _P]),
+    "rks_net_conv3x3_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _I32,
+                                                _I32, _P]),
+    "rks_net_subspace_loss": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P]),
+    "rks_net_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, _I32, _P]),
+    "rks_net_upsample": (ctypes.c_int, [_P, _I32, _I32, _P, _I32, _I32, _P]),
+    "rks_copy_probe": (ctypes.c_int, [_P, _P, _I64, _I32, ctypes.POINTER(_D), _P]),
 }
 
 _lib = None
@@ -255,3 +266,42 @@ def rks_host_order(T, Z, which, kw):
         which = WHICH[which]
     _check(None, load().rks_host_order(T.shape[0], _ptr(T), _ptr(Z), int(which), int(kw), ctypes.byref(p)))
     return T, Z, int(p.value)
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return stream if isinstance(stream, int) else int(stream.cuda_stream)
+
+
+def rks_net_conv3x3_forward(x, w, b, y, B, Cin, Cout, H, W, dil, relu, stream=None) -> int:
+    return _check(None, load().rks_net_conv3x3_forward(_ptr(x), _ptr(w), _ptr(b), _ptr(y), B, Cin, Cout, H, W,
+                                                       dil, int(relu), _stream(stream)))
+
+
+def rks_net_conv3x3_backward(x, w, y, dy, dx, dw, db, B, Cin, Cout, H, W, dil, relu, stream=None) -> int:
+    return _check(None, load().rks_net_conv3x3_backward(_ptr(x), _ptr(w), _ptr(y), _ptr(dy), _ptr(dx), _ptr(dw),
+                                                        _ptr(db), B, Cin, Cout, H, W, dil, int(relu),
+                                                        _stream(stream)))
+
+
+def rks_net_subspace_loss(u, V, loss, du, B, P, K, stream=None) -> int:
+    return _check(None, load().rks_net_subspace_loss(_ptr(u), _ptr(V), _ptr(loss), _ptr(du), B, P, K,
+                                                     _stream(stream)))
+
+
+def rks_net_adam(w, g, m, v, n, lr, t, b1=0.9, b2=0.999, eps=1e-8, stream=None) -> int:
+    return _check(None, load().rks_net_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), int(n), lr, b1, b2, eps, int(t),
+                                            _stream(stream)))
+
+
+def rks_net_upsample(u, h, w, out, H, W, stream=None) -> int:
+    return _check(None, load().rks_net_upsample(_ptr(u), h, w, _ptr(out), H, W, _stream(stream)))
+
+
+def rks_copy_probe(src, dst, nbytes, iters=20, stream=None) -> float:
+    """Achieved GB/s (read + write) of a plain device copy of nbytes."""
+    g = ctypes.c_double(0.0)
+    _check(None, load().rks_copy_probe(_ptr(src), _ptr(dst), int(nbytes), int(iters), ctypes.byref(g),
+                                       _stream(stream)))
+    return g.value

@@ -23,6 +23,7 @@ HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-march=x86-64-v3", f"-I{IN
 
 SOURCES = [
     ("kernels.hip", ["hipcc", "-x", "hip"] + HIP_FLAGS),
+    ("net.hip", ["hipcc", "-x", "hip"] + HIP_FLAGS),
     ("rks_api.cpp", ["hipcc"] + HOST_FLAGS + ["-D__HIP_PLATFORM_AMD__"]),
     ("dense.cpp", ["g++"] + HOST_FLAGS),
 ]

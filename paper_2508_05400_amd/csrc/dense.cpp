@@ -90,30 +90,35 @@ void hessenberg(int n, double* A, int lda, double* Z, int ldz) {
   }
 }
 
-// Apply reflector (I - beta v v^T) of length k from the left to rows
-// r0..r0+k-1, columns [c0, c1), and from the right to columns r0.., rows [0, rr).
-void refl_sim(int n, double* H, int ldh, double* Z, int ldz, int k, const double* v, double beta,
-              int r0, int c0, int c1, int rr) {
+// Apply reflector (I - beta v v^T) of length K (2 or 3, the Francis sweep's
+// bulge size) from the left to rows r0..r0+K-1, columns [c0, c1), and from
+// the right to columns r0.., rows [0, rr) of H and rows [0, n) of Z.  The
+// fixed length lets the compiler keep v in registers and vectorise the
+// column updates (contiguous rows of a column-major matrix).
+template <int K>
+void refl_sim(int n, double* H, int ldh, double* Z, int ldz, const double* v, double beta, int r0, int c0, int c1,
+              int rr) {
+  double vv[K];
+  for (int i = 0; i < K; ++i) vv[i] = v[i];
   for (int j = c0; j < c1; ++j) {
+    double* col = &H[(size_t)r0 + (size_t)j * ldh];
     double s = 0.0;
-    for (int i = 0; i < k; ++i) s += v[i] * at(H, ldh, r0 + i, j);
+    for (int i = 0; i < K; ++i) s += vv[i] * col[i];
     s *= beta;
-    for (int i = 0; i < k; ++i) at(H, ldh, r0 + i, j) -= s * v[i];
+    for (int i = 0; i < K; ++i) col[i] -= s * vv[i];
   }
-  for (int i = 0; i < rr; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < k; ++j) s += at(H, ldh, i, r0 + j) * v[j];
-    s *= beta;
-    for (int j = 0; j < k; ++j) at(H, ldh, i, r0 + j) -= s * v[j];
-  }
-  if (Z) {
-    for (int i = 0; i < n; ++i) {
+  auto right = [&](double* M, int ld, int rows) {
+    double* c[K];
+    for (int j = 0; j < K; ++j) c[j] = &M[(size_t)(r0 + j) * ld];
+    for (int i = 0; i < rows; ++i) {
       double s = 0.0;
-      for (int j = 0; j < k; ++j) s += at(Z, ldz, i, r0 + j) * v[j];
+      for (int j = 0; j < K; ++j) s += c[j][i] * vv[j];
       s *= beta;
-      for (int j = 0; j < k; ++j) at(Z, ldz, i, r0 + j) -= s * v[j];
+      for (int j = 0; j < K; ++j) c[j][i] -= s * vv[j];
     }
-  }
+  };
+  right(H, ldh, rr);
+  if (Z) right(Z, ldz, n);
 }
 
 // Solve T11 X - X T22 = T12 (n1 x n2, each <= 2) by Gaussian elimination
@@ -334,7 +339,7 @@ int real_schur(int n, double* A, int lda, double* Z, int ldz) {
       if (beta != 0.0) {
         int q = std::max(l, k - 1);
         int r = std::min(k + 4, i + 1);
-        refl_sim(n, A, lda, Z, ldz, 3, v, beta, k, q, n, r);
+        refl_sim<3>(n, A, lda, Z, ldz, v, beta, k, q, n, r);
         if (k > l) {
           at(A, lda, k + 1, k - 1) = 0.0;
           at(A, lda, k + 2, k - 1) = 0.0;
@@ -347,7 +352,7 @@ int real_schur(int n, double* A, int lda, double* Z, int ldz) {
     xv[0] = x; xv[1] = y;
     double beta = house(2, xv, v);
     if (beta != 0.0) {
-      refl_sim(n, A, lda, Z, ldz, 2, v, beta, i - 1, i - 2, n, i + 1);
+      refl_sim<2>(n, A, lda, Z, ldz, v, beta, i - 1, i - 2, n, i + 1);
       at(A, lda, i, i - 2) = 0.0;
     }
   }

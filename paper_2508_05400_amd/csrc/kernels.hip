@@ -78,6 +78,9 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
     const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
     TA s = 0;
     int rr, sub;
+    int hrows[8];
+    float hsg[8];
+    int have = 0;
     if (ne <= kTileNnz) {
       int lpr = 64;
       while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
@@ -97,6 +100,12 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
           ci[u] = col[e0 + e];
           vv[u] = val[e0 + e];
         }
+      }
+      // the row's sketch column does not depend on the data: hash it while
+      // the loads are in flight
+      if (KIND == 1 && do_sketch && rr < nr && sub == 0) {
+        sparse_column((uint64_t)(r0 + rr), sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
+        have = 1;
       }
       TA xv[kTileNnz / 64];
 #pragma unroll
@@ -124,7 +133,15 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
       const int r = r0 + rr;
       const TW ws = (TW)s;
       w[r] = ws;
-      if (do_sketch) sketch_add<KIND>(bins, (uint64_t)r, (double)ws, sp);
+      if (do_sketch) {
+        if (KIND == 1 && have) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (q < sp.zeta) atomicAdd(&bins[hrows[q]], (double)hsg[q] * (double)ws);
+        } else {
+          sketch_add<KIND>(bins, (uint64_t)r, (double)ws, sp);
+        }
+      }
     }
   }
   __syncthreads();
@@ -165,26 +182,32 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ pa, 
 
 // Finalise column t when pending (beta = ||s~||, S(:,t) = s~/beta, scale
 // 1/beta, B(t, t-1) = beta, breakdown test), then the low-dimensional
-// projection h = S_t^+ z computed as h = S^T z plus one re-projection
-// h += S^T (z - S h).  Writes B(0:t, t) = h and the coefficients the update
-// needs: coef[l] = h_l * scale_l (l <= t), coef[t+1] = scale_t.
+// projection h = S_t^+ z.  With E = S^T S - I (kept up to date column by
+// column; the host resets it after each contraction) the least-squares
+// solution is (I + E)^{-1} S^T z = y - E y + O(|E|^2 |y|), y = S^T z: the same
+// value as one re-projection h = y + S^T (z - S y), but it needs a single
+// pass over S (for y and, for the new column, its inner products with the
+// old ones) and an O(t^2) correction instead of two more passes.
+// Writes B(0:t, t) = h and the coefficients the update needs:
+// coef[l] = h_l * scale_l (l <= t), coef[t+1] = scale_t.
 // When S(:, 0:t) fits in LDS, every global load of the kernel (S, the two raw
-// sketches) is issued in one round at entry and the three products then run
-// from LDS; otherwise they read S from L2 with unrolled loops.
+// sketches, the first rows of E) is issued in one round at entry.
 constexpr int kLsPre = 20;  // S values per thread staged through registers (LDS path)
+constexpr int kLsPreE = 4;  // rows of E per wave prefetched at entry (t <= 64)
 
 __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int finalize_only, int use_lds,
                                              const double* __restrict__ zraw, const double* __restrict__ sraw,
                                              double* __restrict__ S, double* __restrict__ B, int ldb,
-                                             double* __restrict__ cs, double* __restrict__ coef,
-                                             double* __restrict__ scal, int* __restrict__ flags, double bd_rel) {
+                                             double* __restrict__ E, double* __restrict__ cs,
+                                             double* __restrict__ coef, double* __restrict__ scal,
+                                             int* __restrict__ flags, double bd_rel) {
   extern __shared__ double sm[];
   double* snew = sm;
   double* zs = snew + d;
-  double* rs = zs + d;
-  double* hs = rs + d;             // kMaxM + 2
-  double* red = hs + kMaxM + 2;    // 16
-  double* Ssh = red + 16;          // d * (t + 1) when use_lds
+  double* ys = zs + d;             // kMaxM + 2
+  double* gs = ys + kMaxM + 2;     // kMaxM + 2
+  double* red = gs + kMaxM + 2;    // 32
+  double* Ssh = red + 32;          // d * (t + 1) when use_lds
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   // ---- every global load up front ----
   const int tot = use_lds ? d * t : 0;
@@ -201,17 +224,43 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
     if (!finalize_only) zrv = zraw[tid];
   }
   if (!pending) ctg = cs[t];
+  double ev[kLsPreE];
+  const bool pre_e = !finalize_only && t <= 64;
+#pragma unroll
+  for (int i = 0; i < kLsPreE; ++i) {
+    const int l = wv + nw * i;
+    ev[i] = (pre_e && l < t && lane < t) ? E[lane + (size_t)l * ldb] : 0.0;
+  }
+  // ---- both squared norms in one block reduction ----
+  {
+    double a = wave_sum(srv * srv), b = wave_sum(zrv * zrv);
+    if (lane == 0) {
+      red[wv] = a;
+      red[16 + wv] = b;
+    }
+  }
+  if (use_lds) {
+#pragma unroll
+    for (int u = 0; u < kLsPre; ++u) {
+      const int idx = tid + 1024 * u;
+      if (idx < tot) Ssh[idx] = sv[u];
+    }
+  }
+  __syncthreads();
+  double ss = 0.0, zz = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    ss += red[q];
+    zz += red[16 + q];
+  }
   // ---- finalise the pending column ----
   double ct;
   if (pending) {
-    const double s = block_sum(srv * srv, red);
-    const double beta = sqrt(s);
+    const double beta = sqrt(ss);
     const double inv = 1.0 / beta;
     if (tid < d) {
-      const double v = srv * inv;
-      snew[tid] = v;
-      S[tid + (size_t)t * d] = v;
-      stv = v;
+      stv = srv * inv;
+      snew[tid] = stv;
+      S[tid + (size_t)t * d] = stv;
     }
     if (tid == 0) {
       cs[t] = inv;
@@ -226,64 +275,68 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   }
   if (finalize_only) return;
   const int ncol = t + 1;
-  if (use_lds) {
-#pragma unroll
-    for (int u = 0; u < kLsPre; ++u) {
-      const int idx = tid + 1024 * u;
-      if (idx < tot) Ssh[idx] = sv[u];
-    }
-    if (tid < d) Ssh[(size_t)t * d + tid] = stv;
-  }
+  if (use_lds && tid < d) Ssh[(size_t)t * d + tid] = stv;
+  if (tid < d) zs[tid] = zrv * ct;
+  if (tid == 0) scal[0] = sqrt(zz) * ct;
+  __syncthreads();
+  // ---- one pass over S: y_l = s_l . z, and g_l = s_l . s_t for a new column ----
   const double* Sc = use_lds ? Ssh : S;
-  double zv = 0.0;
-  if (tid < d) {
-    zv = zrv * ct;
-    zs[tid] = zv;
-  }
-  const double s2 = block_sum(zv * zv, red);  // also publishes Ssh, snew and zs
-  if (tid == 0) scal[0] = sqrt(s2);
-  // h = S^T z: one wave per column, lanes over the sketch rows
   for (int l = wv; l < ncol; l += nw) {
-    const bool nu = !use_lds && pending && l == t;
-    const double* Sl = nu ? snew : Sc + (size_t)l * d;
-    double a = 0.0;
+    const double* Sl = (!use_lds && pending && l == t) ? snew : Sc + (size_t)l * d;
+    double a = 0.0, g = 0.0;
+    if (pending && l < t) {
 #pragma unroll 4
-    for (int b = lane; b < d; b += 64) a += Sl[b] * zs[b];
-    a = wave_sum(a);
-    if (lane == 0) hs[l] = a;
-  }
-  __syncthreads();
-  // r = z - S h: one thread per sketch row, 4 independent chains over columns
-  for (int b = tid; b < d; b += blockDim.x) {
-    double a0 = zs[b], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int l = 0;
-    const int lim = (!use_lds && pending) ? t : ncol;
-    for (; l + 4 <= lim; l += 4) {
-      a0 -= Sc[b + (size_t)l * d] * hs[l];
-      a1 -= Sc[b + (size_t)(l + 1) * d] * hs[l + 1];
-      a2 -= Sc[b + (size_t)(l + 2) * d] * hs[l + 2];
-      a3 -= Sc[b + (size_t)(l + 3) * d] * hs[l + 3];
+      for (int b = lane; b < d; b += 64) {
+        const double v = Sl[b];
+        a += v * zs[b];
+        g += v * snew[b];
+      }
+      g = wave_sum(g);
+    } else {
+#pragma unroll 4
+      for (int b = lane; b < d; b += 64) a += Sl[b] * zs[b];
     }
-    for (; l < lim; ++l) a0 -= Sc[b + (size_t)l * d] * hs[l];
-    if (lim == t) a0 -= snew[b] * hs[t];
-    rs[b] = (a0 + a1) + (a2 + a3);
-  }
-  __syncthreads();
-  // h += S^T r
-  for (int l = wv; l < ncol; l += nw) {
-    const bool nu = !use_lds && pending && l == t;
-    const double* Sl = nu ? snew : Sc + (size_t)l * d;
-    double a = 0.0;
-#pragma unroll 4
-    for (int b = lane; b < d; b += 64) a += Sl[b] * rs[b];
     a = wave_sum(a);
-    if (lane == 0) hs[l] += a;
+    if (lane == 0) {
+      ys[l] = a;
+      gs[l] = g;
+    }
   }
   __syncthreads();
-  for (int l = tid; l <= t; l += blockDim.x) {
-    const double h = hs[l];
-    B[l + (size_t)t * ldb] = h;
-    coef[l] = h * ((l == t) ? ct : cs[l]);
+  // ---- the new column of E, then h = y - E y ----
+  if (pending) {
+    for (int l = tid; l <= t; l += blockDim.x) {
+      const double g = (l < t) ? gs[l] : 0.0;
+      E[l + (size_t)t * ldb] = g;
+      E[t + (size_t)l * ldb] = g;
+    }
+  }
+  for (int i = 0, l = wv; l < ncol; ++i, l += nw) {
+    // row l of E: columns c < t from memory (prefetched when t <= 64), column t
+    // from this kernel when it was just finalised
+    double a = 0.0;
+    if (l < t) {
+      if (pre_e && i < kLsPreE) {
+        if (lane < t) a = ev[i] * ys[lane];
+      } else {
+        for (int c = lane; c < t; c += 64) a += E[c + (size_t)l * ldb] * ys[c];
+      }
+      a = wave_sum(a);
+      a += (pending ? gs[l] : E[l + (size_t)t * ldb]) * ys[t];
+    } else {  // l == t
+      if (pending) {
+        for (int c = lane; c < t; c += 64) a += gs[c] * ys[c];
+      } else {
+        for (int c = lane; c < t; c += 64) a += E[t + (size_t)c * ldb] * ys[c];
+      }
+      a = wave_sum(a);
+      if (!pending) a += E[t + (size_t)t * ldb] * ys[t];
+    }
+    if (lane == 0) {
+      const double h = ys[l] - a;
+      B[l + (size_t)t * ldb] = h;
+      coef[l] = h * ((l == t) ? ct : cs[l]);
+    }
   }
   if (tid == 0) coef[t + 1] = ct;
 }
@@ -487,6 +540,13 @@ __global__ __launch_bounds__(256) void k_fill(int64_t n, double* __restrict__ x,
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
 }
 
+// Plain streaming copy of n 16-byte packets (bandwidth reference).
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
 inline int grid_for(int64_t work, int per_block, int cap) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -536,9 +596,10 @@ void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* p
 }
 
 void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
-               double* S, double* B, int ldb, double* cs, double* coef, double* scal, int* flags, double bd_rel) {
+               double* S, double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
+               double bd_rel) {
   const int d = e.sp.d;
-  const size_t base = (size_t)(3 * d + kMaxM + 2 + 16) * 8;
+  const size_t base = (size_t)(2 * d + 2 * (kMaxM + 2) + 32) * 8;
   const size_t full = base + (size_t)d * (t + 1) * 8;
   const int use_lds = (!finalize_only && full <= kLsLdsMax && (size_t)d * t <= (size_t)kLsPre * 1024) ? 1 : 0;
   const size_t lds = use_lds ? full : base;
@@ -547,8 +608,8 @@ void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const 
     (void)hipFuncSetAttribute((const void*)k_ls, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLsLdsMax);
     attr = true;
   }
-  k_ls<<<1, 1024, lds, e.stream>>>(t, d, pending, finalize_only, use_lds, zraw, sraw, S, B, ldb, cs, coef, scal,
-                                   flags, bd_rel);
+  k_ls<<<1, 1024, lds, e.stream>>>(t, d, pending, finalize_only, use_lds, zraw, sraw, S, B, ldb, E, cs, coef,
+                                   scal, flags, bd_rel);
 }
 
 int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
@@ -644,6 +705,10 @@ int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const d
 
 void launch_scale(const LaunchEnv& e, double* x, double s) {
   k_scale<<<grid_for(e.n, 256, kMaxG), 256, 0, e.stream>>>(e.n, x, s);
+}
+
+void launch_copy16(hipStream_t stream, const void* src, void* dst, int64_t packets) {
+  k_copy16<<<grid_for(packets, 256, 8192), 256, 0, stream>>>((const u32x4*)src, (u32x4*)dst, packets);
 }
 
 void launch_fill(const LaunchEnv& e, int64_t len, double* x, double v) {

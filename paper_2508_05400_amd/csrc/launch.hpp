@@ -27,8 +27,10 @@ struct LaunchEnv {
 // w = A x, partials of Omega w (returns the number of partial rows).
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override);
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob);
+// E = S^T S - I ((m+1) x (m+1), leading dimension ldb), kept current column by column.
 void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
-               double* S, double* B, int ldb, double* cs, double* coef, double* scal, int* flags, double bd_rel);
+               double* S, double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
+               double bd_rel);
 int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
                   void* unew, double* spart);
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
@@ -39,5 +41,6 @@ int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const d
                  double re, double im, double* part);
 void launch_scale(const LaunchEnv& e, double* x, double s);
 void launch_fill(const LaunchEnv& e, int64_t len, double* x, double v);
+void launch_copy16(hipStream_t stream, const void* src, void* dst, int64_t packets);
 
 }  // namespace rks

@@ -71,12 +71,14 @@ struct rks_ctx {
   double phase_tol = 0.0;
   double *S = nullptr, *B = nullptr, *cs = nullptr, *coef = nullptr, *z = nullptr, *sr = nullptr;
   double *zpart = nullptr, *spart = nullptr, *scal = nullptr, *Yd = nullptr, *u0tmp = nullptr;
+  double* E = nullptr;  // S^T S - I, (m+1) x (m+1), leading dimension m+1
   double *Xr = nullptr, *ax1 = nullptr, *ax2 = nullptr, *rpart = nullptr;  // residual scratch (lazy)
   // pinned host mirrors
-  double *hB = nullptr, *hS = nullptr, *hcs = nullptr, *hY = nullptr;
+  double *hB = nullptr, *hS = nullptr, *hcs = nullptr, *hY = nullptr, *hE = nullptr;
   int* hflags = nullptr;
   // state
   int j = 0, q = 0, keff = 0, pending = 0;
+  int64_t step_count = 0;  // Arnoldi steps run by this context (profiling sample clock)
   int G_z = 1, G_s = 1;
   bool have_state = false, solved = false;
   std::vector<double> Tk, bk;
@@ -125,8 +127,8 @@ struct Prof {
   rks_ctx* c;
   int cat;
   hipEvent_t a = nullptr;
-  Prof(rks_ctx* c_, int cat_) : c(c_), cat(cat_) {
-    if (c->o.profile && c->st) {
+  Prof(rks_ctx* c_, int cat_, bool on) : c(c_), cat(cat_) {
+    if (on && c->o.profile > 0 && c->st) {
       a = get_event(c);
       if (a) hipEventRecord(a, c->env.stream);
     }
@@ -172,29 +174,36 @@ double spmv_bytes(const rks_ctx* c) {
 // ---- one Arnoldi step (Algorithm 2 loop body) ------------------------------
 int arnoldi_step(rks_ctx* c, int t) {
   const auto& e = c->env;
+  const bool timed = c->o.profile > 0 && c->st && (c->step_count++ % c->o.profile) == 0;
   {
-    Prof p(c, CAT_SPMV);
+    Prof p(c, CAT_SPMV, timed);
     c->G_z = rks::launch_spmv_sketch(e, basis_col(c, t), c->w, c->zpart, 1, -1);
   }
   {
-    Prof p(c, CAT_REDUCE);
+    Prof p(c, CAT_REDUCE, timed);
     rks::launch_reduce(e, c->zpart, c->G_z, c->pending ? c->spart : nullptr, c->G_s, c->z, c->sr);
   }
   {
-    Prof p(c, CAT_LS);
-    rks::launch_ls(e, t, c->pending, 0, c->z, c->sr, c->S, c->B, c->m + 1, c->cs, c->coef, c->scal, c->flags,
+    Prof p(c, CAT_LS, timed);
+    rks::launch_ls(e, t, c->pending, 0, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef, c->scal, c->flags,
                    kBreakdownRel);
   }
   {
-    Prof p(c, CAT_UPDATE);
+    Prof p(c, CAT_UPDATE, timed);
     c->G_s = rks::launch_update(e, t + 1, c->U, c->ldu, c->w, c->coef, basis_col(c, t + 1), c->spart);
   }
   if (c->st) {
+    const double bs = spmv_bytes(c), bu = (double)(t + 2) * c->n * c->vbytes + (double)c->wbytes * c->n;
     c->st->n_spmv += 1;
-    c->st->bytes_spmv += spmv_bytes(c);
+    c->st->bytes_spmv += bs;
     c->st->n_update += 1;
-    c->st->bytes_update += (double)(t + 2) * c->n * c->vbytes + (double)c->wbytes * c->n;
+    c->st->bytes_update += bu;
     c->st->matvecs += 1;
+    if (timed) {
+      c->st->n_timed_steps += 1;
+      c->st->bytes_timed_spmv += bs;
+      c->st->bytes_timed_update += bu;
+    }
   }
   c->pending = 1;
   c->j = t + 1;
@@ -204,7 +213,7 @@ int arnoldi_step(rks_ctx* c, int t) {
 int finalize_last(rks_ctx* c) {
   const auto& e = c->env;
   rks::launch_reduce(e, nullptr, 0, c->spart, c->G_s, c->z, c->sr);
-  rks::launch_ls(e, c->j, 1, 1, c->z, c->sr, c->S, c->B, c->m + 1, c->cs, c->coef, c->scal, c->flags,
+  rks::launch_ls(e, c->j, 1, 1, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef, c->scal, c->flags,
                  kBreakdownRel);
   c->pending = 0;
   return RKS_OK;
@@ -430,19 +439,38 @@ int rotate_basis(rks_ctx* c, int in0, int min, int out0, int kout, double xscale
   auto stm = c->env.stream;
   HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)min * kout * 8, hipMemcpyHostToDevice, stm));
   {
-    Prof p(c, CAT_ROTATE);
+    Prof p(c, CAT_ROTATE, true);
     rks::launch_rotate(c->env, c->U, c->ldu, in0, min, c->U, c->ldu, out0, kout, c->Yd, c->m, c->keff, xscale, 0);
   }
   HIPCHK(c, hipGetLastError());
   if (c->st) {
+    const double br = (double)(min + 1 + kout + 1) * c->n * c->vbytes;
     c->st->n_rotate += 1;
-    c->st->bytes_rotate += (double)(min + 1 + kout + 1) * c->n * c->vbytes;
+    c->st->bytes_rotate += br;
+    if (c->o.profile > 0) {
+      c->st->n_timed_rotate += 1;
+      c->st->bytes_timed_rotate += br;
+    }
   }
   return RKS_OK;
 }
 
 int push_state(rks_ctx* c) {
   auto stm = c->env.stream;
+  // E = S^T S - I of the contracted sketch (columns 0..keff), exactly symmetric
+  const int d = c->d, ld = c->m + 1, nc = c->keff + 1;
+  std::fill(c->hE, c->hE + (size_t)ld * ld, 0.0);
+  for (int j = 0; j < nc; ++j)
+    for (int i = 0; i <= j; ++i) {
+      const double* a = &c->hS[(size_t)i * d];
+      const double* b = &c->hS[(size_t)j * d];
+      double acc = 0.0;
+      for (int r = 0; r < d; ++r) acc += a[r] * b[r];
+      if (i == j) acc -= 1.0;
+      c->hE[i + (size_t)j * ld] = acc;
+      c->hE[j + (size_t)i * ld] = acc;
+    }
+  HIPCHK(c, hipMemcpyAsync(c->E, c->hE, (size_t)ld * nc * 8, hipMemcpyHostToDevice, stm));
   HIPCHK(c, hipMemcpyAsync(c->B, c->hB, (size_t)(c->m + 1) * c->m * 8, hipMemcpyHostToDevice, stm));
   HIPCHK(c, hipMemcpyAsync(c->S, c->hS, (size_t)c->d * (c->m + 1) * 8, hipMemcpyHostToDevice, stm));
   HIPCHK(c, hipMemcpyAsync(c->cs, c->hcs, (size_t)(c->m + 1) * 8, hipMemcpyHostToDevice, stm));
@@ -680,11 +708,11 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 
 void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U_lo, c->U64, c->w, c->S, c->B, c->cs,
-                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp,
+                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->E,
                  c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  void* host[] = {c->hB, c->hS, c->hcs, c->hY, c->hflags};
+  void* host[] = {c->hB, c->hS, c->hcs, c->hY, c->hE, c->hflags};
   for (void* p : host)
     if (p) (void)hipHostFree(p);
   for (auto e : c->pool) (void)hipEventDestroy(e);
@@ -839,10 +867,12 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->flags, 4 * 4);
   dm((void**)&c->Yd, (size_t)(m + 1) * (m + 1) * 8);
   dm((void**)&c->u0tmp, (size_t)n * 8);
+  dm((void**)&c->E, (size_t)(m + 1) * (m + 1) * 8);
   hm((void**)&c->hB, (size_t)(m + 1) * m * 8);
   hm((void**)&c->hS, (size_t)d * (m + 1) * 8);
   hm((void**)&c->hcs, (size_t)(m + 1) * 8);
   hm((void**)&c->hY, (size_t)(m + 1) * (m + 1) * 8);
+  hm((void**)&c->hE, (size_t)(m + 1) * (m + 1) * 8);
   hm((void**)&c->hflags, 4 * 4);
   if (!ok) {
     free_all(c);
@@ -864,6 +894,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
   // padding rows of U and w stay zero for the whole life of the context
   if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
+  if (rc == RKS_OK && hipMemset(c->E, 0, (size_t)(m + 1) * (m + 1) * 8) != hipSuccess) rc = RKS_EHIP;
   if (rc != RKS_OK) {
     free_all(c);
     delete c;
@@ -1077,6 +1108,24 @@ int rks_rotate(rks_ctx* c, int32_t in0, int32_t min, int32_t out0, int32_t kout,
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->cs, c->hcs, (size_t)(c->m + 1) * 8, hipMemcpyHostToDevice, c->env.stream));
   HIPCHK(c, hipStreamSynchronize(c->env.stream));
+  return RKS_OK;
+}
+
+int rks_copy_probe(const void* src, void* dst, int64_t nbytes, int32_t iters, double* gbs, void* stream) {
+  if (!src || !dst || nbytes < 16 || nbytes % 16 != 0 || iters < 1 || !gbs) return RKS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RKS_EHIP;
+  rks::launch_copy16(st, src, dst, nbytes / 16);  // warm-up
+  (void)hipEventRecord(a, st);
+  for (int i = 0; i < iters; ++i) rks::launch_copy16(st, src, dst, nbytes / 16);
+  (void)hipEventRecord(b, st);
+  float ms = 0.f;
+  const bool ok = hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (!ok || ms <= 0.f) return RKS_EHIP;
+  *gbs = 2.0 * (double)nbytes * iters / (ms * 1e-3) / 1e9;
   return RKS_OK;
 }
 

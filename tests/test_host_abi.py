@@ -127,3 +127,9 @@ def test_product_path_has_no_oracle_dependency():
             if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 txt = open(os.path.join(dp, fn)).read()
                 assert "oracle" not in txt.lower(), fn
+
+
+def test_learned_start_falls_back_to_random_without_weights(tmp_path):
+    """No trained weights: the start is None, i.e. the solver's seeded random start."""
+    from paper_2508_05400_amd.learned_start import start_for
+    assert start_for(np.zeros((2, 64, 64)), 512, weights=str(tmp_path / "missing.npz")) is None
