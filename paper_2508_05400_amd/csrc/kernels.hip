@@ -73,7 +73,23 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
   TA* pw = prod[wv];
-  for (int t = blockIdx.x * 8 + wv; t < ntiles; t += gridDim.x * 8) {
+  // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+  // Giving each XCD one contiguous eighth of the tiles keeps the x entries that
+  // neighbouring rows share (stencil offsets) inside one XCD's L2.
+  const int Gx = gridDim.x >> 3;
+  int t0, tend, tstep;
+  if (Gx > 0 && (gridDim.x & 7) == 0) {
+    const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
+    const int chunk = (ntiles + 7) >> 3;
+    t0 = xcd * chunk + lb * 8 + wv;
+    tend = min(ntiles, (xcd + 1) * chunk);
+    tstep = Gx * 8;
+  } else {
+    t0 = blockIdx.x * 8 + wv;
+    tend = ntiles;
+    tstep = gridDim.x * 8;
+  }
+  for (int t = t0; t < tend; t += tstep) {
     const int4 dsc = tdesc[t];  // {first row, rows, first nonzero, nonzeros}, wave-uniform
     const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
     TA s = 0;
@@ -188,12 +204,17 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ pa, 
 // value as one re-projection h = y + S^T (z - S y), but it needs a single
 // pass over S (for y and, for the new column, its inner products with the
 // old ones) and an O(t^2) correction instead of two more passes.
+// Both block products use a 16 x 64 thread grid: thread (r, c) sums rows
+// r, r + 16, r + 32, ... of column c (16 consecutive rows per column in a
+// wave: coalesced from L2, at most 2-way LDS bank conflicts), and 64 threads
+// add the 16 partial sums.
 // Writes B(0:t, t) = h and the coefficients the update needs:
 // coef[l] = h_l * scale_l (l <= t), coef[t+1] = scale_t.
 // When S(:, 0:t) fits in LDS, every global load of the kernel (S, the two raw
-// sketches, the first rows of E) is issued in one round at entry.
+// sketches, E) is issued in one round at entry.
 constexpr int kLsPre = 20;  // S values per thread staged through registers (LDS path)
-constexpr int kLsPreE = 4;  // rows of E per wave prefetched at entry (t <= 64)
+constexpr int kLsPreE = 4;  // E values per thread prefetched at entry (t <= 64)
+constexpr int kRC = 16;     // row chunks of the block products (1024 threads = 16 x 64)
 
 __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int finalize_only, int use_lds,
                                              const double* __restrict__ zraw, const double* __restrict__ sraw,
@@ -207,8 +228,11 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   double* ys = zs + d;             // kMaxM + 2
   double* gs = ys + kMaxM + 2;     // kMaxM + 2
   double* red = gs + kMaxM + 2;    // 32
-  double* Ssh = red + 32;          // d * (t + 1) when use_lds
+  double* pa = red + 32;           // 64 x 17 partial sums
+  double* pg = pa + 64 * 17;       // 64 x 17 partial sums
+  double* Ssh = pg + 64 * 17;      // d * (t + 1) when use_lds
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const int rc = tid & (kRC - 1), cl = tid >> 4;  // chunk of rows, column slot
   // ---- every global load up front ----
   const int tot = use_lds ? d * t : 0;
   double sv[kLsPre];
@@ -224,12 +248,12 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
     if (!finalize_only) zrv = zraw[tid];
   }
   if (!pending) ctg = cs[t];
+  const bool pre_e = !finalize_only && t <= kRC * kLsPreE;
   double ev[kLsPreE];
-  const bool pre_e = !finalize_only && t <= 64;
 #pragma unroll
   for (int i = 0; i < kLsPreE; ++i) {
-    const int l = wv + nw * i;
-    ev[i] = (pre_e && l < t && lane < t) ? E[lane + (size_t)l * ldb] : 0.0;
+    const int c = rc + kRC * i;
+    ev[i] = (pre_e && c < t && cl < t) ? E[c + (size_t)cl * ldb] : 0.0;
   }
   // ---- both squared norms in one block reduction ----
   {
@@ -281,28 +305,38 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   __syncthreads();
   // ---- one pass over S: y_l = s_l . z, and g_l = s_l . s_t for a new column ----
   const double* Sc = use_lds ? Ssh : S;
-  for (int l = wv; l < ncol; l += nw) {
-    const double* Sl = (!use_lds && pending && l == t) ? snew : Sc + (size_t)l * d;
+  for (int c0 = 0; c0 < ncol; c0 += 64) {
+    const int l = c0 + cl;
     double a = 0.0, g = 0.0;
-    if (pending && l < t) {
+    if (l < ncol) {
+      const double* Sl = (!use_lds && pending && l == t) ? snew : Sc + (size_t)l * d;
+      if (pending && l < t) {
 #pragma unroll 4
-      for (int b = lane; b < d; b += 64) {
-        const double v = Sl[b];
-        a += v * zs[b];
-        g += v * snew[b];
+        for (int b = rc; b < d; b += kRC) {
+          const double v = Sl[b];
+          a += v * zs[b];
+          g += v * snew[b];
+        }
+      } else {
+#pragma unroll 4
+        for (int b = rc; b < d; b += kRC) a += Sl[b] * zs[b];
       }
-      g = wave_sum(g);
-    } else {
-#pragma unroll 4
-      for (int b = lane; b < d; b += 64) a += Sl[b] * zs[b];
     }
-    a = wave_sum(a);
-    if (lane == 0) {
-      ys[l] = a;
-      gs[l] = g;
+    pa[cl * 17 + rc] = a;
+    pg[cl * 17 + rc] = g;
+    __syncthreads();
+    if (tid < 64 && c0 + tid < ncol) {
+      double sa = 0.0, sg = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRC; ++r) {
+        sa += pa[tid * 17 + r];
+        sg += pg[tid * 17 + r];
+      }
+      ys[c0 + tid] = sa;
+      gs[c0 + tid] = sg;
     }
+    __syncthreads();
   }
-  __syncthreads();
   // ---- the new column of E, then h = y - E y ----
   if (pending) {
     for (int l = tid; l <= t; l += blockDim.x) {
@@ -311,32 +345,35 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
       E[t + (size_t)l * ldb] = g;
     }
   }
-  for (int i = 0, l = wv; l < ncol; ++i, l += nw) {
-    // row l of E: columns c < t from memory (prefetched when t <= 64), column t
-    // from this kernel when it was just finalised
+  for (int c0 = 0; c0 < ncol; c0 += 64) {
+    const int l = c0 + cl;
     double a = 0.0;
-    if (l < t) {
-      if (pre_e && i < kLsPreE) {
-        if (lane < t) a = ev[i] * ys[lane];
+    if (l < t) {  // columns c < t of row l (= column l, E is symmetric)
+      if (pre_e && c0 == 0) {
+#pragma unroll
+        for (int i = 0; i < kLsPreE; ++i)
+          if (rc + kRC * i < t) a += ev[i] * ys[rc + kRC * i];
       } else {
-        for (int c = lane; c < t; c += 64) a += E[c + (size_t)l * ldb] * ys[c];
+        for (int c = rc; c < t; c += kRC) a += E[c + (size_t)l * ldb] * ys[c];
       }
-      a = wave_sum(a);
-      a += (pending ? gs[l] : E[l + (size_t)t * ldb]) * ys[t];
-    } else {  // l == t
-      if (pending) {
-        for (int c = lane; c < t; c += 64) a += gs[c] * ys[c];
-      } else {
-        for (int c = lane; c < t; c += 64) a += E[t + (size_t)c * ldb] * ys[c];
-      }
-      a = wave_sum(a);
-      if (!pending) a += E[t + (size_t)t * ldb] * ys[t];
+    } else if (l == t) {
+      for (int c = rc; c < t; c += kRC) a += (pending ? gs[c] : E[c + (size_t)t * ldb]) * ys[c];
     }
-    if (lane == 0) {
-      const double h = ys[l] - a;
-      B[l + (size_t)t * ldb] = h;
-      coef[l] = h * ((l == t) ? ct : cs[l]);
+    pa[cl * 17 + rc] = a;
+    __syncthreads();
+    if (tid < 64 && c0 + tid < ncol) {
+      const int l2 = c0 + tid;
+      double sa = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRC; ++r) sa += pa[tid * 17 + r];
+      // column t of row l2 (just finalised, or from the host)
+      if (l2 < t) sa += (pending ? gs[l2] : E[l2 + (size_t)t * ldb]) * ys[t];
+      else if (!pending) sa += E[t + (size_t)t * ldb] * ys[t];
+      const double h = ys[l2] - sa;
+      B[l2 + (size_t)t * ldb] = h;
+      coef[l2] = h * ((l2 == t) ? ct : cs[l2]);
     }
+    __syncthreads();
   }
   if (tid == 0) coef[t + 1] = ct;
 }
@@ -572,7 +609,8 @@ inline int grid_for(int64_t work, int per_block, int cap) {
 
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
   const int prec = prec_override >= 0 ? prec_override : e.prec;
-  const int G = grid_for(e.ntiles, 8, kMaxG);
+  int G = grid_for(e.ntiles, 8, kMaxG);
+  if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the tile mapping)
   dim3 grid(G), block(512);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<double, double, double, KIND><<<grid, block, 0, e.stream>>>(
@@ -599,7 +637,7 @@ void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const 
                double* S, double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
                double bd_rel) {
   const int d = e.sp.d;
-  const size_t base = (size_t)(2 * d + 2 * (kMaxM + 2) + 32) * 8;
+  const size_t base = (size_t)(2 * d + 2 * (kMaxM + 2) + 32 + 2 * 64 * 17) * 8;
   const size_t full = base + (size_t)d * (t + 1) * 8;
   const int use_lds = (!finalize_only && full <= kLsLdsMax && (size_t)d * t <= (size_t)kLsPre * 1024) ? 1 : 0;
   const size_t lds = use_lds ? full : base;
