@@ -61,10 +61,17 @@ double house(int k, const double* x, double* v) {
   return beta;
 }
 
+// Householder reduction to upper Hessenberg form.  Each reflector only spans
+// rows k+1 .. (last nonzero row of column k): a matrix that is already
+// Hessenberg except for a few rows (the Krylov-Schur contraction's T_k with
+// the residual row b^T below it) costs O(k^2 n) instead of O(n^3).
 void hessenberg(int n, double* A, int lda, double* Z, int ldz) {
   std::vector<double> v(n), x(n);
   for (int k = 0; k + 2 < n; ++k) {
-    int len = n - k - 1;
+    int last = n - 1;
+    while (last > k + 1 && at(A, lda, last, k) == 0.0) --last;
+    if (last <= k + 1) continue;
+    int len = last - k;
     for (int i = 0; i < len; ++i) x[i] = at(A, lda, k + 1 + i, k);
     double beta = house(len, x.data(), v.data());
     if (beta == 0.0) continue;
@@ -74,18 +81,22 @@ void hessenberg(int n, double* A, int lda, double* Z, int ldz) {
       s *= beta;
       for (int i = 0; i < len; ++i) at(A, lda, k + 1 + i, j) -= s * v[i];
     }
-    for (int i = 0; i < n; ++i) {  // cols k+1.. : A <- A H
-      double s = 0.0;
-      for (int j = 0; j < len; ++j) s += at(A, lda, i, k + 1 + j) * v[j];
-      s *= beta;
-      for (int j = 0; j < len; ++j) at(A, lda, i, k + 1 + j) -= s * v[j];
-    }
-    for (int i = 0; i < n; ++i) {  // Z <- Z H
-      double s = 0.0;
-      for (int j = 0; j < len; ++j) s += at(Z, ldz, i, k + 1 + j) * v[j];
-      s *= beta;
-      for (int j = 0; j < len; ++j) at(Z, ldz, i, k + 1 + j) -= s * v[j];
-    }
+    // cols k+1.. : A <- A H and Z <- Z H, column-wise so the inner loops are contiguous
+    auto right = [&](double* M, int ld) {
+      std::fill(x.begin(), x.end(), 0.0);
+      for (int j = 0; j < len; ++j) {
+        const double* c = &M[(size_t)(k + 1 + j) * ld];
+        const double vj = v[j];
+        for (int i = 0; i < n; ++i) x[i] += c[i] * vj;
+      }
+      for (int j = 0; j < len; ++j) {
+        double* c = &M[(size_t)(k + 1 + j) * ld];
+        const double f = beta * v[j];
+        for (int i = 0; i < n; ++i) c[i] -= x[i] * f;
+      }
+    };
+    right(A, lda);
+    right(Z, ldz);
     for (int i = k + 2; i < n; ++i) at(A, lda, i, k) = 0.0;
   }
 }
@@ -108,13 +119,23 @@ void refl_sim(int n, double* H, int ldh, double* Z, int ldz, const double* v, do
     for (int i = 0; i < K; ++i) col[i] -= s * vv[i];
   }
   auto right = [&](double* M, int ld, int rows) {
-    double* c[K];
-    for (int j = 0; j < K; ++j) c[j] = &M[(size_t)(r0 + j) * ld];
-    for (int i = 0; i < rows; ++i) {
-      double s = 0.0;
-      for (int j = 0; j < K; ++j) s += c[j][i] * vv[j];
-      s *= beta;
-      for (int j = 0; j < K; ++j) c[j][i] -= s * vv[j];
+    double* __restrict__ c0 = &M[(size_t)r0 * ld];
+    double* __restrict__ c1 = &M[(size_t)(r0 + 1) * ld];
+    double* __restrict__ c2 = &M[(size_t)(r0 + (K > 2 ? 2 : 1)) * ld];
+    const double b0 = beta * vv[0], b1 = beta * vv[1], b2 = K > 2 ? beta * vv[K - 1] : 0.0;
+    if (K == 3) {
+      for (int i = 0; i < rows; ++i) {
+        const double s = c0[i] * vv[0] + c1[i] * vv[1] + c2[i] * vv[K - 1];
+        c0[i] -= s * b0;
+        c1[i] -= s * b1;
+        c2[i] -= s * b2;
+      }
+    } else {
+      for (int i = 0; i < rows; ++i) {
+        const double s = c0[i] * vv[0] + c1[i] * vv[1];
+        c0[i] -= s * b0;
+        c1[i] -= s * b1;
+      }
     }
   };
   right(H, ldh, rr);
