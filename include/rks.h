@@ -77,9 +77,10 @@ typedef struct {
   int32_t precision;     /* rks_precision, default FP64 */
   int32_t max_restarts;  /* contraction/extension cycles after the first extension, default 300 */
   int32_t lock;          /* lock converged leading Schur vectors, default 1 */
-  int32_t profile;       /* P > 0: time the kernels of every P-th Arnoldi step and every
-                            rotation with HIP events on the solver's stream (each timed
-                            launch adds two event records); 0 = off (default) */
+  int32_t profile;       /* P > 0: time every P-th Arnoldi step with HIP events on the
+                            solver's stream, alternately per kernel and as a whole, and
+                            every rotation (each event pair adds a few microseconds);
+                            0 = off (default) */
   double whiten_tol;     /* whiten when ||S_k^T S_k - I||_F exceeds this, default 1e-12 */
   void* stream;          /* hipStream_t, NULL = default stream */
   double resid_tol;      /* > 0: also stop once every pair's FP64 residual
@@ -121,6 +122,9 @@ typedef struct {
   double bytes_spmv, bytes_update, bytes_rotate;  /* algorithmic HBM bytes moved, all launches */
   int64_t n_timed_steps, n_timed_rotate;  /* timed Arnoldi steps (4 launches each) and rotations */
   double bytes_timed_spmv, bytes_timed_update, bytes_timed_rotate;  /* algorithmic bytes of the timed launches */
+  int64_t n_timed_whole;     /* sampled Arnoldi steps timed as a whole (the other half of the sample) */
+  double t_step;             /* seconds summed over those steps (four launches each, one event pair) */
+  double bytes_timed_whole;  /* their algorithmic bytes (SpMV + update) */
   double hist_est[512];  /* max estimate after contraction r (r < 512) */
 } rks_stats;
 

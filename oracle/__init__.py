@@ -12,6 +12,8 @@ Modules:
   rks     -- Algorithms 1 and 2 of the paper with residual monitoring
              (Section 4.1), locking (Sections 4.2-4.4) and whitening
              (Section 3.3), step by step in the paper's order.
+  convnet -- the learned-start network (dilated 3x3 convolutions, subspace
+             loss, Adam, bilinear resampling) written out with loops.
 
 Parity status: every function is pinned by a test under tests/ (known-answer
 vectors, closed-form spectra, dense brute force, exact identities of the

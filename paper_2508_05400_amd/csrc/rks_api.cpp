@@ -112,7 +112,7 @@ int fail(rks_ctx* c, int code, const std::string& msg) {
 void* basis_col(rks_ctx* c, int l) { return (char*)c->U + (size_t)l * c->ldu * c->vbytes; }
 
 // ---- profiling -------------------------------------------------------------
-enum { CAT_SPMV = 0, CAT_REDUCE, CAT_LS, CAT_UPDATE, CAT_ROTATE };
+enum { CAT_SPMV = 0, CAT_REDUCE, CAT_LS, CAT_UPDATE, CAT_ROTATE, CAT_STEP };
 
 hipEvent_t get_event(rks_ctx* c) {
   if (c->pool_used == c->pool.size()) {
@@ -156,6 +156,7 @@ void flush_events(rks_ctx* c) {
     double s = ms * 1e-3;
     switch (p.cat) {
       case CAT_SPMV: c->st->t_spmv += s; break;
+      case CAT_STEP: c->st->t_step += s; break;
       case CAT_REDUCE: c->st->t_reduce += s; break;
       case CAT_LS: c->st->t_ls += s; break;
       case CAT_UPDATE: c->st->t_update += s; break;
@@ -174,7 +175,15 @@ double spmv_bytes(const rks_ctx* c) {
 // ---- one Arnoldi step (Algorithm 2 loop body) ------------------------------
 int arnoldi_step(rks_ctx* c, int t) {
   const auto& e = c->env;
-  const bool timed = c->o.profile > 0 && c->st && (c->step_count++ % c->o.profile) == 0;
+  // sampled timing: every P-th step, alternately per kernel and as a whole
+  // (one event pair around the four launches, for the loop's bandwidth)
+  bool timed = false, whole = false;
+  if (c->o.profile > 0 && c->st && (c->step_count % c->o.profile) == 0) {
+    if ((c->step_count / c->o.profile) % 2 == 0) timed = true;
+    else whole = true;
+  }
+  ++c->step_count;
+  Prof pw(c, CAT_STEP, whole);
   {
     Prof p(c, CAT_SPMV, timed);
     c->G_z = rks::launch_spmv_sketch(e, basis_col(c, t), c->w, c->zpart, 1, -1);
@@ -203,6 +212,10 @@ int arnoldi_step(rks_ctx* c, int t) {
       c->st->n_timed_steps += 1;
       c->st->bytes_timed_spmv += bs;
       c->st->bytes_timed_update += bu;
+    }
+    if (whole) {
+      c->st->n_timed_whole += 1;
+      c->st->bytes_timed_whole += bs + bu;
     }
   }
   c->pending = 1;

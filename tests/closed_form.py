@@ -25,3 +25,32 @@ def convdiff_eigs(N: int, beta) -> np.ndarray:
     for p in parts[1:]:
         tot = (tot[:, None] + p[None, :]).ravel()
     return tot
+
+
+def factor_kappa(N: int, beta: float) -> np.ndarray:
+    """Eigenvalue condition numbers of the 1D factor (|g| < 1): right
+    eigenvectors r^i sin(i j pi/(N+1)), left ones r^-i sin(i j pi/(N+1)),
+    r = sqrt((1+g)/(1-g)); kappa_j = |v||w| / |w^T v| with w^T v = (N+1)/2."""
+    h = 1.0 / (N + 1)
+    g = beta * h / 2.0
+    r = np.sqrt((1.0 + g) / (1.0 - g))
+    i = np.arange(1, N + 1)
+    kap = np.empty(N)
+    for j in range(1, N + 1):
+        s = np.sin(i * j * np.pi / (N + 1))
+        v = r ** i * s
+        w = r ** (-i) * s
+        kap[j - 1] = np.linalg.norm(v) * np.linalg.norm(w) / abs(w @ v)
+    return kap
+
+
+def convdiff_eigs_kappa(N: int, beta):
+    """Eigenvalues and condition numbers of the Kronecker-sum operator (the
+    eigenvectors are Kronecker products, so the condition numbers multiply)."""
+    lam = [factor_eigs(N, b) for b in beta]
+    kap = [factor_kappa(N, b) for b in beta]
+    L, K = lam[0], kap[0]
+    for l2, k2 in zip(lam[1:], kap[1:]):
+        L = (L[:, None] + l2[None, :]).ravel()
+        K = (K[:, None] * k2[None, :]).ravel()
+    return L, K

@@ -133,3 +133,31 @@ def test_learned_start_falls_back_to_random_without_weights(tmp_path):
     """No trained weights: the start is None, i.e. the solver's seeded random start."""
     from paper_2508_05400_amd.learned_start import start_for
     assert start_for(np.zeros((2, 64, 64)), 512, weights=str(tmp_path / "missing.npz")) is None
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of rks_csr, rks_opts and rks_stats have the C
+    compiler's size and field offsets (a mismatch would corrupt memory)."""
+    import shutil
+    import subprocess
+    from paper_2508_05400_amd import _binding as B
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"rks_csr": B.RksCsr, "rks_opts": B.RksOpts, "rks_stats": B.RksStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rks.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        py = structs[cname]
+        got = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert got == int(val), (cname, field, got, val)

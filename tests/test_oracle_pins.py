@@ -294,3 +294,17 @@ def test_scale_invariance_of_ritz_values():
         o.extend()
     assert np.allclose(o1.B, o2.B, rtol=0, atol=1e-12 * o1.normA1)
     assert np.allclose(o1.U, 2.0 * o2.U, atol=1e-13)
+
+
+def test_closed_form_condition_numbers_match_dense():
+    """The closed-form eigenvalue condition numbers used to bound the GPU's
+    final eigenvalues equal LAPACK's (left/right eigenvectors) on a 12^2 grid."""
+    import scipy.linalg as sla
+    from tests.closed_form import convdiff_eigs_kappa
+    N, beta = 12, (20.0, 10.0)
+    w, vl, vr = sla.eig(convdiff2d(N, beta).to_dense(), left=True, right=True)
+    kd = np.linalg.norm(vl, axis=0) * np.linalg.norm(vr, axis=0) / np.abs(np.einsum("ij,ij->j", vl.conj(), vr))
+    L, K = convdiff_eigs_kappa(N, beta)
+    i1, i2 = np.argsort(w.real), np.argsort(L)
+    assert np.max(np.abs(w.real[i1] - L[i2])) < 1e-10 * L.max()
+    assert np.max(np.abs(kd[i1] / K[i2] - 1.0)) < 1e-6
