@@ -227,6 +227,7 @@ def main():
         "max_resid": float(np.max(res)),
         "max_est": st["max_est"],
         "loop_gbs": loop_gbs,
+        "spmv_layout": {1: "rows", 2: "column_blocks"}.get(st["spmv_layout"], "?"),
         "kernel_avg_us": _kernel_avg_us(st),
         "step_avg_us": st["t_step"] / max(st["n_timed_whole"], 1) * 1e6,
         "timed_sample": (f"HIP events on every {args.profile_every}th Arnoldi step inside the timed solves, "

@@ -57,6 +57,14 @@ typedef enum { RKS_SKETCH_GAUSS = 0, RKS_SKETCH_SPARSE = 1 } rks_sketch_kind;
  * Rayleigh quotient and all small dense steps stay FP64). */
 typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2 } rks_precision;
 
+/* SpMV layout.  ROWS: wave tiles of consecutive rows.  COLUMN_BLOCKS: the
+ * columns split into 8 contiguous blocks, one per XCD, each multiplied on its
+ * own and the 8 partial vectors added (for rows that gather x from everywhere,
+ * with x larger than an XCD's L2; it stores a second, column-blocked copy of
+ * A and 8 partial vectors).  AUTO picks COLUMN_BLOCKS when n >= 2^20 and the
+ * median column span of a row tile exceeds n/4. */
+typedef enum { RKS_SPMV_AUTO = 0, RKS_SPMV_ROWS = 1, RKS_SPMV_COLUMN_BLOCKS = 2 } rks_spmv_layout;
+
 /* Square CSR matrix: row_ptr[n+1] (monotone, row_ptr[0] = 0), col[nnz]
  * (in [0, n), strictly increasing inside a row), val[nnz] FP64.
  * on_device = 0: host arrays; 1: device arrays.  Copied by rks_create. */
@@ -93,6 +101,7 @@ typedef struct {
   double refine_tol;     /* verified-residual target of the low-precision phase
                             (it also stops when its estimates reach it);
                             0 = 1e-6 for an FP32 basis, 1e-3 for BF16 */
+  int32_t spmv_layout;   /* rks_spmv_layout, default AUTO */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -125,6 +134,7 @@ typedef struct {
   int64_t n_timed_whole;     /* sampled Arnoldi steps timed as a whole (the other half of the sample) */
   double t_step;             /* seconds summed over those steps (four launches each, one event pair) */
   double bytes_timed_whole;  /* their algorithmic bytes (SpMV + update) */
+  int32_t spmv_layout;       /* rks_spmv_layout in use (ROWS or COLUMN_BLOCKS) */
   double hist_est[512];  /* max estimate after contraction r (r < 512) */
 } rks_stats;
 

@@ -17,6 +17,7 @@ RKS_EINVAL, RKS_ENOMEM, RKS_EHIP, RKS_ENAN, RKS_ESTATE, RKS_EBREAKDOWN, RKS_EDEN
 WHICH = {"LM": 0, "SM": 1, "LR": 2, "SR": 3}
 SKETCH = {"gauss": 0, "sparse": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "v32": 1, "bf16": 2, "vbf16": 2}
+SPMV_LAYOUT = {"auto": 0, "rows": 1, "column_blocks": 2}
 
 
 class RksCsr(ctypes.Structure):
@@ -31,7 +32,7 @@ class RksOpts(ctypes.Structure):
                 ("lock", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("whiten_tol", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("resid_tol", ctypes.c_double), ("refine", ctypes.c_int32),
-                ("refine_tol", ctypes.c_double)]
+                ("refine_tol", ctypes.c_double), ("spmv_layout", ctypes.c_int32)]
 
 
 class RksStats(ctypes.Structure):
@@ -50,7 +51,8 @@ class RksStats(ctypes.Structure):
                 ("n_timed_rotate", ctypes.c_int64), ("bytes_timed_spmv", ctypes.c_double),
                 ("bytes_timed_update", ctypes.c_double), ("bytes_timed_rotate", ctypes.c_double),
                 ("n_timed_whole", ctypes.c_int64), ("t_step", ctypes.c_double),
-                ("bytes_timed_whole", ctypes.c_double), ("hist_est", ctypes.c_double * 512)]
+                ("bytes_timed_whole", ctypes.c_double), ("spmv_layout", ctypes.c_int32),
+                ("hist_est", ctypes.c_double * 512)]
 
     def as_dict(self) -> dict:
         out = {f: getattr(self, f) for f, _ in self._fields_ if f != "hist_est"}
@@ -156,6 +158,8 @@ def rks_opts_default(**kw) -> RksOpts:
             v = SKETCH[v]
         if k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        if k == "spmv_layout" and isinstance(v, str):
+            v = SPMV_LAYOUT[v]
         if k == "stream" and v is not None and not isinstance(v, int):
             v = int(v.cuda_stream)
         setattr(o, k, v)

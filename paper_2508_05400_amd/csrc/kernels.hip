@@ -54,13 +54,71 @@ __device__ __forceinline__ void bins_store(const double* bins, double* part, int
 }
 
 // ---------------------------------------------------------------------------
-// w = A x (CSR, wave tiles staged through LDS) and partials of Omega w.
-// Each wave owns one tile of <= 64 rows / <= 512 nonzeros at a time: a lane
-// loads up to 8 nonzeros (coalesced, all loads issued before any use), gathers
-// x for them, and stages the products in the wave's own LDS slice; then
-// 64/nr lanes per row reduce the row from LDS.  LDS operations of one wave
-// complete in program order, so the wave needs no block-level barrier.  A
-// tile that is a single row longer than 512 nonzeros is reduced by the wave.
+// Row sums of one wave tile {first row r0, rows nr, first nonzero e0,
+// nonzeros ne} of a CSR matrix times x.  A lane loads up to 8 nonzeros
+// (coalesced, all loads issued before any use), gathers x for them, and
+// stages the products in the wave's own LDS slice pw; then 64/nr lanes per
+// row reduce the row from LDS.  LDS operations of one wave complete in program
+// order, so the wave needs no block-level barrier.  A tile that is a single
+// row longer than 512 nonzeros is reduced by the whole wave.  The row sum ends
+// in the lane with sub == 0 of row rr (< nr).  after_loads(rr, sub) runs while
+// the loads are in flight (independent work can hide under them).
+template <typename TV, typename TA, typename F>
+__device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* __restrict__ col,
+                                        const TA* __restrict__ val, const TV* __restrict__ x, int4 dsc, TA* pw,
+                                        int lane, int& rr, int& sub, F&& after_loads) {
+  const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
+  TA s = 0;
+  if (ne <= kTileNnz) {
+    int lpr = 64;
+    while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
+    rr = lane / lpr;
+    sub = lane - rr * lpr;
+    int ra = 0, rb = 0;
+    if (rr < nr) {
+      ra = rp[r0 + rr] - e0;
+      rb = rp[r0 + rr + 1] - e0;
+    }
+    int ci[kTileNnz / 64];
+    TA vv[kTileNnz / 64];
+#pragma unroll
+    for (int u = 0; u < kTileNnz / 64; ++u) {
+      const int e = lane + 64 * u;
+      if (e < ne) {
+        ci[u] = col[e0 + e];
+        vv[u] = val[e0 + e];
+      }
+    }
+    after_loads(rr, sub);
+    TA xv[kTileNnz / 64];
+#pragma unroll
+    for (int u = 0; u < kTileNnz / 64; ++u) {
+      const int e = lane + 64 * u;
+      if (e < ne) xv[u] = (TA)Conv<TV>::ld(x[ci[u]]);
+    }
+#pragma unroll
+    for (int u = 0; u < kTileNnz / 64; ++u) {
+      const int e = lane + 64 * u;
+      if (e < ne) pw[e] = vv[u] * xv[u];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (rr < nr)
+      for (int e = ra + sub; e < rb; e += lpr) s += pw[e];
+    for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    rr = 0;
+    sub = lane;
+    for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  }
+  return s;
+}
+
+// w = A x (CSR, wave tiles staged through LDS; see tile_rows) and partials of
+// Omega w.  Workgroups are dealt to the 8 XCDs round-robin (block b runs on
+// XCD b % 8); giving each XCD one contiguous eighth of the tiles keeps the x
+// entries that neighbouring rows share (stencil offsets) inside one XCD's L2.
 template <typename TV, typename TW, typename TA, int KIND>
 __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
                                                      const TA* __restrict__ val, const int4* __restrict__ tdesc,
@@ -73,9 +131,6 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
   TA* pw = prod[wv];
-  // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
-  // Giving each XCD one contiguous eighth of the tiles keeps the x entries that
-  // neighbouring rows share (stencil offsets) inside one XCD's L2.
   const int Gx = gridDim.x >> 3;
   int t0, tend, tstep;
   if (Gx > 0 && (gridDim.x & 7) == 0) {
@@ -90,63 +145,21 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
     tstep = gridDim.x * 8;
   }
   for (int t = t0; t < tend; t += tstep) {
-    const int4 dsc = tdesc[t];  // {first row, rows, first nonzero, nonzeros}, wave-uniform
-    const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
-    TA s = 0;
+    const int4 dsc = tdesc[t];  // wave-uniform
     int rr, sub;
     int hrows[8];
     float hsg[8];
     int have = 0;
-    if (ne <= kTileNnz) {
-      int lpr = 64;
-      while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
-      rr = lane / lpr;
-      sub = lane - rr * lpr;
-      int ra = 0, rb = 0;
-      if (rr < nr) {
-        ra = rp[r0 + rr] - e0;
-        rb = rp[r0 + rr + 1] - e0;
-      }
-      int ci[kTileNnz / 64];
-      TA vv[kTileNnz / 64];
-#pragma unroll
-      for (int u = 0; u < kTileNnz / 64; ++u) {
-        const int e = lane + 64 * u;
-        if (e < ne) {
-          ci[u] = col[e0 + e];
-          vv[u] = val[e0 + e];
-        }
-      }
-      // the row's sketch column does not depend on the data: hash it while
-      // the loads are in flight
-      if (KIND == 1 && do_sketch && rr < nr && sub == 0) {
-        sparse_column((uint64_t)(r0 + rr), sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
+    // the row's sketch column does not depend on the data: hash it while the
+    // tile's loads are in flight
+    const TA s = tile_rows<TV, TA>(rp, col, val, x, dsc, pw, lane, rr, sub, [&](int r_, int s_) {
+      if (KIND == 1 && do_sketch && r_ < dsc.y && s_ == 0) {
+        sparse_column((uint64_t)(dsc.x + r_), sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
         have = 1;
       }
-      TA xv[kTileNnz / 64];
-#pragma unroll
-      for (int u = 0; u < kTileNnz / 64; ++u) {
-        const int e = lane + 64 * u;
-        if (e < ne) xv[u] = (TA)Conv<TV>::ld(x[ci[u]]);
-      }
-#pragma unroll
-      for (int u = 0; u < kTileNnz / 64; ++u) {
-        const int e = lane + 64 * u;
-        if (e < ne) pw[e] = vv[u] * xv[u];
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (rr < nr)
-        for (int e = ra + sub; e < rb; e += lpr) s += pw[e];
-      for (int off = lpr >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
-      __builtin_amdgcn_wave_barrier();
-    } else {
-      rr = 0;
-      sub = lane;
-      for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
-      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    }
-    if (rr < nr && sub == 0) {
-      const int r = r0 + rr;
+    });
+    if (rr < dsc.y && sub == 0) {
+      const int r = dsc.x + rr;
       const TW ws = (TW)s;
       w[r] = ws;
       if (do_sketch) {
@@ -164,36 +177,90 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
   if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
 }
 
-// Deterministic sum of G partial rows: block (x, y) sums 32 bins of array y;
-// 32 slices of rows per bin, each slice summed with 4 independent chains.
-__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ pa, const double* __restrict__ pb,
-                                                 int Ga, int Gb, int d, double* __restrict__ oa,
-                                                 double* __restrict__ ob) {
+// Column-blocked SpMV for operators whose rows gather x from everywhere (x
+// larger than an XCD's L2 and no locality to exploit).  The columns are split
+// into kCb contiguous blocks; block c of A is a CSR matrix of its own (all n
+// rows) with its own wave tiles.  Workgroup b runs on XCD b % kCb and
+// multiplies column block b % kCb only, so the x entries it gathers span
+// n / kCb values that stay in that XCD's L2.  Row sums go to P(:, c); a second
+// kernel adds the kCb partial vectors in a fixed order and sketches w.
+template <typename TV, typename TW, typename TA>
+__global__ __launch_bounds__(512) void k_spmv_cb(int64_t n, const int* __restrict__ rp, const int* __restrict__ col,
+                                                 const TA* __restrict__ val, const int4* __restrict__ tdesc,
+                                                 CbTiles cb, const TV* __restrict__ x, TW* __restrict__ P,
+                                                 int64_t ldp) {
+  __shared__ TA prod[8][kTileNnz];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  TA* pw = prod[wv];
+  const int c = blockIdx.x % kCb, lb = blockIdx.x / kCb, Gc = gridDim.x / kCb;
+  const int* rpc = rp + (int64_t)c * (n + 1);  // this block's row pointers (global offsets)
+  TW* Pc = P + (int64_t)c * ldp;
+  for (int t = cb.off[c] + lb * 8 + wv; t < cb.off[c + 1]; t += Gc * 8) {
+    const int4 dsc = tdesc[t];
+    int rr, sub;
+    const TA s = tile_rows<TV, TA>(rpc, col, val, x, dsc, pw, lane, rr, sub, [](int, int) {});
+    if (rr < dsc.y && sub == 0) Pc[dsc.x + rr] = (TW)s;
+  }
+}
+
+// w = sum_c P(:, c) (c in order) and partials of Omega w.
+template <typename TW, int KIND>
+__global__ __launch_bounds__(512) void k_cb_combine(int64_t n, const TW* __restrict__ P, int64_t ldp,
+                                                    TW* __restrict__ w, double* __restrict__ zpart, SketchP sp,
+                                                    int do_sketch) {
+  __shared__ double bins[kMaxD];
+  if (do_sketch) bins_zero(bins, sp.d);
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    TW v[kCb];
+#pragma unroll
+    for (int c = 0; c < kCb; ++c) v[c] = P[i + (int64_t)c * ldp];
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kCb; ++c) s += (double)v[c];
+    const TW ws = (TW)s;
+    w[i] = ws;
+    if (do_sketch) sketch_add<KIND>(bins, (uint64_t)i, (double)ws, sp);
+  }
+  __syncthreads();
+  if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
+}
+
+// Deterministic sum of G partial rows: block (x, y) sums kRedBins bins of
+// array y.  Each of the kRedSl row slices adds every kRedSl-th row with two
+// chains; a fixed tree over the slices finishes the sum (same order every
+// call).  A wave reads 8 rows x 64 contiguous bytes per load.
+constexpr int kRedBins = 8;
+constexpr int kRedSl = 64;
+
+__global__ __launch_bounds__(kRedBins * kRedSl) void k_reduce(const double* __restrict__ pa,
+                                                             const double* __restrict__ pb, int Ga, int Gb, int d,
+                                                             double* __restrict__ oa, double* __restrict__ ob) {
   const double* p = blockIdx.y ? pb : pa;
   double* o = blockIdx.y ? ob : oa;
   const int G = blockIdx.y ? Gb : Ga;
   if (p == nullptr) return;
-  __shared__ double red[32][33];
-  const int lb = threadIdx.x & 31, sl = threadIdx.x >> 5;
-  const int b = blockIdx.x * 32 + lb;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  __shared__ double red[kRedSl][kRedBins + 1];
+  const int lb = threadIdx.x % kRedBins, sl = threadIdx.x / kRedBins;
+  const int b = blockIdx.x * kRedBins + lb;
+  double a0 = 0.0, a1 = 0.0;
   if (b < d) {
     int g = sl;
-    for (; g + 96 < G; g += 128) {
+    for (; g + kRedSl < G; g += 2 * kRedSl) {
       a0 += p[(size_t)g * d + b];
-      a1 += p[(size_t)(g + 32) * d + b];
-      a2 += p[(size_t)(g + 64) * d + b];
-      a3 += p[(size_t)(g + 96) * d + b];
+      a1 += p[(size_t)(g + kRedSl) * d + b];
     }
-    for (; g < G; g += 32) a0 += p[(size_t)g * d + b];
+    for (; g < G; g += kRedSl) a0 += p[(size_t)g * d + b];
   }
-  red[sl][lb] = (a0 + a1) + (a2 + a3);
+  red[sl][lb] = a0 + a1;
   __syncthreads();
-  if (threadIdx.x < 32 && b < d) {
-    double tot = 0.0;
-    for (int q = 0; q < 32; ++q) tot += red[q][lb];
-    o[b] = tot;
+  for (int s = kRedSl / 2; s > 0; s >>= 1) {
+    if (sl < s) red[sl][lb] += red[sl + s][lb];
+    __syncthreads();
   }
+  if (sl == 0 && b < d) o[b] = red[0][lb];
 }
 
 // Finalise column t when pending (beta = ||s~||, S(:,t) = s~/beta, scale
@@ -607,8 +674,26 @@ inline int grid_for(int64_t work, int per_block, int cap) {
     }                                \
   } while (0)
 
+template <typename TV, typename TW, typename TA>
+static int spmv_cb_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, double* zpart, int do_sketch) {
+  const int ntiles = e.cbt.off[kCb];
+  int G1 = grid_for(ntiles, 8, 2048);
+  G1 = (G1 + kCb - 1) / kCb * kCb;  // every column block gets the same number of workgroups
+  k_spmv_cb<TV, TW, TA><<<G1, 512, 0, e.stream>>>(e.n, e.rp_cb, e.col_cb, val, (const int4*)e.tiles_cb, e.cbt, x,
+                                                  (TW*)e.P, e.ldu);
+  const int G2 = grid_for(e.n, 512, kMaxG);
+  RKS_SKETCH_SWITCH(e.sp_kind, (k_cb_combine<TW, KIND><<<G2, 512, 0, e.stream>>>(e.n, (const TW*)e.P, e.ldu, w, zpart,
+                                                                                e.sp, do_sketch)));
+  return G2;
+}
+
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
   const int prec = prec_override >= 0 ? prec_override : e.prec;
+  if (e.cb) {
+    if (prec == 0) return spmv_cb_t<double, double, double>(e, e.val_cb, (const double*)x, (double*)w, zpart, do_sketch);
+    if (prec == 1) return spmv_cb_t<float, float, float>(e, e.val32_cb, (const float*)x, (float*)w, zpart, do_sketch);
+    return spmv_cb_t<bf16_t, float, float>(e, e.val32_cb, (const bf16_t*)x, (float*)w, zpart, do_sketch);
+  }
   int G = grid_for(e.ntiles, 8, kMaxG);
   if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the tile mapping)
   dim3 grid(G), block(512);
@@ -629,7 +714,7 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
 }
 
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob) {
-  dim3 grid((e.sp.d + 31) / 32, 2), block(1024);
+  dim3 grid((e.sp.d + kRedBins - 1) / kRedBins, 2), block(kRedBins * kRedSl);
   k_reduce<<<grid, block, 0, e.stream>>>(pa, pb, Ga, Gb, e.sp.d, oa, ob);
 }
 

@@ -54,6 +54,13 @@ struct Conv<bf16_t> {
   }
 };
 
+constexpr int kCb = 8;  // column blocks of the column-blocked SpMV (one per XCD)
+
+// First wave tile of each column block (tiles of block c are off[c] .. off[c+1]-1).
+struct CbTiles {
+  int off[kCb + 1];
+};
+
 struct SketchP {
   int d;
   int zeta;

@@ -21,6 +21,15 @@ struct LaunchEnv {
   int64_t ldu;         // basis leading dimension (n rounded up to 128; padding rows are zero)
   int sp_kind;         // 0 Gaussian, 1 sparse-sign
   SketchP sp;
+  // column-blocked SpMV (used when cb = 1): kCb CSR blocks with global offsets
+  int cb = 0;
+  const int* rp_cb = nullptr;       // kCb x (n+1) row pointers into col_cb / val_cb
+  const int* col_cb = nullptr;
+  const double* val_cb = nullptr;
+  const float* val32_cb = nullptr;  // mixed precision only
+  const int* tiles_cb = nullptr;    // wave tiles of all blocks, block after block
+  CbTiles cbt{};
+  void* P = nullptr;                // kCb partial vectors, leading dimension ldu (FP64 or FP32)
   int vbytes() const { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 };
 

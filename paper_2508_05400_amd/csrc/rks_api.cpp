@@ -72,6 +72,11 @@ struct rks_ctx {
   double *S = nullptr, *B = nullptr, *cs = nullptr, *coef = nullptr, *z = nullptr, *sr = nullptr;
   double *zpart = nullptr, *spart = nullptr, *scal = nullptr, *Yd = nullptr, *u0tmp = nullptr;
   double* E = nullptr;  // S^T S - I, (m+1) x (m+1), leading dimension m+1
+  // column-blocked SpMV layout (when chosen): blocks of A, their tiles, partial vectors
+  int *rp_cb = nullptr, *col_cb = nullptr, *tiles_cb = nullptr;
+  double* val_cb = nullptr;
+  float* val32_cb = nullptr;
+  void* P = nullptr;
   double *Xr = nullptr, *ax1 = nullptr, *ax2 = nullptr, *rpart = nullptr;  // residual scratch (lazy)
   // pinned host mirrors
   double *hB = nullptr, *hS = nullptr, *hcs = nullptr, *hY = nullptr, *hE = nullptr;
@@ -722,6 +727,7 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U_lo, c->U64, c->w, c->S, c->B, c->cs,
                  c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->E,
+                 c->rp_cb, c->col_cb, c->tiles_cb, c->val_cb, c->val32_cb, c->P,
                  c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -751,6 +757,7 @@ void rks_opts_default(rks_opts* o) {
   o->resid_tol = 0.0;
   o->refine = 1;
   o->refine_tol = 0.0;
+  o->spmv_layout = RKS_SPMV_AUTO;
 }
 
 const char* rks_strerror(int code) { return code_str(code); }
@@ -777,8 +784,8 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
-      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0))
-    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol or refine_tol");
+      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2)
+    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol, refine_tol or spmv_layout");
 
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");
@@ -815,29 +822,82 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     colsum[col[e]] += std::fabs(val[e]);
   }
   c->normA1 = n ? *std::max_element(colsum.begin(), colsum.end()) : 0.0;
-  // wave tiles: <= 64 rows and <= 512 nonzeros, or one long row
-  std::vector<int32_t> tiles;
-  tiles.push_back(0);
-  for (int64_t r = 0; r < n;) {
-    const int64_t s = r;
-    int64_t acc = 0;
-    if (rp[r + 1] - rp[r] > rks::kTileNnz) {
-      ++r;
-    } else {
-      while (r < n && r - s < rks::kTileRows && acc + (rp[r + 1] - rp[r]) <= rks::kTileNnz) {
-        acc += rp[r + 1] - rp[r];
+  // wave tiles: <= 64 rows and <= 512 nonzeros, or one long row;
+  // descriptors {first row, rows, first nonzero, nonzeros} appended to out
+  auto build_tiles = [&](const int32_t* rpx, std::vector<int32_t>& out) {
+    for (int64_t r = 0; r < n;) {
+      const int64_t s0 = r;
+      int64_t acc = 0;
+      if (rpx[r + 1] - rpx[r] > rks::kTileNnz) {
         ++r;
+      } else {
+        while (r < n && r - s0 < rks::kTileRows && acc + (rpx[r + 1] - rpx[r]) <= rks::kTileNnz) {
+          acc += rpx[r + 1] - rpx[r];
+          ++r;
+        }
+      }
+      out.push_back((int32_t)s0);
+      out.push_back((int32_t)(r - s0));
+      out.push_back(rpx[s0]);
+      out.push_back(rpx[r] - rpx[s0]);
+    }
+  };
+  std::vector<int32_t> tdesc;
+  build_tiles(rp.data(), tdesc);
+  const int ntiles = (int)(tdesc.size() / 4);
+  // column-blocked layout for operators whose rows gather x from everywhere
+  bool use_cb = o.spmv_layout == RKS_SPMV_COLUMN_BLOCKS;
+  if (o.spmv_layout == RKS_SPMV_AUTO && n >= (1 << 20)) {
+    std::vector<int64_t> spans;
+    const int step = std::max(1, ntiles / 4096);
+    for (int t = 0; t < ntiles; t += step) {
+      const int64_t e0 = tdesc[4 * t + 2], ne = tdesc[4 * t + 3];
+      if (ne == 0) continue;
+      int32_t lo = col[e0], hi = col[e0];
+      for (int64_t e = e0; e < e0 + ne; ++e) {
+        lo = std::min(lo, col[e]);
+        hi = std::max(hi, col[e]);
+      }
+      spans.push_back(hi - lo);
+    }
+    if (!spans.empty()) {
+      std::nth_element(spans.begin(), spans.begin() + spans.size() / 2, spans.end());
+      use_cb = spans[spans.size() / 2] > n / 4;
+    }
+  }
+  std::vector<int32_t> rp_cb, col_cb, tdesc_cb;
+  std::vector<double> val_cb;
+  rks::CbTiles cbt{};
+  if (use_cb) {
+    const int64_t bw = (n + rks::kCb - 1) / rks::kCb;  // columns per block
+    rp_cb.assign((size_t)rks::kCb * (n + 1), 0);
+    for (int64_t r = 0; r < n; ++r)  // count, then exclusive prefix over (block, row)
+      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) rp_cb[(size_t)(col[e] / bw) * (n + 1) + r] += 1;
+    int64_t pos = 0;
+    for (int cb = 0; cb < rks::kCb; ++cb)
+      for (int64_t r = 0; r <= n; ++r) {
+        int32_t& slot = rp_cb[(size_t)cb * (n + 1) + r];
+        const int32_t cnt = (r < n) ? slot : 0;
+        slot = (int32_t)pos;
+        pos += cnt;
+      }
+    col_cb.resize(nnz);
+    val_cb.resize(nnz);
+    std::vector<int32_t> fill(rks::kCb, 0);
+    for (int64_t r = 0; r < n; ++r) {
+      for (int cb = 0; cb < rks::kCb; ++cb) fill[cb] = rp_cb[(size_t)cb * (n + 1) + r];
+      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {  // columns stay increasing inside each block row
+        const int cb = (int)(col[e] / bw);
+        col_cb[fill[cb]] = col[e];
+        val_cb[fill[cb]] = val[e];
+        ++fill[cb];
       }
     }
-    tiles.push_back((int32_t)r);
-  }
-  const int ntiles = (int)tiles.size() - 1;
-  std::vector<int32_t> tdesc((size_t)ntiles * 4);
-  for (int t = 0; t < ntiles; ++t) {
-    tdesc[4 * t + 0] = tiles[t];
-    tdesc[4 * t + 1] = tiles[t + 1] - tiles[t];
-    tdesc[4 * t + 2] = rp[tiles[t]];
-    tdesc[4 * t + 3] = rp[tiles[t + 1]] - rp[tiles[t]];
+    for (int cb = 0; cb < rks::kCb; ++cb) {
+      cbt.off[cb] = (int)(tdesc_cb.size() / 4);
+      build_tiles(&rp_cb[(size_t)cb * (n + 1)], tdesc_cb);
+    }
+    cbt.off[rks::kCb] = (int)(tdesc_cb.size() / 4);
   }
   c->vbytes = (o.precision == RKS_PREC_FP64) ? 8 : (o.precision == RKS_PREC_V32 ? 4 : 2);
   c->wbytes = (o.precision == RKS_PREC_FP64) ? 8 : 4;
@@ -865,6 +925,14 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->val, nnz * 8);
   if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nnz * 4);
   dm((void**)&c->tiles, tdesc.size() * 4);
+  if (use_cb) {
+    dm((void**)&c->rp_cb, rp_cb.size() * 4);
+    dm((void**)&c->col_cb, (size_t)nnz * 4);
+    dm((void**)&c->val_cb, (size_t)nnz * 8);
+    if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32_cb, (size_t)nnz * 4);
+    dm((void**)&c->tiles_cb, tdesc_cb.size() * 4);
+    dm(&c->P, (size_t)rks::kCb * c->ldu * 8);
+  }
   dm(&c->U_lo, (size_t)c->ldu * (m + 1) * c->vbytes);
   c->U = c->U_lo;
   dm(&c->w, (size_t)c->ldu * 8);
@@ -904,6 +972,16 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     cp(c->val32, v32.data(), nnz * 4);
   }
   cp(c->tiles, tdesc.data(), tdesc.size() * 4);
+  if (use_cb) {
+    cp(c->rp_cb, rp_cb.data(), rp_cb.size() * 4);
+    cp(c->col_cb, col_cb.data(), (size_t)nnz * 4);
+    cp(c->val_cb, val_cb.data(), (size_t)nnz * 8);
+    if (c->val32_cb) {
+      std::vector<float> v32(val_cb.begin(), val_cb.end());
+      cp(c->val32_cb, v32.data(), (size_t)nnz * 4);
+    }
+    cp(c->tiles_cb, tdesc_cb.data(), tdesc_cb.size() * 4);
+  }
   if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
   // padding rows of U and w stay zero for the whole life of the context
   if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
@@ -923,6 +1001,16 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.val32 = c->val32;
   e.tiles = c->tiles;
   e.ntiles = ntiles;
+  if (use_cb) {
+    e.cb = 1;
+    e.rp_cb = c->rp_cb;
+    e.col_cb = c->col_cb;
+    e.val_cb = c->val_cb;
+    e.val32_cb = c->val32_cb;
+    e.tiles_cb = c->tiles_cb;
+    e.cbt = cbt;
+    e.P = c->P;
+  }
   e.ldu = c->ldu;
   e.sp_kind = o.sketch_kind;
   e.sp.d = d;
@@ -993,6 +1081,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   st->restarts = p1.restarts;
   st->locked = c->q;
   st->keff = c->keff;
+  st->spmv_layout = c->env.cb ? RKS_SPMV_COLUMN_BLOCKS : RKS_SPMV_ROWS;
   st->max_est = p1.maxest;
   st->t_host = p1.thost;
   st->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -60,12 +60,13 @@ def test_sketch_parity(lib, cuda, case):
         P.rks_destroy(ctx)
 
 
+@pytest.mark.parametrize("layout", ["rows", "column_blocks"])
 @pytest.mark.parametrize("case", sorted(SMALL))
-def test_spmv_sketch_parity(lib, cuda, case):
+def test_spmv_sketch_parity(lib, cuda, case, layout):
     mk, kind, d = SMALL[case]
     A = mk()
     ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 4, 20, d, "LM", 1e-10,
-                       P.rks_opts_default(sketch_kind=kind, sketch_seed=5))
+                       P.rks_opts_default(sketch_kind=kind, sketch_seed=5, spmv_layout=layout))
     try:
         x = start_vector_normal(A.n, 9)
         w = cuda.zeros(A.n, dtype=cuda.float64, device="cuda")
@@ -90,13 +91,13 @@ ARN = {
 }
 
 
-@pytest.mark.parametrize("case", sorted(ARN))
-def test_arnoldi_parity(lib, cuda, case):
+@pytest.mark.parametrize("case,layout", [(c, "rows") for c in sorted(ARN)] + [("powerlaw-5003", "column_blocks")])
+def test_arnoldi_parity(lib, cuda, case, layout):
     """First extension (Algorithm 2 from one column) vs the oracle: B, S, U."""
     mk, kind, k, m, d = ARN[case]
     A = mk()
     ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
-                       P.rks_opts_default(sketch_kind=kind, sketch_seed=2, start_seed=1))
+                       P.rks_opts_default(sketch_kind=kind, sketch_seed=2, start_seed=1, spmv_layout=layout))
     try:
         P.rks_arnoldi(ctx, None)          # seeded start generated on the device
         B = np.zeros((m + 1, m), order="F")
