@@ -140,8 +140,9 @@ def main():
     ap.add_argument("--profile-every", type=int, default=7,
                     help="time the kernels of every P-th Arnoldi step with HIP events (event records "
                          "cost a few microseconds each, so timing every launch would slow the solve)")
-    ap.add_argument("--compare", default="", help="comma list of extra basis precisions to time on the "
-                    "same workload after the main run (e.g. fp32,bf16); reported under 'precisions'")
+    ap.add_argument("--compare", default="", help="comma list of extra runs on the same workload after the "
+                    "main run: basis precisions (fp32, bf16) and/or ks_cgs2 (deterministic Krylov-Schur); "
+                    "reported under 'precisions'")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block "
@@ -243,9 +244,13 @@ def main():
     }
     extra = {}
     for prec in [p for p in args.compare.split(",") if p]:
+        # a precision (fp32, bf16: mixed precision with FP64 refinement), or
+        # ks_cgs2: deterministic Krylov-Schur with an FP64 basis (the paper's comparison)
+        method = "ks_cgs2" if prec == "ks_cgs2" else "rks"
         with P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
-                               start_seed=cfg["start_seed"], precision=prec, lock=int(cfg["lock"]),
+                               start_seed=cfg["start_seed"], precision="fp64" if method == "ks_cgs2" else prec,
+                               method=method, lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), resid_tol=args.resid_tol,
                                profile=0 if args.no_profile else args.profile_every, stream=stream) as s2:
             s2.solve()
@@ -264,6 +269,7 @@ def main():
                            "restarts_low_precision": st2["restarts_lo"], "refined": bool(st2["refined"]),
                            "low_precision_phase_s": st2["t_lo"], "max_resid": float(np.max(res2)),
                            "converged": bool(st2["converged"]), "loop_gbs": _loop_gbs(st2),
+                           "step_avg_us": st2["t_step"] / max(st2["n_timed_whole"], 1) * 1e6,
                            "vs_fp64_run": _error_vs(lam, X64, lam2, X2)}
     if extra:
         out["precisions"] = extra

@@ -65,6 +65,14 @@ typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2 } rks_pre
  * median column span of a row tile exceeds n/4. */
 typedef enum { RKS_SPMV_AUTO = 0, RKS_SPMV_ROWS = 1, RKS_SPMV_COLUMN_BLOCKS = 2 } rks_spmv_layout;
 
+/* RKS: randomized Krylov-Schur (Algorithm 1 with Algorithm 2).  KS_CGS2:
+ * deterministic Krylov-Schur, the paper's point of comparison (Section 5):
+ * the same restart on the same kernels, with the Euclidean inner product
+ * and classical Gram-Schmidt applied twice in each Arnoldi step (four
+ * passes over the basis instead of one); FP64 basis only; d and the sketch
+ * options are ignored. */
+typedef enum { RKS_METHOD_RKS = 0, RKS_METHOD_KS_CGS2 = 1 } rks_method;
+
 /* Square CSR matrix: row_ptr[n+1] (monotone, row_ptr[0] = 0), col[nnz]
  * (in [0, n), strictly increasing inside a row), val[nnz] FP64.
  * on_device = 0: host arrays; 1: device arrays.  Copied by rks_create. */
@@ -102,6 +110,7 @@ typedef struct {
                             (it also stops when its estimates reach it);
                             0 = 1e-6 for an FP32 basis, 1e-3 for BF16 */
   int32_t spmv_layout;   /* rks_spmv_layout, default AUTO */
+  int32_t method;        /* rks_method, default RKS */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */

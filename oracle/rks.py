@@ -322,3 +322,19 @@ def eigpairs(A, Uk, lam, Y, est, which, normA1):
 def rks(A, k, m, d, which="LM", tol=1e-10, u0=None, **kw):
     """Run the oracle rKS to convergence (or max_restarts); see RKSOracle."""
     return RKSOracle(A, k, m, d, which, tol, **kw).run(u0)
+
+
+def ks_oracle(A, k, m, which="LM", tol=1e-10, **kw):
+    """Deterministic Krylov-Schur, the paper's point of comparison: the same
+    algorithm with Omega = I, so the sketched inner product is the Euclidean
+    one, S = U, and the least squares h = U^+ w is the orthogonal projection
+    (the special case noted with Algorithm 2; pinned against textbook
+    Arnoldi in the oracle's tests)."""
+    if hasattr(A, "row_ptr"):
+        A = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    n = A.shape[0]
+    o = RKSOracle(A, k, m, m + 1, which, tol, **kw)
+    o.Om = sp.identity(n, format="csr")
+    o.d = n
+    o.S = np.zeros((n, m + 1))
+    return o

@@ -18,6 +18,7 @@ WHICH = {"LM": 0, "SM": 1, "LR": 2, "SR": 3}
 SKETCH = {"gauss": 0, "sparse": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "v32": 1, "bf16": 2, "vbf16": 2}
 SPMV_LAYOUT = {"auto": 0, "rows": 1, "column_blocks": 2}
+METHOD = {"rks": 0, "ks_cgs2": 1}
 
 
 class RksCsr(ctypes.Structure):
@@ -32,7 +33,8 @@ class RksOpts(ctypes.Structure):
                 ("lock", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("whiten_tol", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("resid_tol", ctypes.c_double), ("refine", ctypes.c_int32),
-                ("refine_tol", ctypes.c_double), ("spmv_layout", ctypes.c_int32)]
+                ("refine_tol", ctypes.c_double), ("spmv_layout", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 class RksStats(ctypes.Structure):
@@ -160,6 +162,8 @@ def rks_opts_default(**kw) -> RksOpts:
             v = PRECISION[v]
         if k == "spmv_layout" and isinstance(v, str):
             v = SPMV_LAYOUT[v]
+        if k == "method" and isinstance(v, str):
+            v = METHOD[v]
         if k == "stream" and v is not None and not isinstance(v, int):
             v = int(v.cuda_stream)
         setattr(o, k, v)

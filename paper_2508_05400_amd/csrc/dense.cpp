@@ -483,7 +483,7 @@ int swap_blocks(int n, double* T, int ldt, double* Z, int ldz, int p, int n1, in
   const double thresh = std::max(20.0 * kUlp * dnorm, kSafmin);
   if (low > thresh) return 1;
   // accept: apply Q to the full T (rows p..p+nd-1 right part, columns above) and Z
-  std::vector<double> tmp(std::max(n, 1) * 4);
+  double tmp[4];
   for (int j = p + nd; j < n; ++j) {
     for (int r = 0; r < nd; ++r) {
       double s = 0.0;

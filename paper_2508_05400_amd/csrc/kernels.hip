@@ -25,8 +25,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // Scatter v * Omega[:, i] into the block's LDS bins (unscaled).
+// KIND 0: Gaussian Omega; 1: sparse-sign Omega; 2: no sketch (deterministic
+// Krylov-Schur, whose kernels accumulate a squared norm instead).
 template <int KIND>
 __device__ __forceinline__ void sketch_add(double* bins, uint64_t i, double v, const SketchP& sp) {
+  if (KIND == 2) return;
   if (KIND == 1) {
     int rows[8];
     float sg[8];
@@ -471,6 +474,7 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
   bins_zero(bins, sp.d);
   __syncthreads();
   const double ws = coef[ncol];
+  double nrm = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < npk; g += stride) {
     const int64_t i0 = g * V;
@@ -509,11 +513,116 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
     for (int r = 0; r < V; ++r) o.v[r] = Conv<TV>::st(a[r]);
     __builtin_nontemporal_store(o.raw, (u32x4*)(unew + i0));
 #pragma unroll
-    for (int r = 0; r < V; ++r)
-      if (i0 + r < n) sketch_add<KIND>(bins, (uint64_t)(i0 + r), Conv<TV>::ld(o.v[r]), sp);
+    for (int r = 0; r < V; ++r) {
+      if (i0 + r >= n) continue;
+      const double v = Conv<TV>::ld(o.v[r]);
+      if (KIND == 2) nrm += v * v;
+      else sketch_add<KIND>(bins, (uint64_t)(i0 + r), v, sp);
+    }
+  }
+  if (KIND == 2) {  // Euclidean inner product (deterministic Krylov-Schur): ||u~||^2 partial
+    nrm = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&bins[0], nrm);
   }
   __syncthreads();
   bins_store(bins, spart, sp.d, sp.scale);
+}
+
+// Sums over the wave of eight values per lane: lane L returns the total of
+// v[(L >> 3) & 7] (a butterfly that halves the values carried at each of the
+// first three steps: 10 shuffles instead of 48).
+__device__ __forceinline__ double wave_sum8(const double v[8], int lane) {
+  double a[4], b[2];
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = h32 ? v[i + 4] : v[i], send = h32 ? v[i] : v[i + 4];
+    a[i] = keep + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = h16 ? a[i + 2] : a[i], send = h16 ? a[i] : a[i + 2];
+    b[i] = keep + __shfl_xor(send, 16);
+  }
+  double c = (h8 ? b[1] : b[0]) + __shfl_xor(h8 ? b[0] : b[1], 8);
+  c += __shfl_xor(c, 4);
+  c += __shfl_xor(c, 2);
+  c += __shfl_xor(c, 1);
+  return c;
+}
+
+// Partial sums (one row of ncol values per block) of U(:, l)^T x, l < ncol,
+// for the Euclidean Gram-Schmidt of deterministic Krylov-Schur.  Each thread
+// owns one 16-byte packet of rows (as in k_update); columns go in groups of
+// eight with one wave_sum8 per group.
+template <typename TV, typename TX>
+__global__ __launch_bounds__(1024) void k_dots(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U,
+                                               int64_t ldu, const TX* __restrict__ x, double* __restrict__ part) {
+  constexpr int V = 16 / sizeof(TV);
+  __shared__ double bins[kMaxM + 8];
+  for (int b = threadIdx.x; b < ncol; b += blockDim.x) bins[b] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gs = (int64_t)blockIdx.x * blockDim.x; gs < npk; gs += stride) {  // block-uniform trip count
+    const int64_t g = gs + threadIdx.x;
+    const bool act = g < npk;
+    const int64_t i0 = g * V;
+    double xv[V];
+#pragma unroll
+    for (int r = 0; r < V; ++r) xv[r] = (act && i0 + r < n) ? Conv<TX>::ld(x[i0 + r]) : 0.0;
+    const TV* col0 = U + i0;
+    for (int l0 = 0; l0 < ncol; l0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        v[q] = 0.0;
+        if (act && l0 + q < ncol) {
+          Pack16<TV> p;
+          p.raw = __builtin_nontemporal_load((const u32x4*)(col0 + (int64_t)(l0 + q) * ldu));
+#pragma unroll
+          for (int r = 0; r < V; ++r) v[q] += Conv<TV>::ld(p.v[r]) * xv[r];
+        }
+      }
+      const double sv = wave_sum8(v, lane);
+      const int c = l0 + ((lane >> 3) & 7);
+      if ((lane & 7) == 0 && c < ncol) atomicAdd(&bins[c], sv);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < ncol; b += blockDim.x) part[(size_t)blockIdx.x * ncol + b] = bins[b];
+}
+
+// Coefficients of one classical Gram-Schmidt pass from y_raw = sum of the
+// stored columns' products with the input (scaled by `scale`):
+// y_l = cs_l y_raw_l scale, coef_l = cs_l y_l, coef_ncol = scale; h += y.
+__global__ void k_ks_coef(int ncol, const double* __restrict__ cs, const double* __restrict__ yraw, double scale_in,
+                          const double* __restrict__ scale_ptr, double* __restrict__ coef, double* __restrict__ h,
+                          int accumulate) {
+  const double sc = scale_ptr ? *scale_ptr * scale_in : scale_in;
+  for (int l = threadIdx.x; l < ncol; l += blockDim.x) {
+    const double y = cs[l] * yraw[l] * sc;
+    coef[l] = cs[l] * y;
+    h[l] = accumulate ? h[l] + y : y;
+  }
+  if (threadIdx.x == 0) coef[ncol] = sc;
+}
+
+// Close step t of deterministic Krylov-Schur: B(0:t, t) = h, B(t+1, t) = beta
+// = ||u~|| (from the squared norm), cs[t+1] = 1 / beta; breakdown test.
+__global__ void k_ks_finalize(int t, const double* __restrict__ h, const double* __restrict__ nrm2, double* __restrict__ B,
+                              int ldb, double* __restrict__ cs, int* __restrict__ flags, double bd_rel) {
+  double hn = 0.0;
+  for (int l = threadIdx.x; l <= t; l += blockDim.x) {
+    B[l + (size_t)t * ldb] = h[l];
+  }
+  if (threadIdx.x == 0) {
+    for (int l = 0; l <= t; ++l) hn += h[l] * h[l];
+    const double beta = sqrt(*nrm2);
+    B[t + 1 + (size_t)t * ldb] = beta;
+    cs[t + 1] = 1.0 / beta;
+    if (!(beta > bd_rel * sqrt(hn + beta * beta)) && flags[0] == 0) flags[0] = t + 1;
+  }
 }
 
 // First column: u0 (device FP64) or the seeded N(0,1) start, stored in the
@@ -526,6 +635,7 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
   bins_zero(bins, sp.d);
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double nrm = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double v;
     if (u0) {
@@ -536,7 +646,13 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
     }
     const TV st = Conv<TV>::st(v);
     if (store) u[i] = st;
-    sketch_add<KIND>(bins, (uint64_t)i, Conv<TV>::ld(st), sp);
+    const double vs = Conv<TV>::ld(st);
+    if (KIND == 2) nrm += vs * vs;
+    else sketch_add<KIND>(bins, (uint64_t)i, vs, sp);
+  }
+  if (KIND == 2) {
+    nrm = wave_sum(nrm);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&bins[0], nrm);
   }
   __syncthreads();
   bins_store(bins, spart, sp.d, sp.scale);
@@ -667,6 +783,9 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   do {                               \
     if ((kind) == 1) {               \
       constexpr int KIND = 1;        \
+      __VA_ARGS__;                   \
+    } else if ((kind) == 2) {        \
+      constexpr int KIND = 2;        \
       __VA_ARGS__;                   \
     } else {                         \
       constexpr int KIND = 0;        \
@@ -828,6 +947,43 @@ int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const d
 
 void launch_scale(const LaunchEnv& e, double* x, double s) {
   k_scale<<<grid_for(e.n, 256, kMaxG), 256, 0, e.stream>>>(e.n, x, s);
+}
+
+int launch_dots(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* x, int x_is_basis, double* part) {
+  const int V = 16 / e.vbytes();
+  const int64_t npk = (e.n + V - 1) / V;
+  const int G = grid_for(npk, 1024, kMaxG);
+  if (e.prec == 0) {
+    k_dots<double, double><<<G, 1024, 0, e.stream>>>(e.n, npk, ncol, (const double*)U, ldu, (const double*)x, part);
+  } else if (e.prec == 1) {
+    k_dots<float, float><<<G, 1024, 0, e.stream>>>(e.n, npk, ncol, (const float*)U, ldu, (const float*)x, part);
+  } else if (x_is_basis) {
+    k_dots<bf16_t, bf16_t><<<G, 1024, 0, e.stream>>>(e.n, npk, ncol, (const bf16_t*)U, ldu, (const bf16_t*)x, part);
+  } else {
+    k_dots<bf16_t, float><<<G, 1024, 0, e.stream>>>(e.n, npk, ncol, (const bf16_t*)U, ldu, (const float*)x, part);
+  }
+  return G;
+}
+
+void launch_reduce_len(const LaunchEnv& e, const double* pa, int Ga, double* oa, int len) {
+  dim3 grid((len + kRedBins - 1) / kRedBins, 1), block(kRedBins * kRedSl);
+  k_reduce<<<grid, block, 0, e.stream>>>(pa, nullptr, Ga, 0, len, oa, nullptr);
+}
+
+void launch_ks_coef(const LaunchEnv& e, int ncol, const double* cs, const double* yraw, double scale,
+                    const double* scale_ptr, double* coef, double* h, int accumulate) {
+  k_ks_coef<<<1, 256, 0, e.stream>>>(ncol, cs, yraw, scale, scale_ptr, coef, h, accumulate);
+}
+
+__global__ void k_ks_start(const double* __restrict__ nrm2, double* __restrict__ cs) {
+  if (threadIdx.x == 0) cs[0] = 1.0 / sqrt(*nrm2);
+}
+
+void launch_ks_start(const LaunchEnv& e, const double* nrm2, double* cs) { k_ks_start<<<1, 64, 0, e.stream>>>(nrm2, cs); }
+
+void launch_ks_finalize(const LaunchEnv& e, int t, const double* h, const double* nrm2, double* B, int ldb, double* cs,
+                        int* flags, double bd_rel) {
+  k_ks_finalize<<<1, 256, 0, e.stream>>>(t, h, nrm2, B, ldb, cs, flags, bd_rel);
 }
 
 void launch_copy16(hipStream_t stream, const void* src, void* dst, int64_t packets) {

@@ -51,5 +51,15 @@ int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const d
 void launch_scale(const LaunchEnv& e, double* x, double s);
 void launch_fill(const LaunchEnv& e, int64_t len, double* x, double v);
 void launch_copy16(hipStream_t stream, const void* src, void* dst, int64_t packets);
+// Deterministic Krylov-Schur (Euclidean classical Gram-Schmidt, twice):
+// partials of U(:, 0:ncol)^T x (returns the number of partial rows), their sum,
+// the coefficients of one pass, and the closing of a step.
+int launch_dots(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* x, int x_is_basis, double* part);
+void launch_reduce_len(const LaunchEnv& e, const double* pa, int Ga, double* oa, int len);
+void launch_ks_coef(const LaunchEnv& e, int ncol, const double* cs, const double* yraw, double scale,
+                    const double* scale_ptr, double* coef, double* h, int accumulate);
+void launch_ks_finalize(const LaunchEnv& e, int t, const double* h, const double* nrm2, double* B, int ldb, double* cs,
+                        int* flags, double bd_rel);
+void launch_ks_start(const LaunchEnv& e, const double* nrm2, double* cs);
 
 }  // namespace rks

@@ -72,6 +72,8 @@ struct rks_ctx {
   double *S = nullptr, *B = nullptr, *cs = nullptr, *coef = nullptr, *z = nullptr, *sr = nullptr;
   double *zpart = nullptr, *spart = nullptr, *scal = nullptr, *Yd = nullptr, *u0tmp = nullptr;
   double* E = nullptr;  // S^T S - I, (m+1) x (m+1), leading dimension m+1
+  double* kpart = nullptr;  // deterministic Krylov-Schur: partial rows of U^T x (kMaxG x (m+1))
+  bool ks = false;          // deterministic Krylov-Schur (RKS_METHOD_KS_CGS2)
   // column-blocked SpMV layout (when chosen): blocks of A, their tiles, partial vectors
   int *rp_cb = nullptr, *col_cb = nullptr, *tiles_cb = nullptr;
   double* val_cb = nullptr;
@@ -228,6 +230,60 @@ int arnoldi_step(rks_ctx* c, int t) {
   return RKS_OK;
 }
 
+// ---- one Arnoldi step of deterministic Krylov-Schur ------------------------
+// Classical Gram-Schmidt twice with the Euclidean inner product: two passes
+// compute U^T x, two apply x - U y; the basis columns stay unnormalised with
+// their scales in cs, as in the randomized step.
+int arnoldi_step_ks(rks_ctx* c, int t) {
+  const auto& e = c->env;
+  bool timed = false, whole = false;
+  if (c->o.profile > 0 && c->st && (c->step_count % c->o.profile) == 0) {
+    if ((c->step_count / c->o.profile) % 2 == 0) timed = true;
+    else whole = true;
+  }
+  ++c->step_count;
+  Prof pw(c, CAT_STEP, whole);
+  const int ncol = t + 1;
+  void* unew = basis_col(c, t + 1);
+  {
+    Prof p(c, CAT_SPMV, timed);
+    rks::launch_spmv_sketch(e, basis_col(c, t), c->w, nullptr, 0, -1);
+  }
+  {
+    Prof p(c, CAT_UPDATE, timed);
+    int G = rks::launch_dots(e, ncol, c->U, c->ldu, c->w, 0, c->kpart);
+    rks::launch_reduce_len(e, c->kpart, G, c->z, ncol);
+    rks::launch_ks_coef(e, ncol, c->cs, c->z, 1.0, c->cs + t, c->coef, c->sr, 0);
+    rks::launch_update(e, ncol, c->U, c->ldu, c->w, c->coef, unew, c->spart);
+    G = rks::launch_dots(e, ncol, c->U, c->ldu, unew, 1, c->kpart);
+    rks::launch_reduce_len(e, c->kpart, G, c->z, ncol);
+    rks::launch_ks_coef(e, ncol, c->cs, c->z, 1.0, nullptr, c->coef, c->sr, 1);
+    const int Gs = rks::launch_update(e, ncol, c->U, c->ldu, unew, c->coef, unew, c->spart);
+    rks::launch_reduce_len(e, c->spart, Gs, c->scal + 2, 1);
+    rks::launch_ks_finalize(e, t, c->sr, c->scal + 2, c->B, c->m + 1, c->cs, c->flags, kBreakdownRel);
+  }
+  if (c->st) {
+    const double bs = spmv_bytes(c), bu = (4.0 * (t + 1) + 6.0) * c->n * 8.0;
+    c->st->n_spmv += 1;
+    c->st->bytes_spmv += bs;
+    c->st->n_update += 1;
+    c->st->bytes_update += bu;
+    c->st->matvecs += 1;
+    if (timed) {
+      c->st->n_timed_steps += 1;
+      c->st->bytes_timed_spmv += bs;
+      c->st->bytes_timed_update += bu;
+    }
+    if (whole) {
+      c->st->n_timed_whole += 1;
+      c->st->bytes_timed_whole += bs + bu;
+    }
+  }
+  c->pending = 0;
+  c->j = t + 1;
+  return RKS_OK;
+}
+
 int finalize_last(rks_ctx* c) {
   const auto& e = c->env;
   rks::launch_reduce(e, nullptr, 0, c->spart, c->G_s, c->z, c->sr);
@@ -239,10 +295,10 @@ int finalize_last(rks_ctx* c) {
 
 int extend(rks_ctx* c) {
   for (int t = c->j; t < c->m; ++t) {
-    int r = arnoldi_step(c, t);
+    int r = c->ks ? arnoldi_step_ks(c, t) : arnoldi_step(c, t);
     if (r) return r;
   }
-  finalize_last(c);
+  if (!c->ks) finalize_last(c);
   HIPCHK(c, hipGetLastError());
   return RKS_OK;
 }
@@ -265,8 +321,12 @@ int start(rks_ctx* c, const double* u0, int u0_on_device) {
   HIPCHK(c, hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->env.stream));
   HIPCHK(c, hipMemsetAsync(c->scal, 0, sizeof(double) * 4, c->env.stream));
   c->G_s = rks::launch_init(c->env, basis_col(c, 0), u0d, (uint32_t)s, (uint32_t)(s >> 32), c->spart, 1, -1);
+  if (c->ks) {  // Euclidean normalisation of the start
+    rks::launch_reduce_len(c->env, c->spart, c->G_s, c->scal + 2, 1);
+    rks::launch_ks_start(c->env, c->scal + 2, c->cs);
+  }
   HIPCHK(c, hipGetLastError());
-  c->pending = 1;
+  c->pending = c->ks ? 0 : 1;
   c->j = 0;
   c->q = 0;
   c->keff = 0;
@@ -367,7 +427,7 @@ int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscal
     }
   dev = std::sqrt(dev);
   *whitened = 0;
-  if (dev > c->o.whiten_tol) {
+  if (!c->ks && dev > c->o.whiten_tol) {  // deterministic Krylov-Schur keeps no sketch
     std::vector<double> Qs((size_t)d * ke), R((size_t)ke * ke), Ri((size_t)ke * ke);
     rks::householder_qr(d, ke, Sn.data(), d, Qs.data(), d, R.data(), ke);
     rks::upper_tri_inverse(ke, R.data(), ke, Ri.data(), ke);
@@ -476,7 +536,7 @@ int rotate_basis(rks_ctx* c, int in0, int min, int out0, int kout, double xscale
 int push_state(rks_ctx* c) {
   auto stm = c->env.stream;
   // E = S^T S - I of the contracted sketch (columns 0..keff), exactly symmetric
-  const int d = c->d, ld = c->m + 1, nc = c->keff + 1;
+  const int d = c->d, ld = c->m + 1, nc = c->ks ? 0 : c->keff + 1;
   std::fill(c->hE, c->hE + (size_t)ld * ld, 0.0);
   for (int j = 0; j < nc; ++j)
     for (int i = 0; i <= j; ++i) {
@@ -726,7 +786,7 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 
 void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U_lo, c->U64, c->w, c->S, c->B, c->cs,
-                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->E,
+                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->E, c->kpart,
                  c->rp_cb, c->col_cb, c->tiles_cb, c->val_cb, c->val32_cb, c->P,
                  c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
@@ -758,6 +818,7 @@ void rks_opts_default(rks_opts* o) {
   o->refine = 1;
   o->refine_tol = 0.0;
   o->spmv_layout = RKS_SPMV_AUTO;
+  o->method = RKS_METHOD_RKS;
 }
 
 const char* rks_strerror(int code) { return code_str(code); }
@@ -784,8 +845,11 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
-      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2)
-    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol, refine_tol or spmv_layout");
+      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
+      o.method > 1)
+    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout or method");
+  if (o.method == RKS_METHOD_KS_CGS2 && o.precision != RKS_PREC_FP64)
+    return fail(nullptr, RKS_EINVAL, "deterministic Krylov-Schur runs with an FP64 basis only");
 
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");
@@ -949,6 +1013,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->Yd, (size_t)(m + 1) * (m + 1) * 8);
   dm((void**)&c->u0tmp, (size_t)n * 8);
   dm((void**)&c->E, (size_t)(m + 1) * (m + 1) * 8);
+  if (o.method == RKS_METHOD_KS_CGS2) dm((void**)&c->kpart, (size_t)rks::kMaxG * (m + 1) * 8);
   hm((void**)&c->hB, (size_t)(m + 1) * m * 8);
   hm((void**)&c->hS, (size_t)d * (m + 1) * 8);
   hm((void**)&c->hcs, (size_t)(m + 1) * 8);
@@ -1012,12 +1077,17 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     e.P = c->P;
   }
   e.ldu = c->ldu;
-  e.sp_kind = o.sketch_kind;
+  c->ks = o.method == RKS_METHOD_KS_CGS2;
+  e.sp_kind = c->ks ? 2 : o.sketch_kind;
   e.sp.d = d;
   e.sp.zeta = o.zeta;
   e.sp.k0 = (uint32_t)o.sketch_seed;
   e.sp.k1 = (uint32_t)(o.sketch_seed >> 32);
   e.sp.scale = (o.sketch_kind == RKS_SKETCH_SPARSE) ? 1.0 / std::sqrt((double)o.zeta) : 1.0 / std::sqrt((double)d);
+  if (c->ks) {  // no sketch: the update and start kernels accumulate one squared norm instead
+    e.sp.d = 1;
+    e.sp.scale = 1.0;
+  }
   *out = c;
   return RKS_OK;
 }
@@ -1117,6 +1187,7 @@ int rks_eigpairs(rks_ctx* c, double* lam_re, double* lam_im, double* X, int32_t 
 
 int rks_sketch(rks_ctx* c, const double* x_dev, double* z_dev) {
   if (!c || !x_dev || !z_dev) return RKS_EINVAL;
+  if (c->ks) return fail(c, RKS_EINVAL, "deterministic Krylov-Schur has no sketch");
   const int G = rks::launch_init(c->env, nullptr, x_dev, 0, 0, c->spart, 0, 0);
   rks::launch_reduce(c->env, c->spart, G, nullptr, 0, z_dev, nullptr);
   HIPCHK(c, hipGetLastError());
@@ -1126,6 +1197,7 @@ int rks_sketch(rks_ctx* c, const double* x_dev, double* z_dev) {
 
 int rks_spmv_sketch(rks_ctx* c, const double* x_dev, double* w_dev, double* z_dev) {
   if (!c || !x_dev || !w_dev || !z_dev) return RKS_EINVAL;
+  if (c->ks) return fail(c, RKS_EINVAL, "deterministic Krylov-Schur has no sketch");
   const int G = rks::launch_spmv_sketch(c->env, x_dev, w_dev, c->zpart, 1, 0);
   rks::launch_reduce(c->env, c->zpart, G, nullptr, 0, z_dev, nullptr);
   HIPCHK(c, hipGetLastError());

@@ -308,3 +308,19 @@ def test_closed_form_condition_numbers_match_dense():
     i1, i2 = np.argsort(w.real), np.argsort(L)
     assert np.max(np.abs(w.real[i1] - L[i2])) < 1e-10 * L.max()
     assert np.max(np.abs(kd[i1] / K[i2] - 1.0)) < 1e-6
+
+
+def test_deterministic_ks_oracle_closed_form():
+    """The deterministic Krylov-Schur oracle (Omega = I) finds the closed-form
+    eigenvalues of the mildly non-normal 2D operator, and its basis is
+    orthonormal in the Euclidean inner product."""
+    from oracle.rks import ks_oracle
+    N, beta = 20, (20.0, 10.0)
+    A = convdiff2d(N, beta)
+    o = ks_oracle(A, 6, 30, "LR", 1e-13, start_seed=1, max_restarts=300)
+    r = o.run()
+    assert r.converged
+    cf = np.sort(convdiff_eigs(N, beta))[::-1][:6]
+    assert np.max(np.abs(np.sort(r.lam.real)[::-1] - cf) / cf) < 1e-10
+    U = o.U[:, :o.keff + 1]
+    assert np.linalg.norm(U.T @ U - np.eye(o.keff + 1)) < 1e-12
