@@ -409,6 +409,41 @@ cplx block_eig(const double* T, int ldt, int p, int s) {
   return cplx(half, std::sqrt(-disc));
 }
 
+// T(p:p+ND, p+ND:n) <- Q^T T(p:p+ND, p+ND:n); T(0:p, p:p+ND) <- T(0:p, p:p+ND) Q;
+// Z(:, p:p+ND) <- Z(:, p:p+ND) Q  (Q is ND x ND with leading dimension 4).  The
+// column updates run over contiguous memory with the ND columns as streams.
+template <int ND>
+void apply_swap(int n, double* T, int ldt, double* Z, int ldz, int p, const double* Q) {
+  for (int j = p + ND; j < n; ++j) {
+    double* c = &T[(size_t)p + (size_t)j * ldt];
+    double x[ND];
+    for (int r = 0; r < ND; ++r) x[r] = c[r];
+    for (int r = 0; r < ND; ++r) {
+      double s = 0.0;
+      for (int q = 0; q < ND; ++q) s += Q[q + 4 * r] * x[q];
+      c[r] = s;
+    }
+  }
+  auto cols = [&](double* M, int ld, int rows) {
+    double* __restrict__ c[ND];
+    for (int j = 0; j < ND; ++j) c[j] = &M[(size_t)(p + j) * ld];
+    double q[ND][ND];
+    for (int a = 0; a < ND; ++a)
+      for (int b = 0; b < ND; ++b) q[a][b] = Q[a + 4 * b];
+    for (int i = 0; i < rows; ++i) {
+      double x[ND];
+      for (int a = 0; a < ND; ++a) x[a] = c[a][i];
+      for (int b = 0; b < ND; ++b) {
+        double s = 0.0;
+        for (int a = 0; a < ND; ++a) s += x[a] * q[a][b];
+        c[b][i] = s;
+      }
+    }
+  };
+  cols(T, ldt, p);
+  cols(Z, ldz, n);
+}
+
 int swap_blocks(int n, double* T, int ldt, double* Z, int ldz, int p, int n1, int n2) {
   if (n1 == 1 && n2 == 1) {
     double t11 = at(T, ldt, p, p), t22 = at(T, ldt, p + 1, p + 1), t12 = at(T, ldt, p, p + 1);
@@ -483,31 +518,8 @@ int swap_blocks(int n, double* T, int ldt, double* Z, int ldz, int p, int n1, in
   const double thresh = std::max(20.0 * kUlp * dnorm, kSafmin);
   if (low > thresh) return 1;
   // accept: apply Q to the full T (rows p..p+nd-1 right part, columns above) and Z
-  double tmp[4];
-  for (int j = p + nd; j < n; ++j) {
-    for (int r = 0; r < nd; ++r) {
-      double s = 0.0;
-      for (int c = 0; c < nd; ++c) s += Q[c + 4 * r] * at(T, ldt, p + c, j);
-      tmp[r] = s;
-    }
-    for (int r = 0; r < nd; ++r) at(T, ldt, p + r, j) = tmp[r];
-  }
-  for (int i = 0; i < p; ++i) {
-    for (int j = 0; j < nd; ++j) {
-      double s = 0.0;
-      for (int c = 0; c < nd; ++c) s += at(T, ldt, i, p + c) * Q[c + 4 * j];
-      tmp[j] = s;
-    }
-    for (int j = 0; j < nd; ++j) at(T, ldt, i, p + j) = tmp[j];
-  }
-  for (int i = 0; i < n; ++i) {
-    for (int j = 0; j < nd; ++j) {
-      double s = 0.0;
-      for (int c = 0; c < nd; ++c) s += at(Z, ldz, i, p + c) * Q[c + 4 * j];
-      tmp[j] = s;
-    }
-    for (int j = 0; j < nd; ++j) at(Z, ldz, i, p + j) = tmp[j];
-  }
+  if (nd == 3) apply_swap<3>(n, T, ldt, Z, ldz, p, Q);
+  else apply_swap<4>(n, T, ldt, Z, ldz, p, Q);
   for (int j = 0; j < nd; ++j)
     for (int r = 0; r < nd; ++r) at(T, ldt, p + r, p + j) = Dp[r + 4 * j];
   for (int j = 0; j < n2; ++j)
