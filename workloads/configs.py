@@ -10,6 +10,7 @@ import numpy as np
 
 from .convdiff import convdiff2d, convdiff3d, convdiff2d_field
 from .randsparse import powerlaw_random
+from .tridiag import tridiag_noisy
 
 CONFIGS = {
     # 2D convection-diffusion, 100^2, closed-form spectrum, Gaussian sketch.
@@ -32,6 +33,15 @@ CONFIGS = {
     "cd2d-512-field": dict(matrix=lambda: convdiff2d_field(512, 10000), k=16, m=48, d=192,
                            which="SR", tol=1e-10, sketch="sparse", zeta=8, sketch_seed=5,
                            start_seed=1, lock=True, precision="fp64"),
+    # The paper's synthetic tridiagonal family (Section 5.1): k = 40, m = 2k,
+    # sparse-sign sketch with d = 2m; exponential spectrum at its largest n.
+    "tridiag-exp-5m-lm": dict(matrix=lambda: tridiag_noisy(5_000_000, "exponential", 7), k=40, m=80, d=160,
+                              which="LM", tol=1e-10, sketch="sparse", zeta=8, sketch_seed=7,
+                              start_seed=1, lock=True, precision="fp64"),
+    # Same matrix, smallest modulus, a fixed 10 restarts (no convergence expected).
+    "tridiag-exp-5m-sm10": dict(matrix=lambda: tridiag_noisy(5_000_000, "exponential", 7), k=40, m=80, d=160,
+                                which="SM", tol=1e-10, sketch="sparse", zeta=8, sketch_seed=7,
+                                start_seed=1, lock=True, precision="fp64", max_restarts=10),
 }
 
 
