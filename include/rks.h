@@ -102,7 +102,9 @@ typedef struct {
   double resid_tol;      /* > 0: also stop once every pair's FP64 residual
                             ||A x - lambda x|| / (||A||_1 ||x||) is verified on the
                             device to be <= resid_tol (checked only when the
-                            estimates predict it); default 0 = off */
+                            estimates predict it; after a failed check, when they
+                            do so scaled by the true/estimated ratio seen there,
+                            or have halved); default 0 = off */
   int32_t refine;        /* low-precision basis only: 1 = after the low-precision
                             phase reaches refine_tol, continue in FP64 from a
                             combination of its Schur vectors; default 1 */
