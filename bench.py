@@ -5,6 +5,12 @@ with the matrix already resident in HBM, followed by nothing else; the
 eigenpair residual check runs after the timed region.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
+                  [--compare fp32,bf16,ks_cgs2] [--no-cpu-baseline]
+
+The default line times the FP64 solver and, after it, the FP32- and
+BF16-basis solvers (with FP64 refinement) on the same workload, reported under
+"precisions" with their own time-to-k, loop bandwidth and error against the
+FP64 run.
 """
 import argparse
 import json
@@ -140,7 +146,7 @@ def main():
     ap.add_argument("--profile-every", type=int, default=7,
                     help="time the kernels of every P-th Arnoldi step with HIP events (event records "
                          "cost a few microseconds each, so timing every launch would slow the solve)")
-    ap.add_argument("--compare", default="", help="comma list of extra runs on the same workload after the "
+    ap.add_argument("--compare", default="fp32,bf16", help="comma list of extra runs on the same workload after the "
                     "main run: basis precisions (fp32, bf16) and/or ks_cgs2 (deterministic Krylov-Schur); "
                     "reported under 'precisions'")
     args = ap.parse_args()
