@@ -30,6 +30,14 @@ Readings where the paper is open (listed with the reasons in the design notes):
     U_j, and B(j+1, j) is set to 0.
   * convergence: all effective-k estimates <= tol; at most max_restarts
     contraction/extension cycles after the first extension.
+
+Pins (tests/test_oracle_pins.py): the decomposition's identities through
+restarts, textbook Arnoldi for Omega = I, closed-form convection-diffusion
+spectra, dense brute force, the Section 4.1 residual bound, breakdown
+recovery, scale invariance.  Parity unpinned: the eigenvalues it returns for
+strongly non-normal operators (condition numbers 1e11-1e13, as on the 1000^2
+smallest-real-part workload) have no reference at that accuracy; only their
+residuals are checked there.
 """
 from dataclasses import dataclass, field
 
