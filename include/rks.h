@@ -113,6 +113,14 @@ typedef struct {
                             0 = 1e-6 for an FP32 basis, 1e-3 for BF16 */
   int32_t spmv_layout;   /* rks_spmv_layout, default AUTO */
   int32_t method;        /* rks_method, default RKS */
+  int32_t keep;          /* restart size: Schur vectors kept at each contraction,
+                            k <= keep <= m - 2 (keep + 1 when a conjugate pair
+                            would be split); 0 = k, the truncation of Algorithm 1.
+                            Any leading truncation of an rKS decomposition is
+                            again one (Section 3.1), so keeping the keep most
+                            wanted vectors instead of k is valid; convergence,
+                            locking and the returned pairs still concern only
+                            the leading k (k + 1 for a pair).  Default 0. */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */

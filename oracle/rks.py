@@ -124,14 +124,21 @@ class RKSOracle:
 
     def __init__(self, A, k, m, d, which="LM", tol=1e-10, sketch="sparse", zeta=8,
                  sketch_seed=0, start_seed=1, lock=True, whiten_tol=1e-12,
-                 max_restarts=300):
+                 max_restarts=300, keep=None):
         if hasattr(A, "row_ptr"):
             A = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
         self.A = sp.csr_matrix(A, dtype=np.float64)
         n = self.A.shape[0]
         if not (1 <= k and k + 2 <= m and m + 1 <= d and d <= n and m + 1 <= n):
             raise ValueError("need 1 <= k, k+2 <= m, m+1 <= d <= n")
+        keep = k if not keep else keep
+        if not (k <= keep <= m - 2):
+            raise ValueError("need k <= keep <= m-2")
         self.n, self.k, self.m, self.d = n, k, m, d
+        # restart size: any leading truncation of an rKS decomposition is one
+        # (Section 3.1); Algorithm 1 keeps k, a larger keep keeps more of the
+        # most wanted Schur vectors.  Only the leading k are tested/returned.
+        self.keep = keep
         self.which, self.tol, self.lock = which, tol, lock
         self.whiten_tol, self.max_restarts = whiten_tol, max_restarts
         self.start_seed = start_seed
@@ -143,6 +150,7 @@ class RKSOracle:
         self.j = 0          # index of the last basis column
         self.q = 0          # number of locked columns
         self.keff = 0
+        self.kr = 0         # wanted pairs: leading k, k+1 when a 2x2 block straddles k
         self.matvecs = 0
         self.breakdowns = 0
         self.whitenings = 0
@@ -204,8 +212,12 @@ class RKSOracle:
         m, q, k = self.m, self.q, self.k
         B = self.B
         T_a, Z = sla.schur(B[q:m, q:m], output="real")
-        T_a, Z, p = order_wanted(T_a, Z, self.which, k - q)
+        T_a, Z, p = order_wanted(T_a, Z, self.which, self.keep - q)
         keff = q + p
+        kr = min(k, keff)
+        if q < kr < keff and T_a[kr - q, kr - 1 - q] != 0.0:
+            kr += 1
+        self.kr = kr
         Q = np.eye(m)
         Q[q:, q:] = Z
         T = np.zeros((m, m))
@@ -240,10 +252,11 @@ class RKSOracle:
         self.j = keff
 
     def ritz(self):
-        """Eigenpairs of T_k and the estimates |b^T y| / |lambda| (Section 4.1)."""
-        keff = self.keff
-        Tk = self.B[:keff, :keff]
-        bk = self.B[keff, :keff]
+        """Eigenpairs of the wanted leading block T_k and the estimates
+        |b^T y| / |lambda| (Section 4.1)."""
+        keff, kr = self.keff, self.kr
+        Tk = self.B[:kr, :kr]
+        bk = self.B[keff, :kr]
         lam, Y = sla.eig(Tk)
         with np.errstate(divide="ignore", invalid="ignore"):
             est = np.abs(bk @ Y) / np.abs(lam)
@@ -258,7 +271,7 @@ class RKSOracle:
         tnorm = np.linalg.norm(Tk)
         q = self.q
         for (i, s, lam) in _blocks(Tk, q):
-            if i != q:
+            if i != q or i + s > self.kr:
                 break
             scale = max(abs(lam), UNIT_ROUNDOFF * tnorm)
             if np.all(np.abs(bk[i:i + s]) <= self.tol * scale):
@@ -287,13 +300,13 @@ class RKSOracle:
         return self._finish(converged, restarts, history)
 
     def _finish(self, converged, restarts, history):
-        keff = self.keff
-        Tk = self.B[:keff, :keff]
-        bk = self.B[keff, :keff]
+        keff, kr = self.keff, self.kr
+        Tk = self.B[:kr, :kr]
+        bk = self.B[keff, :kr]
         lam, Y = sla.eig(Tk)
         with np.errstate(divide="ignore", invalid="ignore"):
             est = np.abs(bk @ Y) / np.abs(lam)
-        lam, X, resid, est = eigpairs(self.A, self.U[:, :keff], lam, Y, est, self.which, self.normA1)
+        lam, X, resid, est = eigpairs(self.A, self.U[:, :kr], lam, Y, est, self.which, self.normA1)
         return OracleResult(lam, X, resid, est, converged, restarts, self.matvecs, self.q, history)
 
 

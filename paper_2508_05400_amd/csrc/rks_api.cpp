@@ -85,6 +85,8 @@ struct rks_ctx {
   int* hflags = nullptr;
   // state
   int j = 0, q = 0, keff = 0, pending = 0;
+  int keep = 0;  // restart size (kept Schur vectors), k <= keep <= m - 2
+  int kr = 0;    // leading pairs tested and returned: k, or k + 1 to keep a conjugate pair
   int64_t step_count = 0;  // Arnoldi steps run by this context (profiling sample clock)
   int G_z = 1, G_s = 1;
   bool have_state = false, solved = false;
@@ -330,6 +332,7 @@ int start(rks_ctx* c, const double* u0, int u0_on_device) {
   c->j = 0;
   c->q = 0;
   c->keff = 0;
+  c->kr = 0;
   c->have_state = true;
   c->solved = false;
   return RKS_OK;
@@ -347,15 +350,17 @@ int pull_state(rks_ctx* c) {
 }
 
 // Ritz values/vectors of the truncated factor and the estimates.
+// Only the leading kr x kr block (the wanted set) is used: T is quasi upper
+// triangular, so its eigenvectors there have no components beyond kr.
 void ritz(const rks_ctx* c, std::vector<cplx>& lam, std::vector<cplx>& Y, std::vector<double>& est) {
-  const int ke = c->keff;
-  lam.assign(ke, 0.0);
-  Y.assign((size_t)ke * ke, 0.0);
-  est.assign(ke, 0.0);
-  rks::quasi_tri_eig(ke, c->Tk.data(), ke, lam.data(), Y.data());
-  for (int i = 0; i < ke; ++i) {
+  const int kr = c->kr;
+  lam.assign(kr, 0.0);
+  Y.assign((size_t)kr * kr, 0.0);
+  est.assign(kr, 0.0);
+  rks::quasi_tri_eig(kr, c->Tk.data(), c->keff, lam.data(), Y.data());
+  for (int i = 0; i < kr; ++i) {
     cplx s = 0.0;
-    for (int r = 0; r < ke; ++r) s += c->bk[r] * Y[(size_t)r + (size_t)i * ke];
+    for (int r = 0; r < kr; ++r) s += c->bk[r] * Y[(size_t)r + (size_t)i * kr];
     est[i] = std::abs(s) / std::abs(lam[i]);
   }
 }
@@ -374,12 +379,17 @@ int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscal
   if (rks::real_schur(ma, Ta.data(), ma, Z.data(), ma) != 0)
     return fail(c, RKS_EDENSE, "QR iteration did not converge");
   int p = 0;
-  if (rks::order_wanted(ma, Ta.data(), ma, Z.data(), ma, c->which, k - q, &p) != 0) {
+  if (rks::order_wanted(ma, Ta.data(), ma, Z.data(), ma, c->which, c->keep - q, &p) != 0) {
     if (c->st) c->st->dense_fail += 1;
     if (p == 0) return fail(c, RKS_EDENSE, "reordering rejected every swap");
   }
   const int ke = q + p;
   c->keff = ke;
+  // the wanted pairs: the leading k (the ordering is most wanted first), plus
+  // one when a 2x2 block straddles column k
+  int kr = std::min(k, ke);
+  if (kr < ke && kr > q && Ta[(kr - q) + (size_t)(kr - 1 - q) * ma] != 0.0) kr += 1;
+  c->kr = kr;
   // truncated factor T (ke x ke) and b
   std::vector<double> T((size_t)ke * ke, 0.0), b(ke, 0.0);
   for (int jj = 0; jj < q; ++jj)
@@ -486,8 +496,8 @@ int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscal
   return RKS_OK;
 }
 
-// Lock leading blocks whose b entries are small relative to their
-// eigenvalue (Section 4.4, with the relative test) and zero them.
+// Lock leading blocks of the wanted set whose b entries are small relative
+// to their eigenvalue (Section 4.4, with the relative test) and zero them.
 void lock_converged(rks_ctx* c) {
   const int ke = c->keff, ldb = c->m + 1;
   double tn = 0.0;
@@ -498,7 +508,7 @@ void lock_converged(rks_ctx* c) {
   int q = c->q;
   for (size_t bi = 0; bi < st.size(); ++bi) {
     if (st[bi] < q) continue;
-    if (st[bi] != q) break;
+    if (st[bi] != q || st[bi] + sz[bi] > c->kr) break;
     const double lam = std::abs(rks::block_eig(c->Tk.data(), ke, st[bi], sz[bi]));
     const double scale = std::max(lam, kUnitRoundoff * tn);
     bool ok = true;
@@ -566,7 +576,7 @@ struct Packed {
 };
 
 Packed pack_ritz(const rks_ctx* c) {
-  const int ke = c->keff;
+  const int ke = c->kr;
   std::vector<cplx> lam, Y;
   std::vector<double> est;
   ritz(c, lam, Y, est);
@@ -610,7 +620,7 @@ int ensure_resid_scratch(rks_ctx* c) {
 // residual of every pair; optionally X columns are normalised to unit norm.
 int device_residuals(rks_ctx* c, const Packed& P, double* Xd, double* resid, bool normalise) {
   auto stm = c->env.stream;
-  const int ke = c->keff;
+  const int ke = c->kr;
   const int64_t n = c->n;
   HIPCHK(c, hipStreamSynchronize(stm));  // the pinned staging buffer hY may still be in flight
   for (int c0 = 0; c0 < ke; c0 += rks::kRotMax) {
@@ -733,7 +743,7 @@ int run_phase(rks_ctx* c, const double* u0, int u0_on_device, double tol, double
       rc = ensure_resid_scratch(c);
       if (rc) break;
       Packed P = pack_ritz(c);
-      std::vector<double> res(c->keff, 0.0);
+      std::vector<double> res(c->kr, 0.0);
       rc = device_residuals(c, P, c->Xr, res.data(), false);
       if (rc) break;
       out->resid_checks += 1;
@@ -768,7 +778,7 @@ int run_phase(rks_ctx* c, const double* u0, int u0_on_device, double tol, double
 // Schur vectors U_k (which span the approximate wanted invariant subspace),
 // formed in FP64 on the device into u0tmp; then switch the basis to FP64.
 int refine_start(rks_ctx* c) {
-  const int ke = c->keff;
+  const int ke = c->kr;
   HIPCHK(c, hipStreamSynchronize(c->env.stream));
   for (int i = 0; i < ke; ++i) c->hY[i] = 1.0 + 0.25 * (i % 3);
   HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)ke * 8, hipMemcpyHostToDevice, c->env.stream));
@@ -825,6 +835,7 @@ void rks_opts_default(rks_opts* o) {
   o->refine_tol = 0.0;
   o->spmv_layout = RKS_SPMV_AUTO;
   o->method = RKS_METHOD_RKS;
+  o->keep = 0;
 }
 
 const char* rks_strerror(int code) { return code_str(code); }
@@ -854,12 +865,16 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
       !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
       o.method > 1)
     return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout or method");
+  const int keep = o.keep == 0 ? k : o.keep;
+  if (keep < k || keep + 2 > m || keep + 1 > rks::kRotMax)
+    return fail(nullptr, RKS_EINVAL, "need k <= keep <= m - 2 and keep + 1 <= 64");
   if (o.method == RKS_METHOD_KS_CGS2 && o.precision != RKS_PREC_FP64)
     return fail(nullptr, RKS_EINVAL, "deterministic Krylov-Schur runs with an FP64 basis only");
 
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");
   c->n = n; c->nnz = nnz; c->k = k; c->m = m; c->d = d; c->which = which; c->tol = tol; c->o = o;
+  c->keep = keep;
   hipStream_t stm = (hipStream_t)o.stream;
   // host copies for validation, the 1-norm and the SpMV tiles
   std::vector<int32_t> rp(n + 1), col(nnz);
@@ -1105,7 +1120,7 @@ void rks_destroy(rks_ctx* c) {
   delete c;
 }
 
-int32_t rks_num_pairs(const rks_ctx* c) { return c ? c->keff : 0; }
+int32_t rks_num_pairs(const rks_ctx* c) { return c ? c->kr : 0; }
 
 int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st) {
   if (!c) return RKS_EINVAL;
@@ -1156,7 +1171,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   st->resid_checks = p1.resid_checks;
   st->restarts = p1.restarts;
   st->locked = c->q;
-  st->keff = c->keff;
+  st->keff = c->kr;
   st->spmv_layout = c->env.cb ? RKS_SPMV_COLUMN_BLOCKS : RKS_SPMV_ROWS;
   st->max_est = p1.maxest;
   st->t_host = p1.thost;
@@ -1170,7 +1185,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
 int rks_eigpairs(rks_ctx* c, double* lam_re, double* lam_im, double* X, int32_t X_on_device, double* resid) {
   if (!c) return RKS_EINVAL;
   if (!c->solved) return fail(c, RKS_ESTATE, "rks_eigpairs before a successful rks_solve");
-  const int ke = c->keff;
+  const int ke = c->kr;
   Packed P = pack_ritz(c);
   if (X || resid) {
     int rc = ensure_resid_scratch(c);

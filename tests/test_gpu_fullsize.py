@@ -100,14 +100,16 @@ def test_fullsize_first_extension(lib, cuda, name, prec):
     _identities(cfg, A, Sp, nA, prec, B, S, U, m)
 
 
-@pytest.mark.parametrize("name,prec", FULL)
-def test_fullsize_after_restarts(lib, cuda, name, prec):
+@pytest.mark.parametrize("name,prec,keep", [f + (0,) for f in FULL] + [("cd2d-1000", "fp64", 40)])
+def test_fullsize_after_restarts(lib, cuda, name, prec, keep):
     """Two contraction/extension cycles (rotation, locking, whitening) leave a
-    valid decomposition: checked on the contracted state at exit."""
+    valid decomposition: checked on the contracted state at exit.  keep = 40
+    keeps 40 of the 60 columns (k = 20) at each contraction."""
     cfg, A, Sp, nA = _workload(name)
     m, d = cfg["m"], cfg["d"]
-    print(f"full-size restarts {name} {prec}", flush=True)
-    with _ctx(cfg, A, prec, max_restarts=2, refine=0) as s:
+    kk = keep or cfg["k"]
+    print(f"full-size restarts {name} {prec} keep={kk}", flush=True)
+    with _ctx(cfg, A, prec, max_restarts=2, refine=0, keep=keep) as s:
         code = s.solve()
         assert code in (0, 1), P.rks_last_error(s.ctx)
         assert s.stats.restarts <= 2
@@ -115,6 +117,8 @@ def test_fullsize_after_restarts(lib, cuda, name, prec):
         S = np.zeros((d, m + 1), order="F")
         U = np.zeros((A.n, m + 1), order="F")
         nc = P.rks_get_state(s.ctx, B, S, U)
+        npairs = P.rks_num_pairs(s.ctx)
     j = nc - 1
-    assert cfg["k"] <= j <= cfg["k"] + 1
+    assert kk <= j <= kk + 1
+    assert npairs in (cfg["k"], cfg["k"] + 1)
     _identities(cfg, A, Sp, nA, prec, B, S, U, j, locked_slack=cfg["tol"] * np.sqrt(j), rotated=True)

@@ -157,19 +157,21 @@ def test_rotate_parity(lib, cuda):
 
 CONV = {
     # mildly non-normal operators on which rKS converges within the cap
-    "cd2d-40-LR-sparse": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse"),
-    "cd2d-40-LM-gauss": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LM", "gauss"),
+    "cd2d-40-LR-sparse": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 0),
+    "cd2d-40-LM-gauss": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LM", "gauss", 0),
+    # restart size 14 of m = 24 (k = 6)
+    "cd2d-40-LR-sparse-keep14": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 14),
 }
 
 
 @pytest.mark.parametrize("case", sorted(CONV))
 def test_solve_parity_converged(lib, cuda, case):
-    mk, k, m, d, which, kind = CONV[case]
+    mk, k, m, d, which, kind, keep = CONV[case]
     A = mk()
-    ref = oracle_rks(A, k, m, d, which, 1e-10, sketch=kind, sketch_seed=3, start_seed=1)
+    ref = oracle_rks(A, k, m, d, which, 1e-10, sketch=kind, sketch_seed=3, start_seed=1, keep=keep)
     assert ref.converged
     s = P.Solver.from_csr(A, k=k, m=m, d=d, which=which, tol=1e-10, sketch_kind=kind, sketch_seed=3,
-                          start_seed=1)
+                          start_seed=1, keep=keep)
     try:
         code = s.solve()
         assert code == 0, P.rks_last_error(s.ctx)
@@ -206,14 +208,17 @@ def test_solve_parity_converged(lib, cuda, case):
         s.close()
 
 
-def test_solve_parity_fixed_restarts(lib, cuda):
+@pytest.mark.parametrize("keep", [0, 25])
+def test_solve_parity_fixed_restarts(lib, cuda, keep):
     """The 100^2 convection-diffusion workload (Gaussian sketch d = 80): both
-    sides run 6 restarts from the same start; the leading Ritz values agree."""
+    sides run 6 restarts from the same start, keeping k = 10 or 25 Schur
+    vectors at each contraction; the leading Ritz values agree."""
     A = convdiff2d(100, (20.0, 10.0))
     k, m, d = 10, 40, 80
-    ref = oracle_rks(A, k, m, d, "LR", 1e-10, sketch="gauss", sketch_seed=0, start_seed=1, max_restarts=6)
+    ref = oracle_rks(A, k, m, d, "LR", 1e-10, sketch="gauss", sketch_seed=0, start_seed=1, max_restarts=6,
+                     keep=keep)
     s = P.Solver.from_csr(A, k=k, m=m, d=d, which="LR", tol=1e-10, sketch_kind="gauss", sketch_seed=0,
-                          start_seed=1, max_restarts=6)
+                          start_seed=1, max_restarts=6, keep=keep)
     try:
         code = s.solve()
         assert code in (0, 1)

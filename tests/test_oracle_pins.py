@@ -143,10 +143,12 @@ def _check_decomposition(o, ncols):
     return rel, orth, cons, rqe
 
 
-@pytest.mark.parametrize("kind", ["gauss", "sparse"])
-def test_decomposition_identities_through_restarts(kind):
+@pytest.mark.parametrize("kind,keep", [("gauss", None), ("sparse", None), ("sparse", 14)])
+def test_decomposition_identities_through_restarts(kind, keep):
+    """keep > k: a longer leading truncation is again an rKS decomposition
+    (Section 3.1), so the same identities hold on all keff columns."""
     A = convdiff2d(30, (20.0, 10.0))
-    o = RKSOracle(A, 6, 24, 60, "LR", 1e-10, sketch=kind, sketch_seed=4, start_seed=1)
+    o = RKSOracle(A, 6, 24, 60, "LR", 1e-10, sketch=kind, sketch_seed=4, start_seed=1, keep=keep)
     o.start()
     o.extend()
     for r in range(6):
@@ -158,11 +160,12 @@ def test_decomposition_identities_through_restarts(kind):
         # truncated factor is quasi-triangular (rKS decomposition)
         T = o.B[:o.keff, :o.keff]
         assert np.all(np.tril(T, -2) == 0)
-        # residual identity A x - lambda x = u b^T y for every Ritz pair
+        assert o.keff >= (keep or 6) and o.kr in (6, 7)
+        # residual identity A x - lambda x = u b^T y for every wanted Ritz pair
         lam, Y, est = o.ritz()
-        X = o.U[:, :o.keff] @ Y
+        X = o.U[:, :o.kr] @ Y
         lhs = o.A @ X - X * lam[None, :]
-        rhs = np.outer(o.U[:, o.keff], o.B[o.keff, :o.keff] @ Y)
+        rhs = np.outer(o.U[:, o.keff], o.B[o.keff, :o.kr] @ Y)
         assert np.linalg.norm(lhs - rhs) <= 1e-12 * o.normA1 * np.linalg.norm(X)
         o.lock_converged()
         o.extend()
@@ -223,14 +226,18 @@ def test_closed_form_convdiff_3d_brute_force():
     assert np.max(np.abs(got - cf[:5]) / cf[0]) < 1e-10
 
 
-def test_dense_brute_force_random_lm():
+@pytest.mark.parametrize("keep", [None, 20])
+def test_dense_brute_force_random_lm(keep):
     """Random non-symmetric n = 300 matrix: the oracle's LM pairs equal
-    LAPACK's eigenvalues of largest modulus."""
+    LAPACK's eigenvalues of largest modulus, also with a restart size of 20
+    (the returned pairs are the 6 most wanted, not the kept ones)."""
     A = powerlaw_random(300, 7, mean_len=12.0, lmin=4, lmax=64)
     lam_all = np.linalg.eigvals(A.to_dense())
     order = sorted(range(len(lam_all)), key=lambda i: which_key(lam_all[i], "LM"), reverse=True)
-    r = rks(A, 6, 40, 100, "LM", 1e-12, sketch="sparse", sketch_seed=9, start_seed=2, max_restarts=300)
+    r = rks(A, 6, 40, 100, "LM", 1e-12, sketch="sparse", sketch_seed=9, start_seed=2, max_restarts=300,
+            keep=keep)
     assert r.converged
+    assert len(r.lam) in (6, 7)
     want = lam_all[order[:len(r.lam)]]
     for z in r.lam:
         assert np.min(np.abs(want - z)) < 1e-10 * abs(z)
@@ -248,6 +255,7 @@ def test_residual_estimate_bound():
     o.contract()
     lam, Y, est = o.ritz()
     ke = o.keff
+    assert o.kr == ke
     Q, _ = np.linalg.qr(o.U[:, :ke + 1])
     s = np.linalg.svd(np.asarray(o.Om @ Q), compute_uv=False)
     eps = max(abs(s.max() ** 2 - 1), abs(s.min() ** 2 - 1))
@@ -324,3 +332,25 @@ def test_deterministic_ks_oracle_closed_form():
     assert np.max(np.abs(np.sort(r.lam.real)[::-1] - cf) / cf) < 1e-10
     U = o.U[:, :o.keff + 1]
     assert np.linalg.norm(U.T @ U - np.eye(o.keff + 1)) < 1e-12
+
+
+def test_restart_size_converges_to_closed_form_with_less_work():
+    """keep = 14 of m = 30 on the 2D operator of test_closed_form_convdiff_2d:
+    the 6 returned values still equal the closed form, and the run needs
+    fewer products with A than keep = k (the reason for the option)."""
+    N, beta = 20, (20.0, 10.0)
+    A = convdiff2d(N, beta)
+    cf = np.sort(convdiff_eigs(N, beta))[::-1][:6]
+    out = {}
+    for keep in (None, 14):
+        r = rks(A, 6, 30, 80, "LR", 1e-13, sketch="gauss", sketch_seed=1, start_seed=1, max_restarts=300,
+                keep=keep)
+        assert r.converged and len(r.lam) == 6
+        got = np.sort(r.lam.real)[::-1]
+        assert np.max(np.abs(got - cf) / cf) < 1e-10
+        out[keep] = r.matvecs
+    assert out[14] < out[None], out
+    with pytest.raises(ValueError):
+        RKSOracle(A, 6, 30, 80, "LR", keep=29)
+    with pytest.raises(ValueError):
+        RKSOracle(A, 6, 30, 80, "LR", keep=5)
