@@ -25,27 +25,27 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // Scatter v * Omega[:, i] into the block's LDS bins (unscaled).
-// KIND 0: Gaussian Omega; 1: sparse-sign Omega; 2: no sketch (deterministic
-// Krylov-Schur, whose kernels accumulate a squared norm instead).
+// KIND 1: sparse-sign Omega, accumulated by the producing kernel; 2: no
+// sketch (deterministic Krylov-Schur, whose kernels accumulate a squared norm
+// instead); 3: no sketch in the producing kernel: a Gaussian Omega (d dense
+// entries per column) is applied by k_gauss_sketch afterwards, which spreads
+// its Box-Muller work over the whole grid instead of one lane per element.
 template <int KIND>
 __device__ __forceinline__ void sketch_add(double* bins, uint64_t i, double v, const SketchP& sp) {
-  if (KIND == 2) return;
-  if (KIND == 1) {
-    int rows[8];
-    float sg[8];
-    sparse_column(i, sp.d, sp.zeta, sp.k0, sp.k1, rows, sg);
+  if (KIND != 1) return;
+  int rows[8];
+  float sg[8];
+  sparse_column(i, sp.d, sp.zeta, sp.k0, sp.k1, rows, sg);
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
-      if (t < sp.zeta) atomicAdd(&bins[rows[t]], (double)sg[t] * v);
-  } else {
-    const int np = (sp.d + 1) >> 1;
-    for (int p = 0; p < np; ++p) {
-      double g0, g1;
-      gauss_pair(i, (uint32_t)p, 0u, sp.k0, sp.k1, g0, g1);
-      atomicAdd(&bins[2 * p], g0 * v);
-      if (2 * p + 1 < sp.d) atomicAdd(&bins[2 * p + 1], g1 * v);
-    }
-  }
+  for (int t = 0; t < 8; ++t)
+    if (t < sp.zeta) atomicAdd(&bins[rows[t]], (double)sg[t] * v);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int j) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, j);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), j);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 __device__ __forceinline__ void bins_zero(double* bins, int d) {
@@ -126,9 +126,10 @@ template <typename TV, typename TW, typename TA, int KIND>
 __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
                                                      const TA* __restrict__ val, const int4* __restrict__ tdesc,
                                                      int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
-                                                     double* __restrict__ zpart, SketchP sp, int do_sketch) {
+                                                     double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
   __shared__ double bins[kMaxD];
   __shared__ TA prod[8][kTileNnz];
+  const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (do_sketch) bins_zero(bins, sp.d);
@@ -211,8 +212,9 @@ __global__ __launch_bounds__(512) void k_spmv_cb(int64_t n, const int* __restric
 template <typename TW, int KIND>
 __global__ __launch_bounds__(512) void k_cb_combine(int64_t n, const TW* __restrict__ P, int64_t ldp,
                                                     TW* __restrict__ w, double* __restrict__ zpart, SketchP sp,
-                                                    int do_sketch) {
+                                                    int do_sketch_arg) {
   __shared__ double bins[kMaxD];
+  const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -524,6 +526,7 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
     nrm = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) atomicAdd(&bins[0], nrm);
   }
+  if (KIND == 3) return;
   __syncthreads();
   bins_store(bins, spart, sp.d, sp.scale);
 }
@@ -654,6 +657,7 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
     nrm = wave_sum(nrm);
     if ((threadIdx.x & 63) == 0) atomicAdd(&bins[0], nrm);
   }
+  if (KIND == 3) return;
   __syncthreads();
   bins_store(bins, spart, sp.d, sp.scale);
 }
@@ -774,6 +778,56 @@ inline int grid_for(int64_t work, int per_block, int cap) {
   return (int)g;
 }
 
+// Partial sums of Omega x for a Gaussian Omega generated on the fly (entry
+// pair (2p, 2p+1) of column i comes from one Philox block, counter (i, p,
+// tag 0), and Box-Muller).  Block (bx, by) owns rows [bx R, bx R + R) and
+// the pairs p = 64 by + lane.  Its four waves take consecutive quarters of
+// those rows; a wave loads 64 entries of x at a time and walks them in
+// order, every lane reading the current entry from the lane that loaded it
+// and adding its own pair's two products.  So each of the n (d/2) pairs is
+// evaluated once, by a different lane than its neighbours in the sum, and
+// nothing is accumulated atomically.  The waves' sums are added in a fixed
+// order; row bx of part gets this block's bins.
+constexpr int kGsMinRows = 32;
+
+template <typename TX>
+__global__ __launch_bounds__(256) void k_gauss_sketch(int64_t n, const TX* __restrict__ x, int64_t R,
+                                                      double* __restrict__ part, SketchP sp) {
+  __shared__ double acc[4][2][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int np = (sp.d + 1) >> 1;
+  const int p = (int)blockIdx.y * 64 + lane;
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  const int64_t rend = min(n, r0 + R);
+  const int64_t Rw = (R + 3) >> 2;
+  const int64_t a0 = min(rend, r0 + wv * Rw), a1 = min(rend, a0 + Rw);
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t c = a0; c < a1; c += 64) {  // wave-uniform trip count
+    const int64_t i = c + lane;
+    const double xv = i < a1 ? Conv<TX>::ld(x[i]) : 0.0;
+    const int cnt = (int)min((int64_t)64, a1 - c);
+    for (int j = 0; j < cnt; ++j) {
+      const double v = readlane_f64(xv, j);
+      if (p < np) {
+        double g0, g1;
+        gauss_pair((uint64_t)(c + j), (uint32_t)p, 0u, sp.k0, sp.k1, g0, g1);
+        s0 += g0 * v;
+        s1 += g1 * v;
+      }
+    }
+  }
+  acc[wv][0][lane] = s0;
+  acc[wv][1][lane] = s1;
+  __syncthreads();
+  if (wv == 0 && p < np) {
+    const double t0 = ((acc[0][0][lane] + acc[1][0][lane]) + acc[2][0][lane]) + acc[3][0][lane];
+    const double t1 = ((acc[0][1][lane] + acc[1][1][lane]) + acc[2][1][lane]) + acc[3][1][lane];
+    double* row = part + (size_t)blockIdx.x * sp.d;
+    row[2 * p] = t0 * sp.scale;
+    if (2 * p + 1 < sp.d) row[2 * p + 1] = t1 * sp.scale;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -788,10 +842,23 @@ inline int grid_for(int64_t work, int per_block, int cap) {
       constexpr int KIND = 2;        \
       __VA_ARGS__;                   \
     } else {                         \
-      constexpr int KIND = 0;        \
+      constexpr int KIND = 3;        \
       __VA_ARGS__;                   \
     }                                \
   } while (0)
+
+// The Gaussian sketch of x (n entries of type TX) as partial rows of part;
+// returns the number of rows (<= kMaxG).
+template <typename TX>
+static int gauss_t(const LaunchEnv& e, const TX* x, double* part) {
+  const int np = (e.sp.d + 1) >> 1;
+  int64_t R = (e.n + kMaxG - 1) / kMaxG;
+  if (R < kGsMinRows) R = kGsMinRows;
+  const int Gx = (int)((e.n + R - 1) / R);
+  dim3 grid(Gx, (np + 63) / 64), block(256);
+  k_gauss_sketch<TX><<<grid, block, 0, e.stream>>>(e.n, x, R, part, e.sp);
+  return Gx;
+}
 
 template <typename TV, typename TW, typename TA>
 static int spmv_cb_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, double* zpart, int do_sketch) {
@@ -803,6 +870,7 @@ static int spmv_cb_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, doub
   const int G2 = grid_for(e.n, 512, kMaxG);
   RKS_SKETCH_SWITCH(e.sp_kind, (k_cb_combine<TW, KIND><<<G2, 512, 0, e.stream>>>(e.n, (const TW*)e.P, e.ldu, w, zpart,
                                                                                 e.sp, do_sketch)));
+  if (do_sketch && e.sp_kind == 0) return gauss_t<TW>(e, w, zpart);
   return G2;
 }
 
@@ -829,6 +897,8 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
                                      e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
                                      e.sp, do_sketch)));
   }
+  if (do_sketch && e.sp_kind == 0)
+    return prec == 0 ? gauss_t<double>(e, (const double*)w, zpart) : gauss_t<float>(e, (const float*)w, zpart);
   return G;
 }
 
@@ -873,6 +943,11 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
                                      e.n, npk, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew,
                                      spart, e.sp)));
   }
+  if (e.sp_kind == 0) {  // sketch of the stored value
+    if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
+    if (e.prec == 1) return gauss_t<float>(e, (const float*)unew, spart);
+    return gauss_t<bf16_t>(e, (const bf16_t*)unew, spart);
+  }
   return G;
 }
 
@@ -890,6 +965,13 @@ int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, (k_init<bf16_t, KIND><<<grid, block, 0, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1,
                                                                                      spart, e.sp, store)));
+  }
+  if (e.sp_kind == 0) {
+    // sketch of the stored value; without a store, of u0 itself (FP64 only)
+    if (!store) return u0 ? gauss_t<double>(e, u0, spart) : 0;
+    if (prec == 0) return gauss_t<double>(e, (const double*)u, spart);
+    if (prec == 1) return gauss_t<float>(e, (const float*)u, spart);
+    return gauss_t<bf16_t>(e, (const bf16_t*)u, spart);
   }
   return G;
 }
