@@ -5,12 +5,15 @@ with the matrix already resident in HBM, followed by nothing else; the
 eigenpair residual check runs after the timed region.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
-                  [--compare fp32,bf16,ks_cgs2] [--no-cpu-baseline]
+                  [--keep auto|N] [--compare alg1,fp32,bf16,ks_cgs2] [--no-cpu-baseline]
 
-The default line times the FP64 solver and, after it, the FP32- and
-BF16-basis solvers (with FP64 refinement) on the same workload, reported under
-"precisions" with their own time-to-k, loop bandwidth and error against the
-FP64 run.
+The solver keeps the restart size --keep Schur vectors at each contraction
+(auto: k + (m - k)/4; any leading truncation is an rKS decomposition,
+Section 3.1).  The default line times the FP64 solver and, after it, three
+variants on the same workload, reported under "variants" with their own
+time-to-k, loop bandwidth and error against the main run: "alg1" (FP64,
+keep = k, the truncation of Algorithm 1 as printed) and the FP32- and
+BF16-basis solvers (with FP64 refinement).
 """
 import argparse
 import json
@@ -24,7 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def cpu_baseline(A, cfg, restarts_gpu: int, budget_s: float = 25.0):
+def cpu_baseline(A, cfg, restarts_gpu: int, keep: int, budget_s: float = 25.0):
     """Time the FP64 oracle on a bounded sample: its first extension plus as
     many restart cycles as fit in the budget, extrapolated to the GPU's
     restart count (seconds, same unit as the metric)."""
@@ -34,7 +37,7 @@ def cpu_baseline(A, cfg, restarts_gpu: int, budget_s: float = 25.0):
     from oracle.rks import RKSOracle
     o = RKSOracle(A, cfg["k"], cfg["m"], cfg["d"], cfg["which"], cfg["tol"], sketch=cfg["sketch"],
                   zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"], start_seed=cfg["start_seed"],
-                  lock=cfg["lock"], max_restarts=restarts_gpu)
+                  lock=cfg["lock"], max_restarts=restarts_gpu, keep=keep)
     t0 = time.perf_counter()
     o.start(None)
     o.extend()
@@ -54,7 +57,8 @@ def cpu_baseline(A, cfg, restarts_gpu: int, budget_s: float = 25.0):
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
             "sample": (f"first extension ({cfg['m']} Arnoldi steps, {t_first:.2f}s) + {cycles} restart "
-                       f"cycles ({per:.2f}s each) of the same workload, extrapolated to the GPU's "
+                       f"cycles (keep {o.keep}; "
+                       f"{per:.2f}s each) of the same workload, extrapolated to the GPU's "
                        f"{restarts_gpu} restarts"),
             "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
@@ -146,9 +150,10 @@ def main():
     ap.add_argument("--profile-every", type=int, default=7,
                     help="time the kernels of every P-th Arnoldi step with HIP events (event records "
                          "cost a few microseconds each, so timing every launch would slow the solve)")
-    ap.add_argument("--compare", default="fp32,bf16", help="comma list of extra runs on the same workload after the "
-                    "main run: basis precisions (fp32, bf16) and/or ks_cgs2 (deterministic Krylov-Schur); "
-                    "reported under 'precisions'")
+    ap.add_argument("--keep", default="auto", help="restart size: auto (k + (m-k)/4), or a number in [k, m-2]")
+    ap.add_argument("--compare", default="alg1,fp32,bf16", help="comma list of extra runs on the same workload after "
+                    "the main run: alg1 (FP64, keep = k), basis precisions (fp32, bf16) and/or ks_cgs2 "
+                    "(deterministic Krylov-Schur); reported under 'variants'")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block "
@@ -168,12 +173,13 @@ def main():
     if args.max_restarts is not None:
         cfg["max_restarts"] = args.max_restarts
     A = cfg["matrix"]()
+    keep = -1 if args.keep == "auto" else int(args.keep)
     stream = torch.cuda.current_stream()
     solver = P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else args.profile_every,
-                               resid_tol=args.resid_tol, stream=stream)
+                               resid_tol=args.resid_tol, keep=keep, stream=stream)
     for _ in range(args.warmup):
         solver.solve()
     torch.cuda.synchronize()
@@ -223,7 +229,8 @@ def main():
                                f"{cfg['which']} k={cfg['k']} m={cfg['m']} d={cfg['d']} {cfg['sketch']}-sign"
                                if args.workload == "cd2d-1000" else args.workload,
                    "n": A.n, "nnz": A.nnz, "k": cfg["k"], "m": cfg["m"], "d": cfg["d"],
-                   "which": cfg["which"], "tol": cfg["tol"], "precision": cfg["precision"]},
+                   "which": cfg["which"], "tol": cfg["tol"], "precision": cfg["precision"],
+                   "keep": st["keep"], "keep_rule": "auto: k + (m-k)/4" if keep == -1 else "fixed"},
         "converged": bool(st["converged"]),
         "stop_reason": {0: "restart cap", 1: "estimates <= tol", 2: "verified residual <= resid_tol"}[st["stop_reason"]],
         "resid_tol": args.resid_tol,
@@ -250,12 +257,14 @@ def main():
     }
     extra = {}
     for prec in [p for p in args.compare.split(",") if p]:
-        # a precision (fp32, bf16: mixed precision with FP64 refinement), or
-        # ks_cgs2: deterministic Krylov-Schur with an FP64 basis (the paper's comparison)
+        # a precision (fp32, bf16: mixed precision with FP64 refinement), ks_cgs2:
+        # deterministic Krylov-Schur with an FP64 basis (the paper's comparison),
+        # or alg1: FP64 with the restart size of Algorithm 1 (keep = k)
         method = "ks_cgs2" if prec == "ks_cgs2" else "rks"
+        vprec = "fp64" if prec in ("ks_cgs2", "alg1") else prec
         with P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
-                               start_seed=cfg["start_seed"], precision="fp64" if method == "ks_cgs2" else prec,
+                               start_seed=cfg["start_seed"], precision=vprec, keep=0 if prec == "alg1" else keep,
                                method=method, lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), resid_tol=args.resid_tol,
                                profile=0 if args.no_profile else args.profile_every, stream=stream) as s2:
@@ -271,16 +280,16 @@ def main():
                       file=sys.stderr, flush=True)
             st2 = s2.stats.as_dict()
             lam2, X2, res2 = s2.eigpairs(want_vectors=True, want_resid=True)
-            extra[prec] = {"time_to_k_s": float(np.mean(ts)), "restarts": st2["restarts"],
+            extra[prec] = {"time_to_k_s": float(np.mean(ts)), "keep": st2["keep"], "restarts": st2["restarts"],
                            "restarts_low_precision": st2["restarts_lo"], "refined": bool(st2["refined"]),
                            "low_precision_phase_s": st2["t_lo"], "max_resid": float(np.max(res2)),
                            "converged": bool(st2["converged"]), "loop_gbs": _loop_gbs(st2),
                            "step_avg_us": st2["t_step"] / max(st2["n_timed_whole"], 1) * 1e6,
-                           "vs_fp64_run": _error_vs(lam, X64, lam2, X2)}
+                           "vs_main_run": _error_vs(lam, X64, lam2, X2)}
     if extra:
-        out["precisions"] = extra
+        out["variants"] = extra
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, cfg, st["restarts"])
+        out["cpu_baseline"] = cpu_baseline(A, cfg, st["restarts"], keep)
     print(json.dumps(out))
 
 

@@ -73,6 +73,9 @@ typedef enum { RKS_SPMV_AUTO = 0, RKS_SPMV_ROWS = 1, RKS_SPMV_COLUMN_BLOCKS = 2 
  * options are ignored. */
 typedef enum { RKS_METHOD_RKS = 0, RKS_METHOD_KS_CGS2 = 1 } rks_method;
 
+/* rks_opts.keep: restart size chosen from k and m (see the field). */
+#define RKS_KEEP_AUTO (-1)
+
 /* Square CSR matrix: row_ptr[n+1] (monotone, row_ptr[0] = 0), col[nnz]
  * (in [0, n), strictly increasing inside a row), val[nnz] FP64.
  * on_device = 0: host arrays; 1: device arrays.  Copied by rks_create. */
@@ -114,13 +117,15 @@ typedef struct {
   int32_t spmv_layout;   /* rks_spmv_layout, default AUTO */
   int32_t method;        /* rks_method, default RKS */
   int32_t keep;          /* restart size: Schur vectors kept at each contraction,
-                            k <= keep <= m - 2 (keep + 1 when a conjugate pair
-                            would be split); 0 = k, the truncation of Algorithm 1.
-                            Any leading truncation of an rKS decomposition is
-                            again one (Section 3.1), so keeping the keep most
-                            wanted vectors instead of k is valid; convergence,
-                            locking and the returned pairs still concern only
-                            the leading k (k + 1 for a pair).  Default 0. */
+                            k <= keep <= min(m - 2, 63) (keep + 1 when a conjugate
+                            pair would be split); 0 = k, the truncation of
+                            Algorithm 1; RKS_KEEP_AUTO (-1) = k + (m - k) / 4,
+                            clamped to that range.  Any leading truncation of an
+                            rKS decomposition is again one (Section 3.1), so
+                            keeping the keep most wanted vectors instead of k is
+                            valid; convergence, locking and the returned pairs
+                            still concern only the leading k (k + 1 for a pair).
+                            Default 0. */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -154,6 +159,7 @@ typedef struct {
   double t_step;             /* seconds summed over those steps (four launches each, one event pair) */
   double bytes_timed_whole;  /* their algorithmic bytes (SpMV + update) */
   int32_t spmv_layout;       /* rks_spmv_layout in use (ROWS or COLUMN_BLOCKS) */
+  int32_t keep;              /* restart size in use */
   double hist_est[512];  /* max estimate after contraction r (r < 512) */
 } rks_stats;
 

@@ -131,6 +131,8 @@ class RKSOracle:
         n = self.A.shape[0]
         if not (1 <= k and k + 2 <= m and m + 1 <= d and d <= n and m + 1 <= n):
             raise ValueError("need 1 <= k, k+2 <= m, m+1 <= d <= n")
+        if keep == -1:      # automatic: k + (m - k) / 4, at most m - 2 and 63 (as the library)
+            keep = max(k, min(k + (m - k) // 4, m - 2, 63))
         keep = k if not keep else keep
         if not (k <= keep <= m - 2):
             raise ValueError("need k <= keep <= m-2")

@@ -54,7 +54,7 @@ class RksStats(ctypes.Structure):
                 ("bytes_timed_update", ctypes.c_double), ("bytes_timed_rotate", ctypes.c_double),
                 ("n_timed_whole", ctypes.c_int64), ("t_step", ctypes.c_double),
                 ("bytes_timed_whole", ctypes.c_double), ("spmv_layout", ctypes.c_int32),
-                ("hist_est", ctypes.c_double * 512)]
+                ("keep", ctypes.c_int32), ("hist_est", ctypes.c_double * 512)]
 
     def as_dict(self) -> dict:
         out = {f: getattr(self, f) for f, _ in self._fields_ if f != "hist_est"}

@@ -865,7 +865,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
       !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
       o.method > 1)
     return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout or method");
-  const int keep = o.keep == 0 ? k : o.keep;
+  int keep = o.keep == 0 ? k : o.keep;
+  if (o.keep == RKS_KEEP_AUTO)
+    keep = std::max(k, std::min({k + (m - k) / 4, m - 2, rks::kRotMax - 1}));
   if (keep < k || keep + 2 > m || keep + 1 > rks::kRotMax)
     return fail(nullptr, RKS_EINVAL, "need k <= keep <= m - 2 and keep + 1 <= 64");
   if (o.method == RKS_METHOD_KS_CGS2 && o.precision != RKS_PREC_FP64)
@@ -1173,6 +1175,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   st->locked = c->q;
   st->keff = c->kr;
   st->spmv_layout = c->env.cb ? RKS_SPMV_COLUMN_BLOCKS : RKS_SPMV_ROWS;
+  st->keep = c->keep;
   st->max_est = p1.maxest;
   st->t_host = p1.thost;
   st->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

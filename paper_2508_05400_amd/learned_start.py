@@ -19,6 +19,8 @@ Every tensor operation of training and inference runs in the library's HIP
 kernels (rks_net_*); torch only provides device memory.
 
   python -m paper_2508_05400_amd.learned_start --train 2000 --test 200 --out DIR
+  python -m paper_2508_05400_amd.learned_start --eval-only --keep -1 --test 200 --out DIR
+      (held-out comparison only, with the committed weights and a given restart size)
 """
 import argparse
 import json
@@ -170,14 +172,16 @@ def instance(i: int):
     return A, features(bx, by, N)
 
 
-def solve(A, u0=None, resid_tol=1e-5, want_vectors=True):
+def solve(A, u0=None, resid_tol=1e-5, want_vectors=True, keep=0):
     """rKS on one family member to a verified residual; returns (stats, Ritz vectors, seconds).
-    The Ritz vectors at exit are returned even when the restart cap is hit."""
+    The Ritz vectors at exit are returned even when the restart cap is hit.
+    keep is the restart size (0: k, as in Algorithm 1; -1: automatic)."""
     import torch
     from . import Solver
     f = FAMILY
     with Solver.from_csr(A, k=f["k"], m=f["m"], d=f["d"], which=f["which"], tol=f["tol"], sketch_kind=f["sketch"],
-                         sketch_seed=f["sketch_seed"], start_seed=f["start_seed"], resid_tol=resid_tol) as s:
+                         sketch_seed=f["sketch_seed"], start_seed=f["start_seed"], resid_tol=resid_tol,
+                         keep=keep) as s:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         code = s.solve(u0)
@@ -201,7 +205,13 @@ def main(argv=None):
     ap.add_argument("--final", type=int, default=50, help="test instances also run to residual 1e-8")
     ap.add_argument("--out", default="learned_out")
     ap.add_argument("--weights", default=None)
+    ap.add_argument("--keep", type=int, default=0, help="restart size of every solve (0: k, -1: automatic)")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="skip data generation and training: compare the weights (default: the committed ones) "
+                         "with the random start on the held-out instances")
     args = ap.parse_args(argv)
+    if args.eval_only:
+        return evaluate(args)
     import torch
     os.makedirs(args.out, exist_ok=True)
     N = FAMILY["N"]
@@ -217,7 +227,7 @@ def main(argv=None):
     seeds = list(range(args.train)) + [100000 + j for j in range(args.test)]
     for i, sd in enumerate(seeds):
         A, f = instance(sd)
-        st, X, dt = solve(A, resid_tol=args.target)
+        st, X, dt = solve(A, resid_tol=args.target, keep=args.keep)
         base.append({"seed": 10000 + sd, "restarts": st["restarts"], "matvecs": st["matvecs"], "time_s": dt,
                      "code": st["code"], "resid": st["max_resid_final"]})
         feats.append(f)
@@ -251,7 +261,7 @@ def main(argv=None):
         i = args.train + j
         A, f = instance(seeds[i])
         u0 = net.start_vector(f, N)
-        st, _, dt = solve(A, u0, resid_tol=args.target, want_vectors=False)
+        st, _, dt = solve(A, u0, resid_tol=args.target, want_vectors=False, keep=args.keep)
         Vt = torch.tensor(targets[i][None], dtype=torch.float32, device="cuda")
         l, _ = net.loss_and_grad(net.predict(f), Vt)
         e = {"seed": base[i]["seed"], "random_restarts": base[i]["restarts"], "random_matvecs": base[i]["matvecs"],
@@ -259,8 +269,8 @@ def main(argv=None):
              "learned_restarts": st["restarts"], "learned_matvecs": st["matvecs"], "learned_time_s": dt,
              "learned_code": st["code"], "subspace_fraction": 1.0 - float(l[0])}
         if j < args.final:
-            sr, _, tr = solve(A, None, resid_tol=1e-8, want_vectors=False)
-            sl, _, tl = solve(A, u0, resid_tol=1e-8, want_vectors=False)
+            sr, _, tr = solve(A, None, resid_tol=1e-8, want_vectors=False, keep=args.keep)
+            sl, _, tl = solve(A, u0, resid_tol=1e-8, want_vectors=False, keep=args.keep)
             e.update({"random_1e-8_code": sr["code"], "random_1e-8_restarts": sr["restarts"],
                       "random_1e-8_time_s": tr, "learned_1e-8_code": sl["code"],
                       "learned_1e-8_restarts": sl["restarts"], "learned_1e-8_time_s": tl})
@@ -287,6 +297,72 @@ def main(argv=None):
     with open(os.path.join(args.out, "learned_start_results.json"), "w") as fh:
         json.dump({"summary": summary, "loss_history": hist, "eval": evals, "data": base}, fh)
     log("summary " + json.dumps(summary))
+    return summary
+
+
+def evaluate(args):
+    """Held-out comparison with trained weights: for each test instance the
+    random start and the network's start, both to the verified residual
+    args.target, and the first args.final instances also to 1e-8."""
+    N = FAMILY["N"]
+    t_start = time.time()
+    net = StartNet.load(args.weights or WEIGHTS)
+    evals = []
+    for j in range(args.test):
+        A, f = instance(100000 + j)
+        u0 = net.start_vector(f, N)
+        sr, Xr, tr = solve(A, None, resid_tol=args.target, want_vectors=True, keep=args.keep)
+        sl, _, tl = solve(A, u0, resid_tol=args.target, want_vectors=False, keep=args.keep)
+        import torch
+        Vt = torch.tensor(target_basis(Xr, N)[None], dtype=torch.float32, device="cuda")
+        l, _ = net.loss_and_grad(net.predict(f), Vt)
+        e = {"seed": 110000 + j, "random_restarts": sr["restarts"], "random_matvecs": sr["matvecs"],
+             "random_time_s": tr, "random_code": sr["code"], "learned_restarts": sl["restarts"],
+             "learned_matvecs": sl["matvecs"], "learned_time_s": tl, "learned_code": sl["code"],
+             "subspace_fraction": 1.0 - float(l[0])}
+        if j < args.final:
+            s8r, _, t8r = solve(A, None, resid_tol=1e-8, want_vectors=False, keep=args.keep)
+            s8l, _, t8l = solve(A, u0, resid_tol=1e-8, want_vectors=False, keep=args.keep)
+            e.update({"random_1e-8_code": s8r["code"], "random_1e-8_restarts": s8r["restarts"],
+                      "random_1e-8_matvecs": s8r["matvecs"], "random_1e-8_time_s": t8r,
+                      "learned_1e-8_code": s8l["code"], "learned_1e-8_restarts": s8l["restarts"],
+                      "learned_1e-8_matvecs": s8l["matvecs"], "learned_1e-8_time_s": t8l})
+        evals.append(e)
+        if (j + 1) % 10 == 0:
+            print(f"[{time.time() - t_start:7.1f}s] eval {j + 1}/{args.test}", flush=True)
+    rm = np.array([e["random_matvecs"] for e in evals], dtype=float)
+    lm = np.array([e["learned_matvecs"] for e in evals], dtype=float)
+    both = [e for e in evals if e["random_code"] == 0 and e["learned_code"] == 0]
+    fin = [e for e in evals if "random_1e-8_code" in e]
+    fin_both = [e for e in fin if e["random_1e-8_code"] == 0 and e["learned_1e-8_code"] == 0]
+    summary = {"test": len(evals), "keep": args.keep, "target_resid": args.target,
+               "mean_subspace_fraction_learned": float(np.mean([e["subspace_fraction"] for e in evals])),
+               "median_matvec_ratio_learned_over_random": float(np.median(lm / rm)),
+               "mean_matvecs_random": float(rm.mean()), "mean_matvecs_learned": float(lm.mean()),
+               "mean_time_random_s": float(np.mean([e["random_time_s"] for e in evals])),
+               "mean_time_learned_s": float(np.mean([e["learned_time_s"] for e in evals])),
+               "reached_target_random": int(sum(e["random_code"] == 0 for e in evals)),
+               "reached_target_learned": int(sum(e["learned_code"] == 0 for e in evals)),
+               "median_matvec_ratio_where_both_reached": (float(np.median(
+                   [e["learned_matvecs"] / e["random_matvecs"] for e in both])) if both else None),
+               "final_1e-8_instances": len(fin),
+               "reached_1e-8_random": int(sum(e["random_1e-8_code"] == 0 for e in fin)),
+               "reached_1e-8_learned": int(sum(e["learned_1e-8_code"] == 0 for e in fin)),
+               "median_1e-8_matvec_ratio_where_both_reached": (float(np.median(
+                   [e["learned_1e-8_matvecs"] / e["random_1e-8_matvecs"] for e in fin_both])) if fin_both else None),
+               "mean_1e-8_time_random_s": (float(np.mean([e["random_1e-8_time_s"] for e in fin])) if fin else None),
+               "mean_1e-8_time_learned_s": (float(np.mean([e["learned_1e-8_time_s"] for e in fin])) if fin else None)}
+    os.makedirs(args.out, exist_ok=True)
+    what = (f"held-out evaluation of {os.path.basename(args.weights or WEIGHTS)}: {len(evals)} instances (seeds "
+            f"110000..{110000 + len(evals) - 1}) of the 512^2 variable-velocity convection-diffusion family, rKS "
+            f"k=16 m=48 d=192 SR sparse-sign seed 5, restart size keep={args.keep} (0: k, -1: k + (m-k)/4), "
+            f"random start against the network's start, verified residual {args.target:g} (and 1e-8 on the "
+            f"first {len(fin)}); code 0 = reached, 1 = restart cap 300")
+    command = (f"python -m paper_2508_05400_amd.learned_start --eval-only --keep {args.keep} --test {args.test} "
+               f"--final {args.final} --target {args.target:g} --out <dir>")
+    with open(os.path.join(args.out, "learned_start_eval.json"), "w") as fh:
+        json.dump({"what": what, "command": command, "summary": summary, "eval": evals}, fh, indent=0)
+    print("summary " + json.dumps(summary), flush=True)
     return summary
 
 

@@ -6,9 +6,13 @@ What is asserted is what the network is trained for and what the solver
 guarantees: the predicted start lies almost entirely in the wanted invariant
 subspace at the network's 64^2 resolution (a random vector has 17/4096 of
 its energy there), and the solve from it reaches the same verified residual.
-The restart counts and times of both starts are printed; on this family they
-are statistically the same (the committed evaluation summary beside the
-weights covers 200 held-out instances), so no speed-up is asserted.
+The restart counts and times of both starts are printed.  The committed
+evaluation summaries beside the weights cover 200 held-out instances: with
+the restart size of Algorithm 1 (keep = k) the two starts need the same
+number of products with A; with keep = k + (m - k)/4 (used here) every
+instance converges from both, and the learned start needs a median 4.5%
+fewer products at residual 1e-5 and 1.4% fewer at 1e-8.  That gain is small
+against the instance-to-instance spread, so it is not asserted on three.
 """
 import numpy as np
 import pytest
@@ -26,7 +30,7 @@ def test_learned_start_vs_random(lib, cuda):
     rows = []
     for sd in HELD_OUT:
         A, f = instance(sd)
-        st_r, X, t_r = solve(A, None, resid_tol=1e-5, want_vectors=True)
+        st_r, X, t_r = solve(A, None, resid_tol=1e-5, want_vectors=True, keep=-1)
         u = net.start_vector(f, N)
         uh = u.cpu().numpy()
         assert np.all(np.isfinite(uh)) and np.linalg.norm(uh) > 0
@@ -35,7 +39,7 @@ def test_learned_start_vs_random(lib, cuda):
         frac_coarse = float(np.sum((V.T @ uc) ** 2) / np.sum(uc ** 2))
         Q, _ = np.linalg.qr(X)
         frac_fine = float(np.sum((Q.T @ uh) ** 2) / np.sum(uh ** 2))
-        st_l, _, t_l = solve(A, u, resid_tol=1e-5, want_vectors=False)
+        st_l, _, t_l = solve(A, u, resid_tol=1e-5, want_vectors=False, keep=-1)
         rows.append((sd, frac_coarse, frac_fine, st_r["restarts"], st_l["restarts"], st_r["matvecs"],
                      st_l["matvecs"], t_r, t_l, st_r["code"], st_l["code"], st_l["max_resid_final"]))
         print(f"instance {10000 + sd}: subspace fraction coarse {frac_coarse:.4f} fine {frac_fine:.4f}; "
@@ -45,7 +49,7 @@ def test_learned_start_vs_random(lib, cuda):
     assert fc.min() > 0.8, fc                       # random: KPAD / GRID^2
     assert fc.mean() > 100 * KPAD / GRID**2
     for r in rows:
-        if r[10] == 0:                              # converged from the learned start
-            assert r[11] <= 1e-5
+        assert r[9] == 0 and r[10] == 0             # both starts converge with this restart size
+        assert r[11] <= 1e-5
     print(f"matvecs over {len(rows)} instances: random {sum(r[5] for r in rows)}, "
           f"learned {sum(r[6] for r in rows)}", flush=True)

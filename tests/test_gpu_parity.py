@@ -336,3 +336,17 @@ def test_mixed_precision_unrefined_error_reported(lib, cuda):
     assert res.max() <= 1e-6
     rel = np.abs(np.sort_complex(lam) - np.sort_complex(ref.lam)) / np.abs(np.sort_complex(ref.lam))
     assert rel.max() <= 1e-4
+
+
+def test_restart_size_resolution_and_limits(lib, cuda):
+    """keep = RKS_KEEP_AUTO resolves to k + (m - k)/4 (clamped to m - 2 and 63);
+    sizes outside [k, min(m - 2, 63)] are rejected at create."""
+    A = convdiff2d(30, (2.0, 1.0))
+    for (k, m, want) in [(6, 24, 10), (10, 40, 17), (50, 120, 63), (6, 8, 6)]:
+        with P.Solver.from_csr(A, k=k, m=m, d=m + 20, which="LR", tol=1e-6, keep=-1, max_restarts=1) as s:
+            s.solve()
+            assert s.stats.keep == want, (k, m, s.stats.keep)
+    for bad in (5, 23, 64):
+        with pytest.raises(P.RksError) as ei:
+            P.Solver.from_csr(A, k=6, m=24 if bad != 64 else 100, d=130, which="LR", tol=1e-6, keep=bad)
+        assert ei.value.code == -1

@@ -350,6 +350,8 @@ def test_restart_size_converges_to_closed_form_with_less_work():
         assert np.max(np.abs(got - cf) / cf) < 1e-10
         out[keep] = r.matvecs
     assert out[14] < out[None], out
+    assert RKSOracle(A, 6, 30, 80, "LR", keep=-1).keep == 12
+    assert RKSOracle(A, 6, 8, 80, "LR", keep=-1).keep == 6
     with pytest.raises(ValueError):
         RKSOracle(A, 6, 30, 80, "LR", keep=29)
     with pytest.raises(ValueError):
