@@ -80,6 +80,11 @@ struct rks_ctx {
   float* val32_cb = nullptr;
   void* P = nullptr;
   double *Xr = nullptr, *ax1 = nullptr, *ax2 = nullptr, *rpart = nullptr;  // residual scratch (lazy)
+  // E, B, S, cs and flags live in one device block and one pinned host block
+  // of the same layout, so a restart moves them with one copy each way
+  void* dstate = nullptr;
+  void* hstate = nullptr;
+  size_t bytes_pull = 0, bytes_push = 0;
   // pinned host mirrors
   double *hB = nullptr, *hS = nullptr, *hcs = nullptr, *hY = nullptr, *hE = nullptr;
   int* hflags = nullptr;
@@ -139,14 +144,14 @@ struct Prof {
   Prof(rks_ctx* c_, int cat_, bool on) : c(c_), cat(cat_) {
     if (on && c->o.profile > 0 && c->st) {
       a = get_event(c);
-      if (a) hipEventRecord(a, c->env.stream);
+      if (a) (void)hipEventRecord(a, c->env.stream);
     }
   }
   ~Prof() {
     if (a) {
       hipEvent_t b = get_event(c);
       if (b) {
-        hipEventRecord(b, c->env.stream);
+        (void)hipEventRecord(b, c->env.stream);
         c->open.push_back({cat, a, b});
       }
     }
@@ -340,10 +345,8 @@ int start(rks_ctx* c, const double* u0, int u0_on_device) {
 
 int pull_state(rks_ctx* c) {
   auto st = c->env.stream;
-  HIPCHK(c, hipMemcpyAsync(c->hB, c->B, (size_t)(c->m + 1) * c->m * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipMemcpyAsync(c->hS, c->S, (size_t)c->d * (c->m + 1) * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipMemcpyAsync(c->hcs, c->cs, (size_t)(c->m + 1) * 8, hipMemcpyDeviceToHost, st));
-  HIPCHK(c, hipMemcpyAsync(c->hflags, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+  // B, S, cs, flags: contiguous in both state blocks
+  HIPCHK(c, hipMemcpyAsync(c->hB, c->B, c->bytes_pull, hipMemcpyDeviceToHost, st));
   HIPCHK(c, hipStreamSynchronize(st));
   flush_events(c);
   return RKS_OK;
@@ -365,8 +368,32 @@ void ritz(const rks_ctx* c, std::vector<cplx>& lam, std::vector<cplx>& Y, std::v
   }
 }
 
+// Dot product of two contiguous vectors with eight independent partial sums
+// (a single running sum is one long dependent chain of FMAs).
+double dot8(const double* a, const double* b, int n) {
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int r = 0;
+  for (; r + 8 <= n; r += 8)
+    for (int t = 0; t < 8; ++t) s[t] += a[r + t] * b[r + t];
+  for (; r < n; ++r) s[r & 7] += a[r] * b[r];
+  return ((s[0] + s[4]) + (s[1] + s[5])) + ((s[2] + s[6]) + (s[3] + s[7]));
+}
+
+// G = Sn^T Sn - I for the first nc columns of Sn (d rows), symmetric, into
+// the (ld x ld) column-major array E.
+void sketch_gram(const double* Sn, int d, int nc, double* E, int ld) {
+  for (int j = 0; j < nc; ++j)
+    for (int i = 0; i <= j; ++i) {
+      double g = dot8(&Sn[(size_t)i * d], &Sn[(size_t)j * d], d);
+      if (i == j) g -= 1.0;
+      E[i + (size_t)j * ld] = g;
+      E[j + (size_t)i * ld] = g;
+    }
+}
+
 // Contraction on the host: Schur form of the active block, reordering,
-// truncation, whitening; fills Y for the device rotation and the new B, S.
+// truncation, whitening; fills Y for the device rotation and the new B, S,
+// and E = S^T S - I of the contracted sketch (uploaded by push_state).
 int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscale, int* whitened) {
   const int m = c->m, q = c->q, k = c->k, d = c->d, ldb = m + 1;
   const int ma = m - q;
@@ -427,14 +454,12 @@ int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscal
   for (int jj = 0; jj < p; ++jj)
     for (int l = 0; l < ma; ++l) Yf[(q + l) + (size_t)(q + jj) * m] = c->hcs[q + l] * Z[l + (size_t)jj * ma];
   // whitening (Section 3.3) when the truncated sketch lost orthonormality
+  const int ldE = m + 1;
+  std::fill(c->hE, c->hE + (size_t)ldE * ldE, 0.0);
+  if (!c->ks) sketch_gram(Sn.data(), d, ke + 1, c->hE, ldE);
   double dev = 0.0;
   for (int a = 0; a < ke; ++a)
-    for (int bcol = 0; bcol < ke; ++bcol) {
-      double s = 0.0;
-      for (int r = 0; r < d; ++r) s += Sn[r + (size_t)a * d] * Sn[r + (size_t)bcol * d];
-      s -= (a == bcol) ? 1.0 : 0.0;
-      dev += s * s;
-    }
+    for (int bcol = 0; bcol < ke; ++bcol) dev += c->hE[a + (size_t)bcol * ldE] * c->hE[a + (size_t)bcol * ldE];
   dev = std::sqrt(dev);
   *whitened = 0;
   if (!c->ks && dev > c->o.whiten_tol) {  // deterministic Krylov-Schur keeps no sketch
@@ -467,6 +492,7 @@ int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscal
     T.swap(T3);
     b.swap(b2);
     Yf.swap(Y2);
+    sketch_gram(Sn.data(), d, ke + 1, c->hE, ldE);
     *whitened = 1;
     if (c->st) c->st->whitenings += 1;
   }
@@ -545,23 +571,9 @@ int rotate_basis(rks_ctx* c, int in0, int min, int out0, int kout, double xscale
 
 int push_state(rks_ctx* c) {
   auto stm = c->env.stream;
-  // E = S^T S - I of the contracted sketch (columns 0..keff), exactly symmetric
-  const int d = c->d, ld = c->m + 1, nc = c->ks ? 0 : c->keff + 1;
-  std::fill(c->hE, c->hE + (size_t)ld * ld, 0.0);
-  for (int j = 0; j < nc; ++j)
-    for (int i = 0; i <= j; ++i) {
-      const double* a = &c->hS[(size_t)i * d];
-      const double* b = &c->hS[(size_t)j * d];
-      double acc = 0.0;
-      for (int r = 0; r < d; ++r) acc += a[r] * b[r];
-      if (i == j) acc -= 1.0;
-      c->hE[i + (size_t)j * ld] = acc;
-      c->hE[j + (size_t)i * ld] = acc;
-    }
-  HIPCHK(c, hipMemcpyAsync(c->E, c->hE, (size_t)ld * nc * 8, hipMemcpyHostToDevice, stm));
-  HIPCHK(c, hipMemcpyAsync(c->B, c->hB, (size_t)(c->m + 1) * c->m * 8, hipMemcpyHostToDevice, stm));
-  HIPCHK(c, hipMemcpyAsync(c->S, c->hS, (size_t)c->d * (c->m + 1) * 8, hipMemcpyHostToDevice, stm));
-  HIPCHK(c, hipMemcpyAsync(c->cs, c->hcs, (size_t)(c->m + 1) * 8, hipMemcpyHostToDevice, stm));
+  // E = S^T S - I of the contracted sketch (computed by contract), B, S and
+  // cs: contiguous in both state blocks
+  HIPCHK(c, hipMemcpyAsync(c->E, c->hE, c->bytes_push, hipMemcpyHostToDevice, stm));
   c->j = c->keff;
   c->pending = 0;
   return RKS_OK;
@@ -611,7 +623,7 @@ int ensure_resid_scratch(rks_ctx* c) {
   if (!c->Xr && hipMalloc(&c->Xr, (size_t)c->n * cols * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "residual X");
   if (!c->ax1 && hipMalloc(&c->ax1, (size_t)c->n * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "residual AX");
   if (!c->ax2 && hipMalloc(&c->ax2, (size_t)c->n * 8) != hipSuccess) return fail(c, RKS_ENOMEM, "residual AX");
-  if (!c->rpart && hipMalloc(&c->rpart, (size_t)2 * rks::kMaxG * 8) != hipSuccess)
+  if (!c->rpart && hipMalloc(&c->rpart, cols * 2 * rks::kMaxG * 8) != hipSuccess)
     return fail(c, RKS_ENOMEM, "residual partials");
   return RKS_OK;
 }
@@ -631,31 +643,43 @@ int device_residuals(rks_ctx* c, const Packed& P, double* Xd, double* resid, boo
     rks::launch_rotate(c->env, c->U, c->ldu, 0, ke, Xd, n, c0, kc, c->Yd, -1, 0, 0.0, 1);
     HIPCHK(c, hipStreamSynchronize(stm));  // hY is reused by the next chunk
   }
-  std::vector<double> hpart(2 * rks::kMaxG);
+  // every pair's products and partial sums first (slot s of rpart, stride
+  // 2 G), then one copy and one synchronisation for all of them; the AX
+  // buffers are reused in stream order
+  std::vector<int> first;
+  int G = 0;
   for (int i = 0; i < ke;) {
     const bool cp = P.pair_of[i] == 1;
     double* xa = Xd + (size_t)i * n;
     double* xb = cp ? Xd + (size_t)(i + 1) * n : nullptr;
     rks::launch_spmv_sketch(c->env, xa, c->ax1, nullptr, 0, 0);
     if (cp) rks::launch_spmv_sketch(c->env, xb, c->ax2, nullptr, 0, 0);
-    const int G = rks::launch_resid(c->env, xa, xb, c->ax1, cp ? c->ax2 : nullptr, P.lam[i].real(),
-                                    P.lam[i].imag(), c->rpart);
-    HIPCHK(c, hipMemcpyAsync(hpart.data(), c->rpart, (size_t)2 * G * 8, hipMemcpyDeviceToHost, stm));
-    HIPCHK(c, hipStreamSynchronize(stm));
+    G = rks::launch_resid(c->env, xa, xb, c->ax1, cp ? c->ax2 : nullptr, P.lam[i].real(), P.lam[i].imag(),
+                          c->rpart + first.size() * 2 * rks::kMaxG);
+    first.push_back(i);
+    i += cp ? 2 : 1;
+  }
+  HIPCHK(c, hipGetLastError());
+  std::vector<double> hpart(first.size() * 2 * rks::kMaxG);
+  HIPCHK(c, hipMemcpyAsync(hpart.data(), c->rpart, hpart.size() * 8, hipMemcpyDeviceToHost, stm));
+  HIPCHK(c, hipStreamSynchronize(stm));
+  for (size_t sl = 0; sl < first.size(); ++sl) {
+    const int i = first[sl];
+    const bool cp = P.pair_of[i] == 1;
+    const double* hp = &hpart[sl * 2 * rks::kMaxG];
     double rr = 0.0, xx = 0.0;
     for (int g = 0; g < G; ++g) {
-      rr += hpart[2 * g];
-      xx += hpart[2 * g + 1];
+      rr += hp[2 * g];
+      xx += hp[2 * g + 1];
     }
     const double res = std::sqrt(rr) / (c->normA1 * std::sqrt(xx));
     if (normalise) {
       const double sc = 1.0 / std::sqrt(xx);
-      rks::launch_scale(c->env, xa, sc);
-      if (cp) rks::launch_scale(c->env, xb, sc);
+      rks::launch_scale(c->env, Xd + (size_t)i * n, sc);
+      if (cp) rks::launch_scale(c->env, Xd + (size_t)(i + 1) * n, sc);
     }
     resid[i] = res;
     if (cp) resid[i + 1] = res;
-    i += cp ? 2 : 1;
   }
   HIPCHK(c, hipGetLastError());
   return RKS_OK;
@@ -801,13 +825,13 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 }
 
 void free_all(rks_ctx* c) {
-  void* dev[] = {c->rp, c->col, c->tiles, c->flags, c->val, c->val32, c->U_lo, c->U64, c->w, c->S, c->B, c->cs,
-                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->E, c->kpart,
+  void* dev[] = {c->rp, c->col, c->tiles, c->dstate, c->val, c->val32, c->U_lo, c->U64, c->w,
+                 c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->kpart,
                  c->rp_cb, c->col_cb, c->tiles_cb, c->val_cb, c->val32_cb, c->P,
                  c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  void* host[] = {c->hB, c->hS, c->hcs, c->hY, c->hE, c->hflags};
+  void* host[] = {c->hstate, c->hY};
   for (void* p : host)
     if (p) (void)hipHostFree(p);
   for (auto e : c->pool) (void)hipEventDestroy(e);
@@ -1023,26 +1047,29 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm(&c->U_lo, (size_t)c->ldu * (m + 1) * c->vbytes);
   c->U = c->U_lo;
   dm(&c->w, (size_t)c->ldu * 8);
-  dm((void**)&c->S, (size_t)d * (m + 1) * 8);
-  dm((void**)&c->B, (size_t)(m + 1) * m * 8);
-  dm((void**)&c->cs, (size_t)(m + 1) * 8);
+  // state block: E ((m+1)^2) | B ((m+1) m) | S (d (m+1)) | cs (m+1) | flags (4 int32), FP64 offsets
+  const size_t oE = 0, oB = oE + (size_t)(m + 1) * (m + 1), oS = oB + (size_t)(m + 1) * m,
+               oC = oS + (size_t)d * (m + 1), oF = oC + (size_t)(m + 1), state_bytes = (oF + 2) * 8;
+  dm(&c->dstate, state_bytes);
+  hm(&c->hstate, state_bytes);
+  if (ok) {
+    double* ds = (double*)c->dstate;
+    double* hs = (double*)c->hstate;
+    c->E = ds + oE; c->B = ds + oB; c->S = ds + oS; c->cs = ds + oC; c->flags = (int*)(ds + oF);
+    c->hE = hs + oE; c->hB = hs + oB; c->hS = hs + oS; c->hcs = hs + oC; c->hflags = (int*)(hs + oF);
+    c->bytes_pull = (oF + 2 - oB) * 8;
+    c->bytes_push = (oF - oE) * 8;
+  }
   dm((void**)&c->coef, (size_t)(m + 2) * 8);
   dm((void**)&c->z, (size_t)d * 8);
   dm((void**)&c->sr, (size_t)d * 8);
   dm((void**)&c->zpart, (size_t)rks::kMaxG * d * 8);
   dm((void**)&c->spart, (size_t)rks::kMaxG * d * 8);
   dm((void**)&c->scal, 8 * 8);
-  dm((void**)&c->flags, 4 * 4);
   dm((void**)&c->Yd, (size_t)(m + 1) * (m + 1) * 8);
   dm((void**)&c->u0tmp, (size_t)n * 8);
-  dm((void**)&c->E, (size_t)(m + 1) * (m + 1) * 8);
   if (o.method == RKS_METHOD_KS_CGS2) dm((void**)&c->kpart, (size_t)rks::kMaxG * (m + 1) * 8);
-  hm((void**)&c->hB, (size_t)(m + 1) * m * 8);
-  hm((void**)&c->hS, (size_t)d * (m + 1) * 8);
-  hm((void**)&c->hcs, (size_t)(m + 1) * 8);
   hm((void**)&c->hY, (size_t)(m + 1) * (m + 1) * 8);
-  hm((void**)&c->hE, (size_t)(m + 1) * (m + 1) * 8);
-  hm((void**)&c->hflags, 4 * 4);
   if (!ok) {
     free_all(c);
     delete c;
