@@ -58,21 +58,25 @@ __device__ __forceinline__ void bins_store(const double* bins, double* part, int
 
 // ---------------------------------------------------------------------------
 // Row sums of one wave tile {first row r0, rows nr, first nonzero e0,
-// nonzeros ne} of a CSR matrix times x.  A lane loads up to 8 nonzeros
-// (coalesced, all loads issued before any use), gathers x for them, and
+// nonzeros ne} of a CSR matrix times x.  A lane loads up to 4 pairs of
+// nonzeros (8-byte column and 8- or 16-byte value loads, coalesced, all issued
+// before any use; pairs start at the even index at or below e0, and the
+// arrays carry kCsrPad readable entries at the end), gathers x for them, and
 // stages the products in the wave's own LDS slice pw; then 64/nr lanes per
 // row reduce the row from LDS.  LDS operations of one wave complete in program
 // order, so the wave needs no block-level barrier.  A tile that is a single
-// row longer than 512 nonzeros is reduced by the whole wave.  The row sum ends
+// row longer than kTileFill nonzeros is reduced by the whole wave.  The row sum ends
 // in the lane with sub == 0 of row rr (< nr).  after_loads(rr, sub) runs while
 // the loads are in flight (independent work can hide under them).
 template <typename TV, typename TA, typename F>
 __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* __restrict__ col,
                                         const TA* __restrict__ val, const TV* __restrict__ x, int4 dsc, TA* pw,
                                         int lane, int& rr, int& sub, F&& after_loads) {
+  typedef TA TA2 __attribute__((ext_vector_type(2)));
+  constexpr int NP = kTileNnz / 128;  // pairs per lane
   const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
   TA s = 0;
-  if (ne <= kTileNnz) {
+  if (ne <= kTileFill) {
     int lpr = 64;
     while (lpr > 1 && lpr * nr > 64) lpr >>= 1;
     rr = lane / lpr;
@@ -82,27 +86,35 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
       ra = rp[r0 + rr] - e0;
       rb = rp[r0 + rr + 1] - e0;
     }
-    int ci[kTileNnz / 64];
-    TA vv[kTileNnz / 64];
+    // pair p covers tile entries 2p - sh and 2p + 1 - sh (ne + sh <= 2 NP 64)
+    const int e0a = e0 & ~1, sh = e0 - e0a, nea = ne + sh;
+    int2 ci[NP];
+    TA2 vv[NP];
 #pragma unroll
-    for (int u = 0; u < kTileNnz / 64; ++u) {
-      const int e = lane + 64 * u;
-      if (e < ne) {
-        ci[u] = col[e0 + e];
-        vv[u] = val[e0 + e];
+    for (int u = 0; u < NP; ++u) {
+      const int p2 = 2 * (lane + 64 * u);
+      if (p2 < nea) {
+        ci[u] = *(const int2*)(col + e0a + p2);
+        vv[u] = *(const TA2*)(val + e0a + p2);
       }
     }
     after_loads(rr, sub);
-    TA xv[kTileNnz / 64];
+    TA xa[NP], xb[NP];
 #pragma unroll
-    for (int u = 0; u < kTileNnz / 64; ++u) {
-      const int e = lane + 64 * u;
-      if (e < ne) xv[u] = (TA)Conv<TV>::ld(x[ci[u]]);
+    for (int u = 0; u < NP; ++u) {
+      const int p2 = 2 * (lane + 64 * u);
+      if (p2 < nea) {
+        if (p2 >= sh) xa[u] = (TA)Conv<TV>::ld(x[ci[u].x]);
+        if (p2 + 1 < nea) xb[u] = (TA)Conv<TV>::ld(x[ci[u].y]);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kTileNnz / 64; ++u) {
-      const int e = lane + 64 * u;
-      if (e < ne) pw[e] = vv[u] * xv[u];
+    for (int u = 0; u < NP; ++u) {
+      const int p2 = 2 * (lane + 64 * u);
+      if (p2 < nea) {
+        if (p2 >= sh) pw[p2 - sh] = vv[u].x * xa[u];
+        if (p2 + 1 < nea) pw[p2 + 1 - sh] = vv[u].y * xb[u];
+      }
     }
     __builtin_amdgcn_wave_barrier();
     if (rr < nr)
@@ -663,10 +675,12 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
 }
 
 // O(:, out0 + o) = sum_l U(:, in0 + l) Y(l, o) for o < kout on the FP64
-// matrix cores (v_mfma_f64_16x16x4f64).  A wave owns a 16-row tile: lane
-// (r, k) = (lane % 16, lane / 16) feeds A(r, k) = U(row0 + r, in0 + k0 + k) and
-// B(k, c) = Y(k0 + k, 16 nt + c) for c = lane % 16; the accumulator holds
-// D(lane / 16 + 4 i, lane % 16), i < 4.  The wave reads every input column
+// matrix cores (v_mfma_f64_16x16x4f64), computed transposed: D = Y^T U^T
+// for a 16-row tile.  Lane (r, k) = (lane % 16, lane / 16) feeds
+// A(r, k) = Y(k0 + k, 16 nt + r) and B(k, c) = U(row0 + c, in0 + k0 + k) for
+// c = lane % 16; the accumulator holds D(lane / 16 + 4 i, lane % 16), i.e.
+// output column 16 nt + lane / 16 + 4 i of row row0 + lane % 16, so one store
+// instruction writes 16 consecutive rows (128 bytes) of each of 4 columns.  The wave reads every input column
 // of its rows before it writes any output, so outputs may overlap inputs
 // (in-place restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -707,16 +721,15 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
       for (int s = 0; s < 4; ++s) {
         const double* yk = Ys + (size_t)(k0 + 4 * s + lk) * KC + lr;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], yk[16 * t], acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yk[16 * t], a[s], acc[t], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int oc = 16 * t + lr;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t orow = tile * 16 + lk + 4 * i;
-        if (orow < n && oc < kout) O[orow + (int64_t)(out0 + oc) * ldo] = Conv<TO>::st(acc[t][i]);
+        const int oc = 16 * t + lk + 4 * i;
+        if (rin && oc < kout) O[row + (int64_t)(out0 + oc) * ldo] = Conv<TO>::st(acc[t][i]);
       }
     }
     if (xsrc >= 0 && lk == 0 && rin) ((TI*)U)[row + (int64_t)xdst * ldu] = Conv<TI>::st(xe);

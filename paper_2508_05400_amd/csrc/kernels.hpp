@@ -21,7 +21,10 @@ constexpr int kMaxD = 1024;      // largest sketch size (LDS bins)
 constexpr int kMaxM = 255;       // largest Krylov dimension
 constexpr int kMaxG = 512;       // largest number of partial-sum rows (producer blocks)
 constexpr int kTileRows = 64;    // rows per SpMV wave tile
-constexpr int kTileNnz = 512;    // nonzeros staged per SpMV wave tile
+constexpr int kTileNnz = 512;    // nonzeros staged per SpMV wave tile (LDS slice)
+constexpr int kTileFill = kTileNnz - 2;  // nonzeros a tile may hold: paired loads start at the even
+                                         // index at or below its first nonzero
+constexpr int kCsrPad = 2;       // readable padding entries after col[] and val[] (paired loads)
 constexpr int kRotMax = 64;      // output columns per rotation pass
 constexpr size_t kLsLdsMax = 150 * 1024;  // LDS budget of the least-squares kernel
 

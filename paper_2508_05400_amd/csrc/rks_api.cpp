@@ -939,10 +939,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     for (int64_t r = 0; r < n;) {
       const int64_t s0 = r;
       int64_t acc = 0;
-      if (rpx[r + 1] - rpx[r] > rks::kTileNnz) {
+      if (rpx[r + 1] - rpx[r] > rks::kTileFill) {
         ++r;
       } else {
-        while (r < n && r - s0 < rks::kTileRows && acc + (rpx[r + 1] - rpx[r]) <= rks::kTileNnz) {
+        while (r < n && r - s0 < rks::kTileRows && acc + (rpx[r + 1] - rpx[r]) <= rks::kTileFill) {
           acc += rpx[r + 1] - rpx[r];
           ++r;
         }
@@ -1032,15 +1032,16 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     }
   };
   dm((void**)&c->rp, (n + 1) * 4);
-  dm((void**)&c->col, nnz * 4);
-  dm((void**)&c->val, nnz * 8);
-  if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nnz * 4);
+  const int64_t nzp = nnz + rks::kCsrPad;  // padded: the SpMV reads nonzeros in aligned pairs
+  dm((void**)&c->col, nzp * 4);
+  dm((void**)&c->val, nzp * 8);
+  if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nzp * 4);
   dm((void**)&c->tiles, tdesc.size() * 4);
   if (use_cb) {
     dm((void**)&c->rp_cb, rp_cb.size() * 4);
-    dm((void**)&c->col_cb, (size_t)nnz * 4);
-    dm((void**)&c->val_cb, (size_t)nnz * 8);
-    if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32_cb, (size_t)nnz * 4);
+    dm((void**)&c->col_cb, (size_t)nzp * 4);
+    dm((void**)&c->val_cb, (size_t)nzp * 8);
+    if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32_cb, (size_t)nzp * 4);
     dm((void**)&c->tiles_cb, tdesc_cb.size() * 4);
     dm(&c->P, (size_t)rks::kCb * c->ldu * 8);
   }
@@ -1097,6 +1098,16 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     }
     cp(c->tiles_cb, tdesc_cb.data(), tdesc_cb.size() * 4);
   }
+  auto zero_pad = [&](void* p, size_t esz) {
+    if (rc == RKS_OK && p && hipMemset((char*)p + (size_t)nnz * esz, 0, rks::kCsrPad * esz) != hipSuccess)
+      rc = RKS_EHIP;
+  };
+  zero_pad(c->col, 4);
+  zero_pad(c->val, 8);
+  zero_pad(c->val32, 4);
+  zero_pad(c->col_cb, 4);
+  zero_pad(c->val_cb, 8);
+  zero_pad(c->val32_cb, 4);
   if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
   // padding rows of U and w stay zero for the whole life of the context
   if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;

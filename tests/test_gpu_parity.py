@@ -350,3 +350,33 @@ def test_restart_size_resolution_and_limits(lib, cuda):
         with pytest.raises(P.RksError) as ei:
             P.Solver.from_csr(A, k=6, m=24 if bad != 64 else 100, d=130, which="LR", tol=1e-6, keep=bad)
         assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("n,d", [(20011, 1023), (36, 9), (16400, 241)])
+def test_gaussian_sketch_grid_edges(lib, cuda, n, d):
+    """The Gaussian sketch kernel's blocking: rows per block above the
+    32-row minimum (n > 512 * 32), an odd d (the last pair has one row), up
+    to 8 pair-blocks (d = 1023), and a matrix smaller than one block; both
+    the stand-alone sketch and the one applied after the SpMV."""
+    A = convdiff2d(6, (2.0, 1.0)) if n == 36 else powerlaw_random(n, 6)
+    assert A.n == n
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 2, 6, d, "LM", 1e-10,
+                       P.rks_opts_default(sketch_kind="gauss", sketch_seed=13))
+    try:
+        x = start_vector_normal(A.n, 5)
+        om = sketch_matrix(A.n, d, "gauss", 13)
+        z = cuda.zeros(d, dtype=cuda.float64, device="cuda")
+        P.rks_sketch(ctx, dev(cuda, x), z)
+        ref = np.asarray(om @ x).ravel()
+        bound = np.asarray(abs(om) @ np.abs(x)).ravel()
+        err = np.abs(z.cpu().numpy() - ref)
+        assert np.all(err <= 64 * U64 * bound + 1e-300), (err.max(), bound.max())
+        w = cuda.zeros(A.n, dtype=cuda.float64, device="cuda")
+        P.rks_spmv_sketch(ctx, dev(cuda, x), w, z)
+        wref = sp_of(A) @ x
+        ref = np.asarray(om @ w.cpu().numpy()).ravel()
+        bound = np.asarray(abs(om) @ np.abs(wref)).ravel()
+        err = np.abs(z.cpu().numpy() - ref)
+        assert np.all(err <= 64 * U64 * bound + 1e-300), (err.max(), bound.max())
+    finally:
+        P.rks_destroy(ctx)
