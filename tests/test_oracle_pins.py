@@ -356,3 +356,35 @@ def test_restart_size_converges_to_closed_form_with_less_work():
         RKSOracle(A, 6, 30, 80, "LR", keep=29)
     with pytest.raises(ValueError):
         RKSOracle(A, 6, 30, 80, "LR", keep=5)
+
+
+def test_rira_exact_shifts_span_equals_rks_truncation():
+    """Section 3.2 (equivalence with randomized implicitly restarted Arnoldi):
+    after one expansion, contracting by Schur reordering (rKS, the oracle)
+    and by implicit shifted QR with the unwanted Ritz values as exact shifts
+    (rIRA, written out here in complex arithmetic) give the same subspace."""
+    import scipy.linalg as sla
+    A = convdiff2d(15, (3.0, 1.5))
+    k, m, d = 4, 10, 40
+    o = RKSOracle(A, k, m, d, "LR", 1e-10, sketch="gauss", sketch_seed=3, start_seed=2)
+    o.start()
+    o.extend()
+    H = o.B[:m, :m].astype(complex)
+    V = o.U[:, :m].astype(complex)
+    assert np.all(np.tril(o.B[:m, :m], -2) == 0)       # randomized Arnoldi: Hessenberg
+    o.contract()
+    ke = o.keff
+    lam = np.linalg.eigvals(H)
+    order = sorted(range(m), key=lambda i: which_key(lam[i], "LR"), reverse=True)
+    shifts = [lam[i] for i in order[ke:]]
+    for mu in shifts:
+        Q, _ = sla.qr(H - mu * np.eye(m))
+        H = Q.conj().T @ H @ Q
+        V = V @ Q
+    Q1, _ = np.linalg.qr(o.U[:, :ke])
+    Q2, _ = np.linalg.qr(V[:, :ke])
+    sin = np.linalg.norm(Q2 - Q1 @ (Q1.T @ Q2), 2)
+    assert sin < 1e-8, sin
+    # the measure discriminates: the next basis vector u_{k+1} lies outside that subspace
+    Q3, _ = np.linalg.qr(o.U[:, ke - 1:ke + 1])
+    assert np.linalg.norm(Q3 - Q1 @ (Q1.T @ Q3), 2) > 0.5
