@@ -201,6 +201,7 @@ def main():
     buf = torch.empty(2 * 1024**3 // 8, dtype=torch.float64, device="cuda")
     buf2 = torch.empty_like(buf)
     copy_gbs = P.rks_copy_probe(buf, buf2, buf.numel() * 8, 10, stream)
+    read_gbs = P.rks_read_probe(buf, buf.numel() * 8, 10, stream)
     del buf, buf2
     st = stats[-1]
     t_mean = float(np.mean(times))
@@ -253,7 +254,8 @@ def main():
                      "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
                      "traffic": counter_traffic(args.workload, cfg["precision"]),
                      "avg_launch_us": upd_avg * 1e6, "bytes_per_launch": upd_bytes,
-                     "copy_probe_gbs": copy_gbs},
+                     "copy_probe_gbs": copy_gbs, "read_probe_gbs": read_gbs,
+                     "frac_of_read_probe": (achieved / read_gbs) if achieved else None},
     }
     extra = {}
     for prec in [p for p in args.compare.split(",") if p]:

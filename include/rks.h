@@ -238,6 +238,11 @@ int rks_rotate(struct rks_ctx* ctx, int32_t in0, int32_t min, int32_t out0, int3
  * achieved GB/s (bytes read + written) in *gbs. */
 int rks_copy_probe(const void* src, void* dst, int64_t nbytes, int32_t iters, double* gbs, void* stream);
 
+/* Bandwidth reference for read-dominated kernels: streams nbytes (multiple
+ * of 16) of src (device, only read) iters times and returns the achieved
+ * GB/s (bytes read) in *gbs. */
+int rks_read_probe(const void* src, int64_t nbytes, int32_t iters, double* gbs, void* stream);
+
 /* Host small dense FP64 helpers used by the contraction step (no device
  * work): real Schur form of A (n x n, in place, lda = n) with Schur vectors
  * Z; reordering of the `which`-wanted kw eigenvalues to the front

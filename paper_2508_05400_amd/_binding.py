@@ -91,6 +91,7 @@ SIGNATURES = {
                                     ctypes.c_float, _I32, _P]),
     "rks_net_upsample": (ctypes.c_int, [_P, _I32, _I32, _P, _I32, _I32, _P]),
     "rks_copy_probe": (ctypes.c_int, [_P, _P, _I64, _I32, ctypes.POINTER(_D), _P]),
+    "rks_read_probe": (ctypes.c_int, [_P, _I64, _I32, ctypes.POINTER(_D), _P]),
 }
 
 _lib = None
@@ -306,6 +307,13 @@ def rks_net_adam(w, g, m, v, n, lr, t, b1=0.9, b2=0.999, eps=1e-8, stream=None) 
 
 def rks_net_upsample(u, h, w, out, H, W, stream=None) -> int:
     return _check(None, load().rks_net_upsample(_ptr(u), h, w, _ptr(out), H, W, _stream(stream)))
+
+
+def rks_read_probe(src, nbytes, iters=20, stream=None) -> float:
+    """Achieved GB/s of a plain streaming read of nbytes of a device buffer."""
+    g = ctypes.c_double(0.0)
+    _check(None, load().rks_read_probe(_ptr(src), int(nbytes), int(iters), ctypes.byref(g), _stream(stream)))
+    return g.value
 
 
 def rks_copy_probe(src, dst, nbytes, iters=20, stream=None) -> float:

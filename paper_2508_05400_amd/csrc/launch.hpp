@@ -51,6 +51,7 @@ int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const d
 void launch_scale(const LaunchEnv& e, double* x, double s);
 void launch_fill(const LaunchEnv& e, int64_t len, double* x, double v);
 void launch_copy16(hipStream_t stream, const void* src, void* dst, int64_t packets);
+void launch_read16(hipStream_t stream, const void* src, int64_t packets);
 // Deterministic Krylov-Schur (Euclidean classical Gram-Schmidt, twice):
 // partials of U(:, 0:ncol)^T x (returns the number of partial rows), their sum,
 // the coefficients of one pass, and the closing of a step.

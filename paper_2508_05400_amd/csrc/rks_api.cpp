@@ -1365,6 +1365,24 @@ int rks_copy_probe(const void* src, void* dst, int64_t nbytes, int32_t iters, do
   return RKS_OK;
 }
 
+int rks_read_probe(const void* src, int64_t nbytes, int32_t iters, double* gbs, void* stream) {
+  if (!src || nbytes < 16 || nbytes % 16 != 0 || iters < 1 || !gbs) return RKS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RKS_EHIP;
+  rks::launch_read16(st, src, nbytes / 16);  // warm-up
+  (void)hipEventRecord(a, st);
+  for (int i = 0; i < iters; ++i) rks::launch_read16(st, src, nbytes / 16);
+  (void)hipEventRecord(b, st);
+  float ms = 0.f;
+  const bool ok = hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (!ok || ms <= 0.f) return RKS_EHIP;
+  *gbs = (double)nbytes * iters / (ms * 1e-3) / 1e9;
+  return RKS_OK;
+}
+
 int rks_host_schur(int32_t n, double* A, double* Z) {
   if (n < 1 || !A || !Z) return RKS_EINVAL;
   return rks::real_schur(n, A, n, Z, n) == 0 ? RKS_OK : RKS_EDENSE;
