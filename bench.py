@@ -27,13 +27,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
-def cpu_baseline(A, cfg, restarts_gpu: int, keep: int, budget_s: float = 25.0):
+def _oracle_sample(A, cfg, restarts_gpu: int, keep: int, budget_s: float):
     """Time the FP64 oracle on a bounded sample: its first extension plus as
-    many restart cycles as fit in the budget, extrapolated to the GPU's
-    restart count (seconds, same unit as the metric)."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
-
+    many restart cycles as fit in the budget; returns (estimate for the GPU's
+    restart count in seconds, first-extension seconds, cycles, seconds per cycle)."""
     from oracle.rks import RKSOracle
     o = RKSOracle(A, cfg["k"], cfg["m"], cfg["d"], cfg["which"], cfg["tol"], sketch=cfg["sketch"],
                   zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"], start_seed=cfg["start_seed"],
@@ -51,15 +48,27 @@ def cpu_baseline(A, cfg, restarts_gpu: int, keep: int, budget_s: float = 25.0):
             o.lock_converged()
         o.extend()
         cycles += 1
-    t_cycles = time.perf_counter() - t1
-    per = t_cycles / max(cycles, 1)
-    est = t_first + per * restarts_gpu
+    per = (time.perf_counter() - t1) / max(cycles, 1)
+    return t_first + per * restarts_gpu, t_first, cycles, per, o.keep
+
+
+def cpu_baseline(A, cfg, restarts_gpu: int, keep: int, budget_s: float = 25.0, budget_1t_s: float = 12.0):
+    """The FP64 oracle timed on the host (all BLAS threads, then one thread),
+    each on a bounded sample extrapolated to the GPU's restart count
+    (seconds, same unit as the metric)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    est, t_first, cycles, per, kp = _oracle_sample(A, cfg, restarts_gpu, keep, budget_s)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    with threadpool_limits(limits=1):
+        est1, t_first1, cycles1, per1, _ = _oracle_sample(A, cfg, restarts_gpu, keep, budget_1t_s)
     return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
             "sample": (f"first extension ({cfg['m']} Arnoldi steps, {t_first:.2f}s) + {cycles} restart "
-                       f"cycles (keep {o.keep}; "
-                       f"{per:.2f}s each) of the same workload, extrapolated to the GPU's "
+                       f"cycles (keep {kp}; {per:.2f}s each) of the same workload, extrapolated to the GPU's "
                        f"{restarts_gpu} restarts"),
+            "single_thread": {"value": est1, "cores": 1,
+                              "sample": (f"first extension ({t_first1:.2f}s) + {cycles1} restart cycles "
+                                         f"({per1:.2f}s each), same extrapolation")},
             "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
