@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 
 def _oracle_sample(A, cfg, restarts_gpu: int, keep: int, budget_s: float):
     """Time the FP64 oracle on a bounded sample: its first extension plus as
-    many restart cycles as fit in the budget; returns (estimate for the GPU's
+    many restart cycles as fit in the budget (at least one); returns (estimate for the GPU's
     restart count in seconds, first-extension seconds, cycles, seconds per cycle)."""
     from oracle.rks import RKSOracle
     o = RKSOracle(A, cfg["k"], cfg["m"], cfg["d"], cfg["which"], cfg["tol"], sketch=cfg["sketch"],
@@ -41,7 +41,9 @@ def _oracle_sample(A, cfg, restarts_gpu: int, keep: int, budget_s: float):
     t_first = time.perf_counter() - t0
     cycles = 0
     t1 = time.perf_counter()
-    while cycles < max(restarts_gpu, 1) and (time.perf_counter() - t0) < budget_s:
+    # at least one cycle, so that the per-cycle time is measured even when the
+    # first extension alone exceeds the budget
+    while cycles < max(restarts_gpu, 1) and (cycles == 0 or (time.perf_counter() - t0) < budget_s):
         o.contract()
         o.ritz()
         if o.lock:
