@@ -2,6 +2,9 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 
+#include <mutex>
+#include <unordered_map>
+
 namespace rks {
 
 __device__ uint32_t g_read_sink[8192];  // written by k_read16 in the rare case described there
@@ -50,12 +53,26 @@ __device__ __forceinline__ double readlane_f64(double v, int j) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Sketch bins in dynamic LDS, one set of d per wave: wave w adds into
+// bins + w d only, so no two waves add to the same word and a wave's adds
+// follow its program order; bins_store then adds the waves' bins in wave
+// order.  The partial rows are the same on every run.
 __device__ __forceinline__ void bins_zero(double* bins, int d) {
-  for (int b = threadIdx.x; b < d; b += blockDim.x) bins[b] = 0.0;
+  const int nb = d * (int)(blockDim.x >> 6);
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) bins[b] = 0.0;
 }
 
 __device__ __forceinline__ void bins_store(const double* bins, double* part, int d, double scale) {
-  for (int b = threadIdx.x; b < d; b += blockDim.x) part[(size_t)blockIdx.x * d + b] = bins[b] * scale;
+  const int nw = blockDim.x >> 6;
+  for (int b = threadIdx.x; b < d; b += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += bins[w * d + b];
+    part[(size_t)blockIdx.x * d + b] = s * scale;
+  }
+}
+
+__device__ __forceinline__ double* wave_bins(double* bins, int d) {
+  return bins + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * d;
 }
 
 // ---------------------------------------------------------------------------
@@ -141,7 +158,7 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
                                                      const TA* __restrict__ val, const int4* __restrict__ tdesc,
                                                      int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
                                                      double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
-  __shared__ double bins[kMaxD];
+  extern __shared__ double bins[];  // 8 waves x d
   __shared__ TA prod[8][kTileNnz];
   const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -149,6 +166,7 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
   TA* pw = prod[wv];
+  double* wb = wave_bins(bins, sp.d);
   const int Gx = gridDim.x >> 3;
   int t0, tend, tstep;
   if (Gx > 0 && (gridDim.x & 7) == 0) {
@@ -184,9 +202,9 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
         if (KIND == 1 && have) {
 #pragma unroll
           for (int q = 0; q < 8; ++q)
-            if (q < sp.zeta) atomicAdd(&bins[hrows[q]], (double)hsg[q] * (double)ws);
+            if (q < sp.zeta) atomicAdd(&wb[hrows[q]], (double)hsg[q] * (double)ws);
         } else {
-          sketch_add<KIND>(bins, (uint64_t)r, (double)ws, sp);
+          sketch_add<KIND>(wb, (uint64_t)r, (double)ws, sp);
         }
       }
     }
@@ -227,10 +245,11 @@ template <typename TW, int KIND>
 __global__ __launch_bounds__(512) void k_cb_combine(int64_t n, const TW* __restrict__ P, int64_t ldp,
                                                     TW* __restrict__ w, double* __restrict__ zpart, SketchP sp,
                                                     int do_sketch_arg) {
-  __shared__ double bins[kMaxD];
+  extern __shared__ double bins[];  // 8 waves x d
   const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
+  double* wb = wave_bins(bins, sp.d);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     TW v[kCb];
@@ -241,7 +260,7 @@ __global__ __launch_bounds__(512) void k_cb_combine(int64_t n, const TW* __restr
     for (int c = 0; c < kCb; ++c) s += (double)v[c];
     const TW ws = (TW)s;
     w[i] = ws;
-    if (do_sketch) sketch_add<KIND>(bins, (uint64_t)i, (double)ws, sp);
+    if (do_sketch) sketch_add<KIND>(wb, (uint64_t)i, (double)ws, sp);
   }
   __syncthreads();
   if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
@@ -486,9 +505,10 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
                                                 double* __restrict__ spart, SketchP sp) {
   constexpr int V = 16 / sizeof(TV);
   constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
-  __shared__ double bins[kMaxD];
-  bins_zero(bins, sp.d);
+  extern __shared__ double bins[];  // 16 waves x d (none for KIND 3)
+  if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
+  double* wb = wave_bins(bins, sp.d);
   const double ws = coef[ncol];
   double nrm = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -533,12 +553,12 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
       if (i0 + r >= n) continue;
       const double v = Conv<TV>::ld(o.v[r]);
       if (KIND == 2) nrm += v * v;
-      else sketch_add<KIND>(bins, (uint64_t)(i0 + r), v, sp);
+      else sketch_add<KIND>(wb, (uint64_t)(i0 + r), v, sp);
     }
   }
   if (KIND == 2) {  // Euclidean inner product (deterministic Krylov-Schur): ||u~||^2 partial
     nrm = wave_sum(nrm);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&bins[0], nrm);
+    if ((threadIdx.x & 63) == 0) wb[0] = nrm;
   }
   if (KIND == 3) return;
   __syncthreads();
@@ -576,10 +596,10 @@ template <typename TV, typename TX>
 __global__ __launch_bounds__(1024) void k_dots(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U,
                                                int64_t ldu, const TX* __restrict__ x, double* __restrict__ part) {
   constexpr int V = 16 / sizeof(TV);
-  __shared__ double bins[kMaxM + 8];
-  for (int b = threadIdx.x; b < ncol; b += blockDim.x) bins[b] = 0.0;
+  __shared__ double bins[16][kMaxM + 8];  // one row per wave, added in wave order at the end
+  for (int b = threadIdx.x; b < 16 * (kMaxM + 8); b += blockDim.x) bins[b / (kMaxM + 8)][b % (kMaxM + 8)] = 0.0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t gs = (int64_t)blockIdx.x * blockDim.x; gs < npk; gs += stride) {  // block-uniform trip count
     const int64_t g = gs + threadIdx.x;
@@ -603,11 +623,16 @@ __global__ __launch_bounds__(1024) void k_dots(int64_t n, int64_t npk, int ncol,
       }
       const double sv = wave_sum8(v, lane);
       const int c = l0 + ((lane >> 3) & 7);
-      if ((lane & 7) == 0 && c < ncol) atomicAdd(&bins[c], sv);
+      if ((lane & 7) == 0 && c < ncol) bins[wv][c] += sv;
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < ncol; b += blockDim.x) part[(size_t)blockIdx.x * ncol + b] = bins[b];
+  const int nw = blockDim.x >> 6;
+  for (int b = threadIdx.x; b < ncol; b += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += bins[q][b];
+    part[(size_t)blockIdx.x * ncol + b] = t;
+  }
 }
 
 // Coefficients of one classical Gram-Schmidt pass from y_raw = sum of the
@@ -648,9 +673,10 @@ template <typename TV, int KIND>
 __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
                                               uint32_t s0, uint32_t s1, double* __restrict__ spart, SketchP sp,
                                               int store) {
-  __shared__ double bins[kMaxD];
-  bins_zero(bins, sp.d);
+  extern __shared__ double bins[];  // 8 waves x d (none for KIND 3)
+  if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
+  double* wb = wave_bins(bins, sp.d);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double nrm = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -665,11 +691,11 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
     if (store) u[i] = st;
     const double vs = Conv<TV>::ld(st);
     if (KIND == 2) nrm += vs * vs;
-    else sketch_add<KIND>(bins, (uint64_t)i, vs, sp);
+    else sketch_add<KIND>(wb, (uint64_t)i, vs, sp);
   }
   if (KIND == 2) {
     nrm = wave_sum(nrm);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&bins[0], nrm);
+    if ((threadIdx.x & 63) == 0) wb[0] = nrm;
   }
   if (KIND == 3) return;
   __syncthreads();
@@ -876,6 +902,24 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(int64_t n, const TX* __res
     }                                \
   } while (0)
 
+// Dynamic LDS of the per-wave sketch bins (waves x d FP64, none when the
+// kernel sketches nothing); above 48 KB the kernel's limit is raised once.
+static size_t bins_lds(const LaunchEnv& e, int waves, bool sketched) {
+  return sketched ? (size_t)waves * e.sp.d * 8 : 0;
+}
+
+static void lds_allow(const void* f, size_t bytes) {
+  if (bytes <= 48 * 1024) return;
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> raised;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = raised[f];
+  if (bytes > cur) {
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    cur = bytes;
+  }
+}
+
 // The Gaussian sketch of x (n entries of type TX) as partial rows of part;
 // returns the number of rows (<= kMaxG).
 template <typename TX>
@@ -897,8 +941,10 @@ static int spmv_cb_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, doub
   k_spmv_cb<TV, TW, TA><<<G1, 512, 0, e.stream>>>(e.n, e.rp_cb, e.col_cb, val, (const int4*)e.tiles_cb, e.cbt, x,
                                                   (TW*)e.P, e.ldu);
   const int G2 = grid_for(e.n, 512, kMaxG);
-  RKS_SKETCH_SWITCH(e.sp_kind, (k_cb_combine<TW, KIND><<<G2, 512, 0, e.stream>>>(e.n, (const TW*)e.P, e.ldu, w, zpart,
-                                                                                e.sp, do_sketch)));
+  const size_t lds = bins_lds(e, 8, do_sketch && e.sp_kind == 1);
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_cb_combine<TW, KIND>, lds);
+                    k_cb_combine<TW, KIND><<<G2, 512, lds, e.stream>>>(e.n, (const TW*)e.P, e.ldu, w, zpart, e.sp,
+                                                                       do_sketch));
   if (do_sketch && e.sp_kind == 0) return gauss_t<TW>(e, w, zpart);
   return G2;
 }
@@ -913,18 +959,22 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
   int G = grid_for(e.ntiles, 8, kMaxG);
   if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the tile mapping)
   dim3 grid(G), block(512);
+  const size_t lds = bins_lds(e, 8, do_sketch && e.sp_kind == 1);
   if (prec == 0) {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<double, double, double, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.rp, e.col, e.val, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
-                                     e.sp, do_sketch)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<double, double, double, KIND>, lds);
+                      k_spmv_sketch<double, double, double, KIND><<<grid, block, lds, e.stream>>>(
+                          e.rp, e.col, e.val, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w, zpart, e.sp,
+                          do_sketch));
   } else if (prec == 1) {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<float, float, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w, zpart,
-                                     e.sp, do_sketch)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<float, float, float, KIND>, lds);
+                      k_spmv_sketch<float, float, float, KIND><<<grid, block, lds, e.stream>>>(
+                          e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w, zpart, e.sp,
+                          do_sketch));
   } else {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_spmv_sketch<bf16_t, float, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
-                                     e.sp, do_sketch)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<bf16_t, float, float, KIND>, lds);
+                      k_spmv_sketch<bf16_t, float, float, KIND><<<grid, block, lds, e.stream>>>(
+                          e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart, e.sp,
+                          do_sketch));
   }
   if (do_sketch && e.sp_kind == 0)
     return prec == 0 ? gauss_t<double>(e, (const double*)w, zpart) : gauss_t<float>(e, (const float*)w, zpart);
@@ -959,18 +1009,19 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
   const int64_t npk = (e.n + V - 1) / V;
   const int G = grid_for(npk, 1024, kMaxG);
   dim3 grid(G), block(1024);
+  const size_t lds = bins_lds(e, 16, e.sp_kind != 0);
   if (e.prec == 0) {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_update<double, double, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.n, npk, ncol, (const double*)U, ldu, (const double*)w, coef, (double*)unew,
-                                     spart, e.sp)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_update<double, double, KIND>, lds);
+                      k_update<double, double, KIND><<<grid, block, lds, e.stream>>>(
+                          e.n, npk, ncol, (const double*)U, ldu, (const double*)w, coef, (double*)unew, spart, e.sp));
   } else if (e.prec == 1) {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_update<float, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.n, npk, ncol, (const float*)U, ldu, (const float*)w, coef, (float*)unew,
-                                     spart, e.sp)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_update<float, float, KIND>, lds);
+                      k_update<float, float, KIND><<<grid, block, lds, e.stream>>>(
+                          e.n, npk, ncol, (const float*)U, ldu, (const float*)w, coef, (float*)unew, spart, e.sp));
   } else {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_update<bf16_t, float, KIND><<<grid, block, 0, e.stream>>>(
-                                     e.n, npk, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew,
-                                     spart, e.sp)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_update<bf16_t, float, KIND>, lds);
+                      k_update<bf16_t, float, KIND><<<grid, block, lds, e.stream>>>(
+                          e.n, npk, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew, spart, e.sp));
   }
   if (e.sp_kind == 0) {  // sketch of the stored value
     if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
@@ -985,15 +1036,19 @@ int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint
   const int prec = prec_override >= 0 ? prec_override : e.prec;
   const int G = grid_for(e.n, 512, kMaxG);
   dim3 grid(G), block(512);
+  const size_t lds = bins_lds(e, 8, e.sp_kind != 0);
   if (prec == 0) {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_init<double, KIND><<<grid, block, 0, e.stream>>>(e.n, (double*)u, u0, s0, s1,
-                                                                                     spart, e.sp, store)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<double, KIND>, lds);
+                      k_init<double, KIND><<<grid, block, lds, e.stream>>>(e.n, (double*)u, u0, s0, s1, spart, e.sp,
+                                                                        store));
   } else if (prec == 1) {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_init<float, KIND><<<grid, block, 0, e.stream>>>(e.n, (float*)u, u0, s0, s1,
-                                                                                    spart, e.sp, store)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<float, KIND>, lds);
+                      k_init<float, KIND><<<grid, block, lds, e.stream>>>(e.n, (float*)u, u0, s0, s1, spart, e.sp,
+                                                                        store));
   } else {
-    RKS_SKETCH_SWITCH(e.sp_kind, (k_init<bf16_t, KIND><<<grid, block, 0, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1,
-                                                                                     spart, e.sp, store)));
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<bf16_t, KIND>, lds);
+                      k_init<bf16_t, KIND><<<grid, block, lds, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1, spart, e.sp,
+                                                                        store));
   }
   if (e.sp_kind == 0) {
     // sketch of the stored value; without a store, of u0 itself (FP64 only)
