@@ -3,6 +3,10 @@ small benchmark configuration: LR, k = 10, m = 40, Gaussian sketch d = 80,
 seeds 0 / 1) against the closed-form spectrum.
 
 The solve stops when every pair's FP64 residual is verified to be <= 1e-8.
+It keeps k + (m - k)/4 Schur vectors per restart: with Algorithm 1's
+truncation to k this strongly non-normal operator converges in about 130
+restarts or stalls at the 300-restart cap depending on the rounding order of
+the sums, while the larger restart size converges in about 34 either way.
 First-order perturbation theory bounds each eigenvalue's error by
 kappa(lambda) * ||A x - lambda x|| / ||x|| (kappa from the closed-form left
 and right eigenvectors); the bar is twice that bound.  The wanted set is
@@ -24,7 +28,7 @@ def test_cd2d_100_against_closed_form(lib, cuda):
     A = cfg["matrix"]()
     with P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                            sketch_kind=cfg["sketch"], sketch_seed=cfg["sketch_seed"],
-                           start_seed=cfg["start_seed"], resid_tol=1e-8) as s:
+                           start_seed=cfg["start_seed"], resid_tol=1e-8, keep=-1) as s:
         code = s.solve()
         print(f"cd2d-100: code {code} restarts {s.stats.restarts} stop {s.stats.stop_reason}", flush=True)
         assert code == 0, P.rks_last_error(s.ctx)
