@@ -207,7 +207,7 @@ class RKSOracle:
                 self.B[j + 1, j] = beta                    # augment Rayleigh quotient
         self.j = self.m
 
-    # -- Algorithm 1, lines 2-4 ---------------------------------------------
+    # -- Algorithm 1, contraction -------------------------------------------
     def contract(self):
         """Schur form of the active block, reorder the wanted eigenvalues to the
         front, truncate.  Leaves an rKS decomposition of order keff."""

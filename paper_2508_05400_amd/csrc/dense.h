@@ -1,13 +1,13 @@
 // Small dense FP64 linear algebra run on the host once per restart.
 //
-// The contraction step of randomized Krylov-Schur (Algorithm 1, lines 2-4)
+// The contraction step of randomized Krylov-Schur (Algorithm 1)
 // needs, for the m x m Rayleigh quotient (m <= a few hundred):
 //   * a real Schur form  B = Q T Q^T  (Proposition "realSchur"): Householder
 //     Hessenberg reduction followed by the Francis double-shift QR iteration;
 //   * reordering of the diagonal blocks by orthogonal similarity so that the
 //     wanted eigenvalues lead (Bai-Demmel direct swapping of adjacent 1x1/2x2
 //     blocks, the stable reordering the paper relies on);
-//   * eigenpairs of the truncated quasi-triangular factor (line 5) for the
+//   * eigenpairs of the truncated quasi-triangular factor for the
 //     residual estimates of Section 4.1;
 //   * a Householder QR of the sketched basis for whitening (Section 3.3).
 // All matrices are column-major with an explicit leading dimension.

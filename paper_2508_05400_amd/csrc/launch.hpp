@@ -19,7 +19,7 @@ struct LaunchEnv {
   const int* tiles;    // SpMV wave tiles: {first row, rows, first nonzero, nonzeros} per tile
   int ntiles;
   int64_t ldu;         // basis leading dimension (n rounded up to 128; padding rows are zero)
-  int sp_kind;         // 0 Gaussian, 1 sparse-sign
+  int sp_kind;         // 0 Gaussian (applied by k_gauss_sketch), 1 sparse-sign, 2 none (deterministic KS)
   SketchP sp;
   // column-blocked SpMV (used when cb = 1): kCb CSR blocks with global offsets
   int cb = 0;

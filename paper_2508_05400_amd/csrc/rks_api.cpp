@@ -2,8 +2,8 @@
 //
 // rks_solve runs Algorithm 1: the first extension (Algorithm 2 from one
 // column), then cycles of contraction (real Schur form of the active block,
-// reordering of the wanted Ritz values to the front, truncation; Algorithm 1,
-// lines 2-4), residual estimates (Section 4.1), locking (Section 4.4),
+// reordering of the wanted Ritz values to the front, truncation: the
+// contraction of Algorithm 1), residual estimates (Section 4.1), locking (Section 4.4),
 // optional whitening (Section 3.3), the basis rotation on the device and a
 // new extension.  Each cycle crosses the host/device boundary once: the
 // Rayleigh quotient B and the sketch S (both FP64, at most a few hundred KB)

@@ -1,5 +1,5 @@
 """CPU tests of the C-ABI library: exported symbols, host small dense code
-(real Schur form and reordering, Algorithm 1 lines 2-3) against LAPACK, and
+(real Schur form and reordering, the contraction of Algorithm 1) against LAPACK, and
 argument validation that rejects bad input before any device work."""
 import ctypes
 import os
