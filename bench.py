@@ -168,7 +168,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block "
-              "sharding is a design note, not part of this build", file=sys.stderr)
+              "sharding is described in the design notes but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
