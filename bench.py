@@ -162,6 +162,8 @@ def main():
                     help="time the kernels of every P-th Arnoldi step with HIP events (event records "
                          "cost a few microseconds each, so timing every launch would slow the solve)")
     ap.add_argument("--keep", default="auto", help="restart size: auto (k + (m-k)/4), or a number in [k, m-2]")
+    ap.add_argument("--graphs", type=int, default=0, help="1: replay repeated extensions as HIP graphs (used only "
+                    "when the per-kernel events are off, --no-profile); 0: launch every kernel")
     ap.add_argument("--compare", default="alg1,fp32,bf16", help="comma list of extra runs on the same workload after "
                     "the main run: alg1 (FP64, keep = k), basis precisions (fp32, bf16) and/or ks_cgs2 "
                     "(deterministic Krylov-Schur); reported under 'variants'")
@@ -190,7 +192,7 @@ def main():
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else args.profile_every,
-                               resid_tol=args.resid_tol, keep=keep, stream=stream)
+                               resid_tol=args.resid_tol, keep=keep, graphs=args.graphs, stream=stream)
     for _ in range(args.warmup):
         solver.solve()
     torch.cuda.synchronize()

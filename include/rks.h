@@ -126,6 +126,16 @@ typedef struct {
                             valid; convergence, locking and the returned pairs
                             still concern only the leading k (k + 1 for a pair).
                             Default 0. */
+  int32_t graphs;        /* 1: an extension (all Arnoldi steps of one restart
+                            cycle) whose start column, pending column and basis
+                            precision occurred before is recorded once as a HIP
+                            graph on a private stream and then replayed on the
+                            solver's stream (same kernels, same arguments, same
+                            results to the last bit); 0: launch every kernel.
+                            Not used when profile > 0 or for deterministic KS.
+                            Default 0: on the measured workloads the host stays
+                            ahead of the GPU, so replays save no time; they
+                            save host launch work. */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -97,6 +98,15 @@ struct rks_ctx {
   bool have_state = false, solved = false;
   std::vector<double> Tk, bk;
   std::string err;
+  // whole extensions recorded as HIP graphs, keyed by (start column, pending
+  // column, basis precision): the launch sequence and every kernel argument
+  // are fixed by that key, so the second occurrence of a key is recorded on a
+  // private stream and every later one replays the graph on the solver's stream
+  rks::LaunchEnv* lenv = nullptr;  // environment the step launchers use (env, or a copy while recording)
+  hipStream_t cap = nullptr;
+  std::map<int, hipGraphExec_t> gexec;
+  std::map<int, int> gseen;
+  std::map<int, std::pair<int, int>> gpart;  // G_z, G_s after the recorded extension
   // profiling
   std::vector<hipEvent_t> pool;
   std::vector<EvPair> open;
@@ -187,8 +197,10 @@ double spmv_bytes(const rks_ctx* c) {
 }
 
 // ---- one Arnoldi step (Algorithm 2 loop body) ------------------------------
+void account_step(rks_ctx* c, int t, bool timed, bool whole);
+
 int arnoldi_step(rks_ctx* c, int t) {
-  const auto& e = c->env;
+  const auto& e = *c->lenv;
   // sampled timing: every P-th step, alternately per kernel and as a whole
   // (one event pair around the four launches, for the loop's bandwidth)
   bool timed = false, whole = false;
@@ -215,26 +227,30 @@ int arnoldi_step(rks_ctx* c, int t) {
     Prof p(c, CAT_UPDATE, timed);
     c->G_s = rks::launch_update(e, t + 1, c->U, c->ldu, c->w, c->coef, basis_col(c, t + 1), c->spart);
   }
-  if (c->st) {
-    const double bs = spmv_bytes(c), bu = (double)(t + 2) * c->n * c->vbytes + (double)c->wbytes * c->n;
-    c->st->n_spmv += 1;
-    c->st->bytes_spmv += bs;
-    c->st->n_update += 1;
-    c->st->bytes_update += bu;
-    c->st->matvecs += 1;
-    if (timed) {
-      c->st->n_timed_steps += 1;
-      c->st->bytes_timed_spmv += bs;
-      c->st->bytes_timed_update += bu;
-    }
-    if (whole) {
-      c->st->n_timed_whole += 1;
-      c->st->bytes_timed_whole += bs + bu;
-    }
-  }
+  account_step(c, t, timed, whole);
   c->pending = 1;
   c->j = t + 1;
   return RKS_OK;
+}
+
+// Launch and byte counts of one randomized Arnoldi step.
+void account_step(rks_ctx* c, int t, bool timed, bool whole) {
+  if (!c->st) return;
+  const double bs = spmv_bytes(c), bu = (double)(t + 2) * c->n * c->vbytes + (double)c->wbytes * c->n;
+  c->st->n_spmv += 1;
+  c->st->bytes_spmv += bs;
+  c->st->n_update += 1;
+  c->st->bytes_update += bu;
+  c->st->matvecs += 1;
+  if (timed) {
+    c->st->n_timed_steps += 1;
+    c->st->bytes_timed_spmv += bs;
+    c->st->bytes_timed_update += bu;
+  }
+  if (whole) {
+    c->st->n_timed_whole += 1;
+    c->st->bytes_timed_whole += bs + bu;
+  }
 }
 
 // ---- one Arnoldi step of deterministic Krylov-Schur ------------------------
@@ -292,7 +308,7 @@ int arnoldi_step_ks(rks_ctx* c, int t) {
 }
 
 int finalize_last(rks_ctx* c) {
-  const auto& e = c->env;
+  const auto& e = *c->lenv;
   rks::launch_reduce(e, nullptr, 0, c->spart, c->G_s, c->z, c->sr);
   rks::launch_ls(e, c->j, 1, 1, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef, c->scal, c->flags,
                  kBreakdownRel);
@@ -300,12 +316,53 @@ int finalize_last(rks_ctx* c) {
   return RKS_OK;
 }
 
-int extend(rks_ctx* c) {
+int extend_launch(rks_ctx* c) {
   for (int t = c->j; t < c->m; ++t) {
     int r = c->ks ? arnoldi_step_ks(c, t) : arnoldi_step(c, t);
     if (r) return r;
   }
   if (!c->ks) finalize_last(c);
+  return RKS_OK;
+}
+
+int extend(rks_ctx* c) {
+  const bool graphs = c->o.graphs && !c->ks && c->o.profile == 0 && c->j < c->m;
+  const int key = (c->j * 2 + c->pending) * 4 + c->env.prec;
+  if (graphs) {
+    auto it = c->gexec.find(key);
+    if (it != c->gexec.end()) {
+      HIPCHK(c, hipGraphLaunch(it->second, c->env.stream));
+      for (int t = c->j; t < c->m; ++t) account_step(c, t, false, false);
+      c->j = c->m;
+      c->pending = 0;
+      c->G_z = c->gpart[key].first;
+      c->G_s = c->gpart[key].second;
+      return RKS_OK;
+    }
+    if (c->gseen[key]++ >= 1) {
+      if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+      rks::LaunchEnv rec = c->env;
+      rec.stream = c->cap;
+      c->lenv = &rec;
+      hipGraph_t g = nullptr;
+      hipError_t e0 = hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed);
+      const int rc = e0 == hipSuccess ? extend_launch(c) : RKS_OK;
+      hipError_t e1 = e0 == hipSuccess ? hipStreamEndCapture(c->cap, &g) : e0;
+      c->lenv = &c->env;
+      if (rc) return rc;
+      if (e1 != hipSuccess) return fail(c, RKS_EHIP, std::string("recording an extension -> ") + hipGetErrorString(e1));
+      hipGraphExec_t ex = nullptr;
+      hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) return fail(c, RKS_EHIP, std::string("hipGraphInstantiate -> ") + hipGetErrorString(e2));
+      c->gexec[key] = ex;
+      c->gpart[key] = {c->G_z, c->G_s};
+      HIPCHK(c, hipGraphLaunch(ex, c->env.stream));
+      return RKS_OK;
+    }
+  }
+  const int rc = extend_launch(c);
+  if (rc) return rc;
   HIPCHK(c, hipGetLastError());
   return RKS_OK;
 }
@@ -835,6 +892,8 @@ void free_all(rks_ctx* c) {
   for (void* p : host)
     if (p) (void)hipHostFree(p);
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  for (auto& kv : c->gexec) (void)hipGraphExecDestroy(kv.second);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
 }
 
 }  // namespace
@@ -860,6 +919,7 @@ void rks_opts_default(rks_opts* o) {
   o->spmv_layout = RKS_SPMV_AUTO;
   o->method = RKS_METHOD_RKS;
   o->keep = 0;
+  o->graphs = 0;
 }
 
 const char* rks_strerror(int code) { return code_str(code); }
@@ -887,8 +947,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
       !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
-      o.method > 1)
-    return fail(nullptr, RKS_EINVAL, "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout or method");
+      o.method > 1 || o.graphs < 0 || o.graphs > 1)
+    return fail(nullptr, RKS_EINVAL,
+                "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout, method or graphs");
   int keep = o.keep == 0 ? k : o.keep;
   if (o.keep == RKS_KEEP_AUTO)
     keep = std::max(k, std::min({k + (m - k) / 4, m - 2, rks::kRotMax - 1}));
@@ -900,6 +961,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");
   c->n = n; c->nnz = nnz; c->k = k; c->m = m; c->d = d; c->which = which; c->tol = tol; c->o = o;
+  c->lenv = &c->env;
   c->keep = keep;
   hipStream_t stm = (hipStream_t)o.stream;
   // host copies for validation, the 1-norm and the SpMV tiles

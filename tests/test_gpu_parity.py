@@ -405,3 +405,31 @@ def test_solves_are_bitwise_reproducible(lib, cuda, kind, prec):
     for x, y in zip(a[1:], b[1:]):
         if isinstance(x, np.ndarray):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("kind,prec", [("sparse", "fp64"), ("gauss", "fp64"), ("sparse", "fp32")])
+def test_graph_replays_match_direct_launches(lib, cuda, kind, prec):
+    """Extensions replayed from recorded HIP graphs give the same solve, to the
+    last bit, as launching every kernel: several solves in one context (the
+    first records nothing, later cycles and solves replay), with other device
+    work on the stream between them."""
+    A = convdiff2d(300, (30.0, 20.0))
+    k, m, d = 8, 30, 120
+    kw = dict(k=k, m=m, d=d, which="SR", tol=1e-10, sketch_kind=kind, sketch_seed=4, start_seed=1,
+              precision=prec, keep=-1, max_restarts=12)
+
+    def one(s):
+        s.solve()
+        lam, _, res = s.eigpairs(want_vectors=False)
+        return s.stats.restarts, s.stats.matvecs, lam, res
+
+    with P.Solver.from_csr(A, graphs=0, **kw) as s0:
+        ref = one(s0)
+    x = dev(cuda, start_vector_normal(A.n, 9))
+    z = cuda.zeros(d, dtype=cuda.float64, device="cuda")
+    with P.Solver.from_csr(A, graphs=1, **kw) as s1:
+        for rep in range(3):
+            got = one(s1)
+            assert got[0] == ref[0] and got[1] == ref[1], (rep, got[:2], ref[:2])
+            assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3]), rep
+            P.rks_sketch(s1.ctx, x, z)          # eager work between solves
