@@ -88,10 +88,10 @@ def kernel_source_hash() -> str:
 
 
 def counter_traffic(workload: str, precision: str):
-    """HBM bytes per k_update launch from the committed FETCH_SIZE/WRITE_SIZE
+    """HBM bytes per k_ls_update launch from the committed FETCH_SIZE/WRITE_SIZE
     counter summary of this workload, or None when there is none or the kernel
     sources changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"k_update_{workload}_{precision}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"k_ls_update_{workload}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -102,12 +102,12 @@ def counter_traffic(workload: str, precision: str):
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return float(kv["k_update_traffic_bytes_per_launch"])
+    return float(kv["k_ls_update_traffic_bytes_per_launch"])
 
 
 def _loop_gbs(st):
     """Algorithmic bytes of the Arnoldi loop (SpMV + sketch, update + re-sketch)
-    / the time of the whole step (its four launches inside one event pair)."""
+    / the time of the whole step (its three launches inside one event pair)."""
     return st["bytes_timed_whole"] / st["t_step"] / 1e9 if st["t_step"] > 0 else None
 
 
@@ -115,7 +115,7 @@ def _kernel_avg_us(st):
     """Average duration (us) of each kernel of the Arnoldi step, and of the rotation."""
     ns, nr = max(st["n_timed_steps"], 1), max(st["n_timed_rotate"], 1)
     return {"k_spmv_sketch": st["t_spmv"] / ns * 1e6, "k_reduce": st["t_reduce"] / ns * 1e6,
-            "k_ls": st["t_ls"] / ns * 1e6, "k_update": st["t_update"] / ns * 1e6,
+            "k_ls_update": st["t_update"] / ns * 1e6,
             "k_rotate": st["t_rotate"] / nr * 1e6}
 
 
@@ -262,7 +262,7 @@ def main():
                          f"alternately around each kernel ({st['n_timed_steps']} steps) and around the "
                          f"whole step ({st['n_timed_whole']} steps), of {st['n_update']}; and every rotation"),
         "host_dense_s": st["t_host"],
-        "roofline": {"bound": "hbm", "kernel": "k_update (V*h update + re-sketch)",
+        "roofline": {"bound": "hbm", "kernel": "k_ls_update (least squares, V*h update, re-sketch)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
                      "traffic": counter_traffic(args.workload, cfg["precision"]),

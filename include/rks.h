@@ -160,7 +160,9 @@ typedef struct {
   double t_total;        /* seconds, host wall clock of the solve */
   double t_host;         /* seconds spent in the host small dense steps */
   /* kernel timings (only when opts.profile > 0), seconds summed over the timed launches */
-  double t_spmv, t_reduce, t_ls, t_update, t_rotate;
+  double t_spmv, t_reduce, t_ls, t_update, t_rotate;  /* the randomized step runs its least squares
+                                                          inside the update launch, so t_update
+                                                          covers both and t_ls stays 0 there */
   int64_t n_spmv, n_update, n_rotate;     /* launches */
   double bytes_spmv, bytes_update, bytes_rotate;  /* algorithmic HBM bytes moved, all launches */
   int64_t n_timed_steps, n_timed_rotate;  /* timed Arnoldi steps (4 launches each) and rotations */

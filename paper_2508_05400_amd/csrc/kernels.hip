@@ -483,6 +483,160 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
   if (tid == 0) coef[t + 1] = ct;
 }
 
+// The least squares of k_ls (finalise the pending column, then h = y - E y)
+// as run by every workgroup of k_ls_update on its own, with S read from L2.
+// Everything it reads is left unchanged by the launch: column t comes from
+// snew (LDS) when it is being finalised, E's new column from gs, and the other
+// columns and scales were written by earlier launches.  The sums run in a
+// fixed order, so every workgroup obtains the same h to the last bit; only the
+// writer (workgroup 0) stores S(:, t), cs[t], B, E's new column, scal, the
+// breakdown flag and the coefficients to global memory.  The coefficients
+// also land in hc[0..t+1] (LDS).  sm holds 2d + 2(kMaxM + 2) + 32 + 2*64*17
+// doubles; the function ends with a barrier, after which sm may be reused.
+__device__ __forceinline__ void ls_solve(int t, int d, int pending, const double* __restrict__ zraw,
+                                         const double* __restrict__ sraw, double* __restrict__ S,
+                                         double* __restrict__ B, int ldb, double* __restrict__ E,
+                                         double* __restrict__ cs, double* __restrict__ coef,
+                                         double* __restrict__ scal, int* __restrict__ flags, double bd_rel,
+                                         bool writer, double* sm, double* hc) {
+  double* snew = sm;
+  double* zs = snew + d;
+  double* ys = zs + d;             // kMaxM + 2
+  double* gs = ys + kMaxM + 2;     // kMaxM + 2
+  double* red = gs + kMaxM + 2;    // 32
+  double* pa = red + 32;           // 64 x 17 partial sums
+  double* pg = pa + 64 * 17;       // 64 x 17 partial sums
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const int rc = tid & (kRC - 1), cl = tid >> 4;
+  double srv = 0.0, zrv = 0.0, ctg = 0.0;
+  if (tid < d) {
+    if (pending) srv = sraw[tid];
+    zrv = zraw[tid];
+  }
+  if (!pending) ctg = cs[t];
+  const bool pre_e = t <= kRC * kLsPreE;
+  double ev[kLsPreE];
+#pragma unroll
+  for (int i = 0; i < kLsPreE; ++i) {
+    const int c = rc + kRC * i;
+    ev[i] = (pre_e && c < t && cl < t) ? E[c + (size_t)cl * ldb] : 0.0;
+  }
+  {
+    double a = wave_sum(srv * srv), b = wave_sum(zrv * zrv);
+    if (lane == 0) {
+      red[wv] = a;
+      red[16 + wv] = b;
+    }
+  }
+  __syncthreads();
+  double ss = 0.0, zz = 0.0;
+  for (int q = 0; q < nw; ++q) {
+    ss += red[q];
+    zz += red[16 + q];
+  }
+  double ct;
+  if (pending) {
+    const double beta = sqrt(ss);
+    const double inv = 1.0 / beta;
+    if (tid < d) {
+      const double stv = srv * inv;
+      snew[tid] = stv;
+      if (writer) S[tid + (size_t)t * d] = stv;
+    }
+    if (writer && tid == 0) {
+      cs[t] = inv;
+      if (t > 0) {
+        B[t + (size_t)(t - 1) * ldb] = beta;
+        if (!(beta > bd_rel * scal[0]) && flags[0] == 0) flags[0] = t;
+      }
+    }
+    ct = inv;
+  } else {
+    ct = ctg;
+  }
+  const int ncol = t + 1;
+  if (tid < d) zs[tid] = zrv * ct;
+  if (writer && tid == 0) scal[0] = sqrt(zz) * ct;
+  __syncthreads();
+  for (int c0 = 0; c0 < ncol; c0 += 64) {
+    const int l = c0 + cl;
+    double a = 0.0, g = 0.0;
+    if (l < ncol) {
+      const double* Sl = (pending && l == t) ? snew : S + (size_t)l * d;
+      if (pending && l < t) {
+#pragma unroll 4
+        for (int b = rc; b < d; b += kRC) {
+          const double v = Sl[b];
+          a += v * zs[b];
+          g += v * snew[b];
+        }
+      } else {
+#pragma unroll 4
+        for (int b = rc; b < d; b += kRC) a += Sl[b] * zs[b];
+      }
+    }
+    pa[cl * 17 + rc] = a;
+    pg[cl * 17 + rc] = g;
+    __syncthreads();
+    if (tid < 64 && c0 + tid < ncol) {
+      double sa = 0.0, sg = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRC; ++r) {
+        sa += pa[tid * 17 + r];
+        sg += pg[tid * 17 + r];
+      }
+      ys[c0 + tid] = sa;
+      gs[c0 + tid] = sg;
+    }
+    __syncthreads();
+  }
+  if (pending && writer) {
+    for (int l = tid; l <= t; l += blockDim.x) {
+      const double g = (l < t) ? gs[l] : 0.0;
+      E[l + (size_t)t * ldb] = g;
+      E[t + (size_t)l * ldb] = g;
+    }
+  }
+  for (int c0 = 0; c0 < ncol; c0 += 64) {
+    const int l = c0 + cl;
+    double a = 0.0;
+    if (l < t) {
+      if (pre_e && c0 == 0) {
+#pragma unroll
+        for (int i = 0; i < kLsPreE; ++i)
+          if (rc + kRC * i < t) a += ev[i] * ys[rc + kRC * i];
+      } else {
+        for (int c = rc; c < t; c += kRC) a += E[c + (size_t)l * ldb] * ys[c];
+      }
+    } else if (l == t) {
+      for (int c = rc; c < t; c += kRC) a += (pending ? gs[c] : E[c + (size_t)t * ldb]) * ys[c];
+    }
+    pa[cl * 17 + rc] = a;
+    __syncthreads();
+    if (tid < 64 && c0 + tid < ncol) {
+      const int l2 = c0 + tid;
+      double sa = 0.0;
+#pragma unroll
+      for (int r = 0; r < kRC; ++r) sa += pa[tid * 17 + r];
+      if (l2 < t) sa += (pending ? gs[l2] : E[l2 + (size_t)t * ldb]) * ys[t];
+      else if (!pending) sa += E[t + (size_t)t * ldb] * ys[t];
+      const double h = ys[l2] - sa;
+      const double cf = h * ((l2 == t) ? ct : cs[l2]);
+      hc[l2] = cf;
+      if (writer) {
+        B[l2 + (size_t)t * ldb] = h;
+        coef[l2] = cf;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    hc[t + 1] = ct;
+    if (writer) coef[t + 1] = ct;
+  }
+  __syncthreads();
+}
+
 // 16-byte packets of the basis: V = 16 / sizeof(TV) consecutive rows.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
@@ -499,13 +653,12 @@ union Pack16 {
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
 template <typename TV, typename TW, int KIND>
-__global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U,
-                                                int64_t ldu, const TW* __restrict__ w,
-                                                const double* __restrict__ coef, TV* __restrict__ unew,
-                                                double* __restrict__ spart, SketchP sp) {
+__device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U, int64_t ldu,
+                                            const TW* __restrict__ w, const double* __restrict__ coef,
+                                            TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
+                                            double* bins) {
   constexpr int V = 16 / sizeof(TV);
   constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
-  extern __shared__ double bins[];  // 16 waves x d (none for KIND 3)
   if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
   double* wb = wave_bins(bins, sp.d);
@@ -563,6 +716,38 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
   if (KIND == 3) return;
   __syncthreads();
   bins_store(bins, spart, sp.d, sp.scale);
+}
+
+template <typename TV, typename TW, int KIND>
+__global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U,
+                                                int64_t ldu, const TW* __restrict__ w,
+                                                const double* __restrict__ coef, TV* __restrict__ unew,
+                                                double* __restrict__ spart, SketchP sp) {
+  extern __shared__ double bins[];  // 16 waves x d (none for KIND 3)
+  update_body<TV, TW, KIND>(n, npk, ncol, U, ldu, w, coef, unew, spart, sp, bins);
+}
+
+// One randomized Arnoldi step's least squares and update in one launch: every
+// workgroup solves the small least squares itself (ls_solve; identical
+// results, workgroup 0 stores them), then streams its rows of the update with
+// the coefficients from LDS.  This takes the least-squares kernel, a
+// latency-bound single workgroup, off the step's critical path.  LDS: the
+// coefficients (kMaxM + 2), then the least-squares scratch, reused afterwards
+// for the per-wave sketch bins.
+template <typename TV, typename TW, int KIND>
+__global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, const double* __restrict__ zraw,
+                                                   const double* __restrict__ sraw, double* __restrict__ S,
+                                                   double* __restrict__ B, int ldb, double* __restrict__ E,
+                                                   double* __restrict__ cs, double* __restrict__ coef,
+                                                   double* __restrict__ scal, int* __restrict__ flags, double bd_rel,
+                                                   int64_t n, int64_t npk, const TV* __restrict__ U, int64_t ldu,
+                                                   const TW* __restrict__ w, TV* __restrict__ unew,
+                                                   double* __restrict__ spart, SketchP sp) {
+  extern __shared__ double smem[];
+  double* hc = smem;
+  double* work = smem + kMaxM + 2;
+  ls_solve(t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, blockIdx.x == 0, work, hc);
+  update_body<TV, TW, KIND>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
@@ -1022,6 +1207,44 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_update<bf16_t, float, KIND>, lds);
                       k_update<bf16_t, float, KIND><<<grid, block, lds, e.stream>>>(
                           e.n, npk, ncol, (const bf16_t*)U, ldu, (const float*)w, coef, (bf16_t*)unew, spart, e.sp));
+  }
+  if (e.sp_kind == 0) {  // sketch of the stored value
+    if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
+    if (e.prec == 1) return gauss_t<float>(e, (const float*)unew, spart);
+    return gauss_t<bf16_t>(e, (const bf16_t*)unew, spart);
+  }
+  return G;
+}
+
+int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw, const double* sraw, double* S,
+                     double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
+                     double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart) {
+  const int V = 16 / e.vbytes();
+  const int64_t npk = (e.n + V - 1) / V;
+  // one workgroup per CU (256): the kernel's registers allow one 1024-thread
+  // workgroup per CU anyway, and fewer workgroups repeat the least squares
+  // fewer times
+  const int G = grid_for(npk, 1024, 256);
+  dim3 grid(G), block(1024);
+  const size_t ls_work = (size_t)2 * e.sp.d + 2 * (kMaxM + 2) + 32 + 2 * 64 * 17;
+  const size_t bins = e.sp_kind != 0 ? (size_t)16 * e.sp.d : 0;
+  const size_t lds = ((size_t)kMaxM + 2 + (ls_work > bins ? ls_work : bins)) * 8;
+  const int d = e.sp.d;
+  if (e.prec == 0) {
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<double, double, KIND>, lds);
+                      k_ls_update<double, double, KIND><<<grid, block, lds, e.stream>>>(
+                          t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                          (const double*)U, ldu, (const double*)w, (double*)unew, spart, e.sp));
+  } else if (e.prec == 1) {
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<float, float, KIND>, lds);
+                      k_ls_update<float, float, KIND><<<grid, block, lds, e.stream>>>(
+                          t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                          (const float*)U, ldu, (const float*)w, (float*)unew, spart, e.sp));
+  } else {
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<bf16_t, float, KIND>, lds);
+                      k_ls_update<bf16_t, float, KIND><<<grid, block, lds, e.stream>>>(
+                          t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                          (const bf16_t*)U, ldu, (const float*)w, (bf16_t*)unew, spart, e.sp));
   }
   if (e.sp_kind == 0) {  // sketch of the stored value
     if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);

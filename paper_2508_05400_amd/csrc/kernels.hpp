@@ -1,11 +1,13 @@
 // HIP kernels of the rKS hot path (CDNA4, wave64).
 //
-// One Arnoldi step of Algorithm 2 runs as four launches on one stream:
+// One Arnoldi step of Algorithm 2 runs as three launches on one stream:
 //   k_spmv_sketch  w' = A u_t  and per-block partial sums of Omega w'   (Algorithm 2: product with A, its sketch)
 //   k_reduce       deterministic bin-parallel sum of the partials
-//   k_ls           finalise the previous column (beta, s, B(t,t-1)), then the
-//                  FP64 least squares h = S^+ z                          (Algorithm 2: low-dimensional projection)
-//   k_update       u~ = w - U_t h, stored, and partial sums of Omega u~  (Algorithm 2: update in R^n, its sketch)
+//   k_ls_update    every workgroup: finalise the previous column (beta, s,
+//                  B(t,t-1)) and solve the FP64 least squares h = S^+ z  (Algorithm 2: low-dimensional projection);
+//                  then u~ = w - U_t h, stored, and partial sums of Omega u~ (Algorithm 2: update in R^n, its sketch)
+// (k_ls alone finalises the last column of an extension; k_update alone
+// serves the deterministic Krylov-Schur step.)
 // The new column is kept unnormalised; its scale 1/beta is folded into the
 // next step's coefficients (lazy normalisation saves one pass over n).
 // k_rotate applies the restart rotation U <- U Y (Algorithm 1, truncation).

@@ -42,6 +42,11 @@ void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const 
                double bd_rel);
 int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
                   void* unew, double* spart);
+// Least squares (as launch_ls, not finalize-only) and update (as launch_update
+// with ncol = t + 1) in one launch; returns the number of partial rows.
+int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw, const double* sraw, double* S,
+                     double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
+                     double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart);
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
                 int prec_override);
 void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,

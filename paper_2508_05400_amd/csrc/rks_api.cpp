@@ -202,7 +202,7 @@ void account_step(rks_ctx* c, int t, bool timed, bool whole);
 int arnoldi_step(rks_ctx* c, int t) {
   const auto& e = *c->lenv;
   // sampled timing: every P-th step, alternately per kernel and as a whole
-  // (one event pair around the four launches, for the loop's bandwidth)
+  // (one event pair around the three launches, for the loop's bandwidth)
   bool timed = false, whole = false;
   if (c->o.profile > 0 && c->st && (c->step_count % c->o.profile) == 0) {
     if ((c->step_count / c->o.profile) % 2 == 0) timed = true;
@@ -219,13 +219,12 @@ int arnoldi_step(rks_ctx* c, int t) {
     rks::launch_reduce(e, c->zpart, c->G_z, c->pending ? c->spart : nullptr, c->G_s, c->z, c->sr);
   }
   {
-    Prof p(c, CAT_LS, timed);
-    rks::launch_ls(e, t, c->pending, 0, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef, c->scal, c->flags,
-                   kBreakdownRel);
-  }
-  {
+    // least squares and update in one launch (the least-squares time is
+    // counted with the update)
     Prof p(c, CAT_UPDATE, timed);
-    c->G_s = rks::launch_update(e, t + 1, c->U, c->ldu, c->w, c->coef, basis_col(c, t + 1), c->spart);
+    c->G_s = rks::launch_ls_update(e, t, c->pending, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef,
+                                   c->scal, c->flags, kBreakdownRel, c->U, c->ldu, c->w, basis_col(c, t + 1),
+                                   c->spart);
   }
   account_step(c, t, timed, whole);
   c->pending = 1;
