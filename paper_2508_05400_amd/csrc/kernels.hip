@@ -1088,13 +1088,14 @@ __global__ __launch_bounds__(256) void k_gauss_sketch(int64_t n, const TX* __res
   } while (0)
 
 // Dynamic LDS of the per-wave sketch bins (waves x d FP64, none when the
-// kernel sketches nothing); above 48 KB the kernel's limit is raised once.
+// kernel sketches nothing); the kernel's dynamic-LDS limit is raised to the
+// largest size it is launched with (once per size increase).
 static size_t bins_lds(const LaunchEnv& e, int waves, bool sketched) {
   return sketched ? (size_t)waves * e.sp.d * 8 : 0;
 }
 
 static void lds_allow(const void* f, size_t bytes) {
-  if (bytes <= 48 * 1024) return;
+  if (bytes == 0) return;
   static std::mutex mu;
   static std::unordered_map<const void*, size_t> raised;
   std::lock_guard<std::mutex> lock(mu);

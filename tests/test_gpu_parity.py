@@ -38,6 +38,8 @@ SMALL = {
     "cd2d-37-sparse": (lambda: convdiff2d(37, (20.0, 10.0)), "sparse", 96),
     "powerlaw-5003": (lambda: powerlaw_random(5003, 4), "sparse", 120),
     "tridiag-4099": (lambda: tridiag_noisy(4099, "exponential", 5), "sparse", 64),
+    # d = 700: per-wave sketch bins of 44.8 KB (SpMV) and 89.6 KB (update) of dynamic LDS
+    "powerlaw-5003-d700": (lambda: powerlaw_random(5003, 4), "sparse", 700),
 }
 
 
