@@ -159,8 +159,8 @@ def main():
                     help="verified FP64 residual target of the metric (0 = paper's estimate test only)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel HIP events")
     ap.add_argument("--profile-every", type=int, default=7,
-                    help="time the kernels of every P-th Arnoldi step with HIP events (event records "
-                         "cost a few microseconds each, so timing every launch would slow the solve)")
+                    help="time the kernels of every P-th Arnoldi step with HIP events (the events "
+                         "around whole steps cost a few microseconds each, so the sample is sparse)")
     ap.add_argument("--keep", default="auto", help="restart size: auto (k + (m-k)/4), or a number in [k, m-2]")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay repeated extensions as HIP graphs (used only "
                     "when the per-kernel events are off, --no-profile); 0: launch every kernel")
@@ -259,8 +259,9 @@ def main():
         "kernel_avg_us": _kernel_avg_us(st),
         "step_avg_us": st["t_step"] / max(st["n_timed_whole"], 1) * 1e6,
         "timed_sample": (f"HIP events on every {args.profile_every}th Arnoldi step inside the timed solves, "
-                         f"alternately around each kernel ({st['n_timed_steps']} steps) and around the "
-                         f"whole step ({st['n_timed_whole']} steps), of {st['n_update']}; and every rotation"),
+                         f"alternately attached to each kernel's launch (its dispatch start and end; "
+                         f"{st['n_timed_steps']} steps) and recorded around the whole step "
+                         f"({st['n_timed_whole']} steps), of {st['n_update']}; and every rotation"),
         "host_dense_s": st["t_host"],
         "roofline": {"bound": "hbm", "kernel": "k_ls_update (least squares, V*h update, re-sketch)",
                      "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -96,10 +96,11 @@ typedef struct {
   int32_t precision;     /* rks_precision, default FP64 */
   int32_t max_restarts;  /* contraction/extension cycles after the first extension, default 300 */
   int32_t lock;          /* lock converged leading Schur vectors, default 1 */
-  int32_t profile;       /* P > 0: time every P-th Arnoldi step with HIP events on the
-                            solver's stream, alternately per kernel and as a whole, and
-                            every rotation (each event pair adds a few microseconds);
-                            0 = off (default) */
+  int32_t profile;       /* P > 0: time every P-th Arnoldi step on the solver's stream,
+                            alternately per kernel (HIP events attached to the launches,
+                            which take the dispatches' own start and end times) and as a
+                            whole (one event pair recorded around the step, which adds a
+                            few microseconds), and every rotation; 0 = off (default) */
   double whiten_tol;     /* whiten when ||S_k^T S_k - I||_F exceeds this, default 1e-12 */
   void* stream;          /* hipStream_t, NULL = default stream */
   double resid_tol;      /* > 0: also stop once every pair's FP64 residual
@@ -165,10 +166,10 @@ typedef struct {
                                                           covers both and t_ls stays 0 there */
   int64_t n_spmv, n_update, n_rotate;     /* launches */
   double bytes_spmv, bytes_update, bytes_rotate;  /* algorithmic HBM bytes moved, all launches */
-  int64_t n_timed_steps, n_timed_rotate;  /* timed Arnoldi steps (4 launches each) and rotations */
+  int64_t n_timed_steps, n_timed_rotate;  /* Arnoldi steps timed per kernel, and rotations */
   double bytes_timed_spmv, bytes_timed_update, bytes_timed_rotate;  /* algorithmic bytes of the timed launches */
   int64_t n_timed_whole;     /* sampled Arnoldi steps timed as a whole (the other half of the sample) */
-  double t_step;             /* seconds summed over those steps (four launches each, one event pair) */
+  double t_step;             /* seconds summed over those steps (one event pair around each) */
   double bytes_timed_whole;  /* their algorithmic bytes (SpMV + update) */
   int32_t spmv_layout;       /* rks_spmv_layout in use (ROWS or COLUMN_BLOCKS) */
   int32_t keep;              /* restart size in use */

@@ -2,6 +2,7 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 
+#include <hip/hip_ext.h>
 #include <mutex>
 #include <unordered_map>
 
@@ -1106,6 +1107,18 @@ static void lds_allow(const void* f, size_t bytes) {
   }
 }
 
+// A kernel launch that carries the environment's timing events: with `first`
+// the kernel's start is recorded in ev0, with `last` its end in ev1.
+template <typename... KArgs, typename... Args>
+static void launch_k(const LaunchEnv& e, bool first, bool last, void (*k)(KArgs...), dim3 grid, dim3 block,
+                     size_t lds, Args... args) {
+  hipEvent_t a = first ? e.ev0 : nullptr, b = last ? e.ev1 : nullptr;
+  if (a || b)
+    hipExtLaunchKernelGGL(k, grid, block, (uint32_t)lds, e.stream, a, b, 0u, static_cast<KArgs>(args)...);
+  else
+    k<<<grid, block, lds, e.stream>>>(static_cast<KArgs>(args)...);
+}
+
 // The Gaussian sketch of x (n entries of type TX) as partial rows of part;
 // returns the number of rows (<= kMaxG).
 template <typename TX>
@@ -1115,7 +1128,7 @@ static int gauss_t(const LaunchEnv& e, const TX* x, double* part) {
   if (R < kGsMinRows) R = kGsMinRows;
   const int Gx = (int)((e.n + R - 1) / R);
   dim3 grid(Gx, (np + 63) / 64), block(256);
-  k_gauss_sketch<TX><<<grid, block, 0, e.stream>>>(e.n, x, R, part, e.sp);
+  launch_k(e, false, true, k_gauss_sketch<TX>, grid, block, 0, e.n, x, R, part, e.sp);
   return Gx;
 }
 
@@ -1124,13 +1137,13 @@ static int spmv_cb_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, doub
   const int ntiles = e.cbt.off[kCb];
   int G1 = grid_for(ntiles, 8, 2048);
   G1 = (G1 + kCb - 1) / kCb * kCb;  // every column block gets the same number of workgroups
-  k_spmv_cb<TV, TW, TA><<<G1, 512, 0, e.stream>>>(e.n, e.rp_cb, e.col_cb, val, (const int4*)e.tiles_cb, e.cbt, x,
-                                                  (TW*)e.P, e.ldu);
+  launch_k(e, true, false, k_spmv_cb<TV, TW, TA>, dim3(G1), dim3(512), 0, e.n, e.rp_cb, e.col_cb, val,
+           (const int4*)e.tiles_cb, e.cbt, x, (TW*)e.P, e.ldu);
   const int G2 = grid_for(e.n, 512, kMaxG);
   const size_t lds = bins_lds(e, 8, do_sketch && e.sp_kind == 1);
   RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_cb_combine<TW, KIND>, lds);
-                    k_cb_combine<TW, KIND><<<G2, 512, lds, e.stream>>>(e.n, (const TW*)e.P, e.ldu, w, zpart, e.sp,
-                                                                       do_sketch));
+                    launch_k(e, false, !(do_sketch && e.sp_kind == 0), k_cb_combine<TW, KIND>, dim3(G2),
+                             dim3(512), lds, e.n, (const TW*)e.P, e.ldu, w, zpart, e.sp, do_sketch));
   if (do_sketch && e.sp_kind == 0) return gauss_t<TW>(e, w, zpart);
   return G2;
 }
@@ -1148,19 +1161,19 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
   const size_t lds = bins_lds(e, 8, do_sketch && e.sp_kind == 1);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<double, double, double, KIND>, lds);
-                      k_spmv_sketch<double, double, double, KIND><<<grid, block, lds, e.stream>>>(
-                          e.rp, e.col, e.val, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w, zpart, e.sp,
-                          do_sketch));
+                      launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<double, double, double, KIND>, grid, block, lds,
+                               e.rp, e.col, e.val, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
+                               e.sp, do_sketch));
   } else if (prec == 1) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<float, float, float, KIND>, lds);
-                      k_spmv_sketch<float, float, float, KIND><<<grid, block, lds, e.stream>>>(
-                          e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w, zpart, e.sp,
-                          do_sketch));
+                      launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<float, float, float, KIND>, grid, block, lds,
+                               e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w, zpart,
+                               e.sp, do_sketch));
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<bf16_t, float, float, KIND>, lds);
-                      k_spmv_sketch<bf16_t, float, float, KIND><<<grid, block, lds, e.stream>>>(
-                          e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart, e.sp,
-                          do_sketch));
+                      launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<bf16_t, float, float, KIND>, grid, block, lds,
+                               e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
+                               e.sp, do_sketch));
   }
   if (do_sketch && e.sp_kind == 0)
     return prec == 0 ? gauss_t<double>(e, (const double*)w, zpart) : gauss_t<float>(e, (const float*)w, zpart);
@@ -1169,7 +1182,7 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
 
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob) {
   dim3 grid((e.sp.d + kRedBins - 1) / kRedBins, 2), block(kRedBins * kRedSl);
-  k_reduce<<<grid, block, 0, e.stream>>>(pa, pb, Ga, Gb, e.sp.d, oa, ob);
+  launch_k(e, true, true, k_reduce, grid, block, 0, pa, pb, Ga, Gb, e.sp.d, oa, ob);
 }
 
 void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
@@ -1233,19 +1246,19 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
   const int d = e.sp.d;
   if (e.prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<double, double, KIND>, lds);
-                      k_ls_update<double, double, KIND><<<grid, block, lds, e.stream>>>(
-                          t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                          (const double*)U, ldu, (const double*)w, (double*)unew, spart, e.sp));
+                      launch_k(e, true, e.sp_kind != 0, k_ls_update<double, double, KIND>, grid, block, lds, t, d, pending,
+                               zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                               (const double*)U, ldu, (const double*)w, (double*)unew, spart, e.sp));
   } else if (e.prec == 1) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<float, float, KIND>, lds);
-                      k_ls_update<float, float, KIND><<<grid, block, lds, e.stream>>>(
-                          t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                          (const float*)U, ldu, (const float*)w, (float*)unew, spart, e.sp));
+                      launch_k(e, true, e.sp_kind != 0, k_ls_update<float, float, KIND>, grid, block, lds, t, d, pending,
+                               zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                               (const float*)U, ldu, (const float*)w, (float*)unew, spart, e.sp));
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<bf16_t, float, KIND>, lds);
-                      k_ls_update<bf16_t, float, KIND><<<grid, block, lds, e.stream>>>(
-                          t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                          (const bf16_t*)U, ldu, (const float*)w, (bf16_t*)unew, spart, e.sp));
+                      launch_k(e, true, e.sp_kind != 0, k_ls_update<bf16_t, float, KIND>, grid, block, lds, t, d, pending,
+                               zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                               (const bf16_t*)U, ldu, (const float*)w, (bf16_t*)unew, spart, e.sp));
   }
   if (e.sp_kind == 0) {  // sketch of the stored value
     if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
@@ -1293,7 +1306,8 @@ static void rotate_nt(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)k_rotate<TI, TO, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-  k_rotate<TI, TO, NT><<<G, 256, lds, e.stream>>>(e.n, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  launch_k(e, true, true, k_rotate<TI, TO, NT>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O, ldo, out0, kout,
+           Y, xsrc, xdst, xscale);
 }
 
 template <typename TI, typename TO>

@@ -30,6 +30,11 @@ struct LaunchEnv {
   const int* tiles_cb = nullptr;    // wave tiles of all blocks, block after block
   CbTiles cbt{};
   void* P = nullptr;                // kCb partial vectors, leading dimension ldu (FP64 or FP32)
+  // Timing (null when off): a launcher that runs with these set records ev0 at
+  // the start of its first kernel and ev1 at the end of its last one, from the
+  // dispatches' own timestamps (no marker packets between the kernels).
+  hipEvent_t ev0 = nullptr;
+  hipEvent_t ev1 = nullptr;
   int vbytes() const { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 };
 

@@ -168,6 +168,28 @@ struct Prof {
   }
 };
 
+// Timing of one launcher's kernels from their own dispatch timestamps: the
+// launcher gets a copy of the environment that carries two events (see
+// LaunchEnv::ev0, ev1), so nothing is enqueued between the kernels.
+struct ProfK {
+  rks_ctx* c;
+  int cat;
+  rks::LaunchEnv env;
+  ProfK(rks_ctx* c_, int cat_, bool on, const rks::LaunchEnv& e) : c(c_), cat(cat_), env(e) {
+    env.ev0 = env.ev1 = nullptr;
+    if (on && c->o.profile > 0 && c->st) {
+      hipEvent_t a = get_event(c), b = a ? get_event(c) : nullptr;
+      if (a && b) {
+        env.ev0 = a;
+        env.ev1 = b;
+      }
+    }
+  }
+  ~ProfK() {
+    if (env.ev0) c->open.push_back({cat, env.ev0, env.ev1});
+  }
+};
+
 void flush_events(rks_ctx* c) {
   if (!c->st) {
     c->open.clear();
@@ -211,18 +233,18 @@ int arnoldi_step(rks_ctx* c, int t) {
   ++c->step_count;
   Prof pw(c, CAT_STEP, whole);
   {
-    Prof p(c, CAT_SPMV, timed);
-    c->G_z = rks::launch_spmv_sketch(e, basis_col(c, t), c->w, c->zpart, 1, -1);
+    ProfK p(c, CAT_SPMV, timed, e);
+    c->G_z = rks::launch_spmv_sketch(p.env, basis_col(c, t), c->w, c->zpart, 1, -1);
   }
   {
-    Prof p(c, CAT_REDUCE, timed);
-    rks::launch_reduce(e, c->zpart, c->G_z, c->pending ? c->spart : nullptr, c->G_s, c->z, c->sr);
+    ProfK p(c, CAT_REDUCE, timed, e);
+    rks::launch_reduce(p.env, c->zpart, c->G_z, c->pending ? c->spart : nullptr, c->G_s, c->z, c->sr);
   }
   {
     // least squares and update in one launch (the least-squares time is
     // counted with the update)
-    Prof p(c, CAT_UPDATE, timed);
-    c->G_s = rks::launch_ls_update(e, t, c->pending, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef,
+    ProfK p(c, CAT_UPDATE, timed, e);
+    c->G_s = rks::launch_ls_update(p.env, t, c->pending, c->z, c->sr, c->S, c->B, c->m + 1, c->E, c->cs, c->coef,
                                    c->scal, c->flags, kBreakdownRel, c->U, c->ldu, c->w, basis_col(c, t + 1),
                                    c->spart);
   }
@@ -609,8 +631,8 @@ int rotate_basis(rks_ctx* c, int in0, int min, int out0, int kout, double xscale
   auto stm = c->env.stream;
   HIPCHK(c, hipMemcpyAsync(c->Yd, c->hY, (size_t)min * kout * 8, hipMemcpyHostToDevice, stm));
   {
-    Prof p(c, CAT_ROTATE, true);
-    rks::launch_rotate(c->env, c->U, c->ldu, in0, min, c->U, c->ldu, out0, kout, c->Yd, c->m, c->keff, xscale, 0);
+    ProfK p(c, CAT_ROTATE, true, c->env);
+    rks::launch_rotate(p.env, c->U, c->ldu, in0, min, c->U, c->ldu, out0, kout, c->Yd, c->m, c->keff, xscale, 0);
   }
   HIPCHK(c, hipGetLastError());
   if (c->st) {
