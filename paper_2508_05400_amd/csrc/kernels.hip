@@ -485,36 +485,63 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
 }
 
 // The least squares of k_ls (finalise the pending column, then h = y - E y)
-// as run by every workgroup of k_ls_update on its own, with S read from L2.
-// Everything it reads is left unchanged by the launch: column t comes from
-// snew (LDS) when it is being finalised, E's new column from gs, and the other
-// columns and scales were written by earlier launches.  The sums run in a
-// fixed order, so every workgroup obtains the same h to the last bit; only the
-// writer (workgroup 0) stores S(:, t), cs[t], B, E's new column, scal, the
-// breakdown flag and the coefficients to global memory.  The coefficients
-// also land in hc[0..t+1] (LDS).  sm holds 2d + 2(kMaxM + 2) + 32 + 2*64*17
-// doubles; the function ends with a barrier, after which sm may be reused.
+// as run by every workgroup of k_ls_update on its own, arranged so that the
+// workgroup waits for global memory once and crosses five barriers:
+//   A  every global load at entry: the raw sketches z~ (of A u~_t) and s~ (of
+//      the pending column), this thread's rows of its column of S (d <= 256,
+//      t < 64), its E values, the scales; the raw sketches go to LDS;
+//   B  one pass of inner products with the raw vectors, Y_l = s_l . z~ and
+//      G_l = s_l . s~ (slot t takes s~ itself, so G_t = ||s~||^2), and z~ . z~;
+//   C  wave 0: beta = sqrt(G_t); then y = ct Y (ct the scale of u~_t), with
+//      y_t = Y_t ct / beta, and E's new column g_l = G_l / beta: the same
+//      quantities as from the normalised vectors, up to rounding;
+//   D  the 16-way partial sums of E y;   E  wave 0: h = y - E y, coefficients.
+// Everything it reads is left unchanged by the launch (column t and E's new
+// column come from LDS; the other columns and scales were written by earlier
+// launches), and the sums run in a fixed order, so every workgroup obtains the
+// same h to the last bit; only the writer (workgroup 0) stores S(:, t),
+// cs[t], B, E's new column, scal, the breakdown flag and the coefficients to
+// global memory.  The coefficients also land in hc[0..t+1] (LDS).  sm holds
+// ls_work_doubles(d) doubles; the function ends with a barrier, after which
+// sm may be reused.
+constexpr int kLsPreS = 16;  // S values per thread prefetched at entry (d <= 256)
+__host__ __device__ constexpr size_t ls_work_doubles(int d) {
+  return 2 * (size_t)d + 4 * (size_t)(kMaxM + 2) + 2 * 64 * 17 + 17;
+}
+
 __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double* __restrict__ zraw,
                                          const double* __restrict__ sraw, double* __restrict__ S,
                                          double* __restrict__ B, int ldb, double* __restrict__ E,
                                          double* __restrict__ cs, double* __restrict__ coef,
                                          double* __restrict__ scal, int* __restrict__ flags, double bd_rel,
                                          bool writer, double* sm, double* hc) {
-  double* snew = sm;
-  double* zs = snew + d;
-  double* ys = zs + d;             // kMaxM + 2
-  double* gs = ys + kMaxM + 2;     // kMaxM + 2
-  double* red = gs + kMaxM + 2;    // 32
-  double* pa = red + 32;           // 64 x 17 partial sums
-  double* pg = pa + 64 * 17;       // 64 x 17 partial sums
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  double* zr = sm;               // d: z~
+  double* sr = zr + d;           // d: s~
+  double* yr = sr + d;           // kMaxM + 2: Y (raw inner products with z~)
+  double* gr = yr + kMaxM + 2;   // kMaxM + 2: G (raw inner products with s~)
+  double* ys = gr + kMaxM + 2;   // kMaxM + 2: y
+  double* gs = ys + kMaxM + 2;   // kMaxM + 2: E's new column g
+  double* pa = gs + kMaxM + 2;   // 64 x 17 partial sums
+  double* pg = pa + 64 * 17;     // 64 x 17 partial sums
+  double* pz = pg + 64 * 17;     // 16 partial sums of z~ . z~
+  const int tid = threadIdx.x, lane = tid & 63;
   const int rc = tid & (kRC - 1), cl = tid >> 4;
-  double srv = 0.0, zrv = 0.0, ctg = 0.0;
+  const int ncol = t + 1;
+  // ---- A: every global load, in one round ----
+  double zv = 0.0, sv0 = 0.0;
   if (tid < d) {
-    if (pending) srv = sraw[tid];
-    zrv = zraw[tid];
+    zv = zraw[tid];
+    if (pending) sv0 = sraw[tid];
   }
-  if (!pending) ctg = cs[t];
+  const double ctg = pending ? 0.0 : cs[t];
+  const bool pre_s = d <= kRC * kLsPreS && ncol <= 64;
+  const bool s_glob = cl < ncol && !(pending && cl == t);  // slot cl reads column cl of S
+  double sv[kLsPreS];
+#pragma unroll
+  for (int i = 0; i < kLsPreS; ++i) {
+    const int b = rc + kRC * i;
+    sv[i] = (pre_s && s_glob && b < d) ? S[b + (size_t)cl * d] : 0.0;
+  }
   const bool pre_e = t <= kRC * kLsPreE;
   double ev[kLsPreE];
 #pragma unroll
@@ -522,62 +549,56 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
     const int c = rc + kRC * i;
     ev[i] = (pre_e && c < t && cl < t) ? E[c + (size_t)cl * ldb] : 0.0;
   }
-  {
-    double a = wave_sum(srv * srv), b = wave_sum(zrv * zrv);
-    if (lane == 0) {
-      red[wv] = a;
-      red[16 + wv] = b;
-    }
+  const double csv = (tid < 64 && tid < t) ? cs[tid] : 0.0;
+  const double etv = (!pending && tid < 64 && tid <= t) ? E[tid + (size_t)t * ldb] : 0.0;  // E(tid, t)
+  double sc0 = 0.0;
+  int fl0 = 1;
+  if (writer && tid == 0 && pending && t > 0) {
+    sc0 = scal[0];
+    fl0 = flags[0];
+  }
+  if (tid < d) {
+    zr[tid] = zv;
+    sr[tid] = sv0;
   }
   __syncthreads();
-  double ss = 0.0, zz = 0.0;
-  for (int q = 0; q < nw; ++q) {
-    ss += red[q];
-    zz += red[16 + q];
-  }
-  double ct;
-  if (pending) {
-    const double beta = sqrt(ss);
-    const double inv = 1.0 / beta;
-    if (tid < d) {
-      const double stv = srv * inv;
-      snew[tid] = stv;
-      if (writer) S[tid + (size_t)t * d] = stv;
-    }
-    if (writer && tid == 0) {
-      cs[t] = inv;
-      if (t > 0) {
-        B[t + (size_t)(t - 1) * ldb] = beta;
-        if (!(beta > bd_rel * scal[0]) && flags[0] == 0) flags[0] = t;
-      }
-    }
-    ct = inv;
-  } else {
-    ct = ctg;
-  }
-  const int ncol = t + 1;
-  if (tid < d) zs[tid] = zrv * ct;
-  if (writer && tid == 0) scal[0] = sqrt(zz) * ct;
-  __syncthreads();
+  // ---- B: Y, G and z~ . z~ in one pass ----
   for (int c0 = 0; c0 < ncol; c0 += 64) {
     const int l = c0 + cl;
     double a = 0.0, g = 0.0;
     if (l < ncol) {
-      const double* Sl = (pending && l == t) ? snew : S + (size_t)l * d;
-      if (pending && l < t) {
-#pragma unroll 4
-        for (int b = rc; b < d; b += kRC) {
-          const double v = Sl[b];
-          a += v * zs[b];
-          g += v * snew[b];
+      const bool newcol = pending && l == t;
+      if (pre_s && !newcol) {
+#pragma unroll
+        for (int i = 0; i < kLsPreS; ++i) {
+          const int b = rc + kRC * i;
+          if (b < d) {
+            a += sv[i] * zr[b];
+            if (pending) g += sv[i] * sr[b];
+          }
         }
       } else {
+        const double* Sl = newcol ? sr : S + (size_t)l * d;
+        if (pending) {
 #pragma unroll 4
-        for (int b = rc; b < d; b += kRC) a += Sl[b] * zs[b];
+          for (int b = rc; b < d; b += kRC) {
+            const double v = Sl[b];
+            a += v * zr[b];
+            g += v * sr[b];
+          }
+        } else {
+#pragma unroll 4
+          for (int b = rc; b < d; b += kRC) a += Sl[b] * zr[b];
+        }
       }
     }
     pa[cl * 17 + rc] = a;
     pg[cl * 17 + rc] = g;
+    if (c0 == 0 && cl == 0) {
+      double zz = 0.0;
+      for (int b = rc; b < d; b += kRC) zz += zr[b] * zr[b];
+      pz[rc] = zz;
+    }
     __syncthreads();
     if (tid < 64 && c0 + tid < ncol) {
       double sa = 0.0, sg = 0.0;
@@ -586,22 +607,58 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
         sa += pa[tid * 17 + r];
         sg += pg[tid * 17 + r];
       }
-      ys[c0 + tid] = sa;
-      gs[c0 + tid] = sg;
+      yr[c0 + tid] = sa;
+      gr[c0 + tid] = sg;
     }
-    __syncthreads();
+    if (c0 + 64 < ncol) __syncthreads();  // the partial sums are reused by the next 64 columns
   }
-  if (pending && writer) {
-    for (int l = tid; l <= t; l += blockDim.x) {
-      const double g = (l < t) ? gs[l] : 0.0;
-      E[l + (size_t)t * ldb] = g;
-      E[t + (size_t)l * ldb] = g;
+  // ---- C: wave 0 finalises column t and scales y and g ----
+  double ct = ctg;
+  if (tid < 64) {
+    double inv = 0.0, beta = 0.0;
+    if (pending) {
+      beta = sqrt(gr[t]);
+      inv = 1.0 / beta;
+      ct = inv;
+    }
+    for (int l = lane; l <= t; l += 64) {
+      double y = yr[l] * ct;
+      if (pending && l == t) y *= inv;
+      ys[l] = y;
+      gs[l] = (pending && l < t) ? gr[l] * inv : 0.0;
+    }
+    if (lane == 0) hc[t + 1] = ct;
+    if (writer) {
+      if (pending) {
+        for (int b = lane; b < d; b += 64) S[b + (size_t)t * d] = sr[b] * inv;
+        for (int l = lane; l <= t; l += 64) {
+          const double g = (l < t) ? gr[l] * inv : 0.0;
+          E[l + (size_t)t * ldb] = g;
+          E[t + (size_t)l * ldb] = g;
+        }
+      }
+      if (lane == 0) {
+        double zz = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRC; ++r) zz += pz[r];
+        scal[0] = sqrt(zz) * ct;
+        coef[t + 1] = ct;
+        if (pending) {
+          cs[t] = inv;
+          if (t > 0) {
+            B[t + (size_t)(t - 1) * ldb] = beta;
+            if (!(beta > bd_rel * sc0) && fl0 == 0) flags[0] = t;
+          }
+        }
+      }
     }
   }
+  __syncthreads();
+  // ---- D, E: h = y - E y ----
   for (int c0 = 0; c0 < ncol; c0 += 64) {
     const int l = c0 + cl;
     double a = 0.0;
-    if (l < t) {
+    if (l < t) {  // columns c < t of row l (= column l, E is symmetric)
       if (pre_e && c0 == 0) {
 #pragma unroll
         for (int i = 0; i < kLsPreE; ++i)
@@ -619,10 +676,11 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
       double sa = 0.0;
 #pragma unroll
       for (int r = 0; r < kRC; ++r) sa += pa[tid * 17 + r];
-      if (l2 < t) sa += (pending ? gs[l2] : E[l2 + (size_t)t * ldb]) * ys[t];
-      else if (!pending) sa += E[t + (size_t)t * ldb] * ys[t];
+      // column t of row l2 (just finalised, or from the host)
+      const double e_lt = pending ? gs[l2] : (c0 == 0 ? etv : E[l2 + (size_t)t * ldb]);
+      if (l2 < t || !pending) sa += e_lt * ys[t];
       const double h = ys[l2] - sa;
-      const double cf = h * ((l2 == t) ? ct : cs[l2]);
+      const double cf = h * ((l2 == t) ? ct : (c0 == 0 ? csv : cs[l2]));
       hc[l2] = cf;
       if (writer) {
         B[l2 + (size_t)t * ldb] = h;
@@ -631,11 +689,6 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    hc[t + 1] = ct;
-    if (writer) coef[t + 1] = ct;
-  }
-  __syncthreads();
 }
 
 // 16-byte packets of the basis: V = 16 / sizeof(TV) consecutive rows.
@@ -1240,7 +1293,7 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
   // fewer times
   const int G = grid_for(npk, 1024, 256);
   dim3 grid(G), block(1024);
-  const size_t ls_work = (size_t)2 * e.sp.d + 2 * (kMaxM + 2) + 32 + 2 * 64 * 17;
+  const size_t ls_work = ls_work_doubles(e.sp.d);
   const size_t bins = e.sp_kind != 0 ? (size_t)16 * e.sp.d : 0;
   const size_t lds = ((size_t)kMaxM + 2 + (ls_work > bins ? ls_work : bins)) * 8;
   const int d = e.sp.d;
