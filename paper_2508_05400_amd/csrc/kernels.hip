@@ -505,16 +505,18 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
 // ls_work_doubles(d) doubles; the function ends with a barrier, after which
 // sm may be reused.
 constexpr int kLsPreS = 16;  // S values per thread prefetched at entry (d <= 256)
+constexpr int kLsPreU = 8;   // basis columns of the first packet loaded during the least squares
 __host__ __device__ constexpr size_t ls_work_doubles(int d) {
   return 2 * (size_t)d + 4 * (size_t)(kMaxM + 2) + 2 * 64 * 17 + 17;
 }
 
+template <typename Pre>
 __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double* __restrict__ zraw,
                                          const double* __restrict__ sraw, double* __restrict__ S,
                                          double* __restrict__ B, int ldb, double* __restrict__ E,
                                          double* __restrict__ cs, double* __restrict__ coef,
                                          double* __restrict__ scal, int* __restrict__ flags, double bd_rel,
-                                         bool writer, double* sm, double* hc) {
+                                         bool writer, double* sm, double* hc, Pre&& prefetch) {
   double* zr = sm;               // d: z~
   double* sr = zr + d;           // d: s~
   double* yr = sr + d;           // kMaxM + 2: Y (raw inner products with z~)
@@ -557,6 +559,11 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
     sc0 = scal[0];
     fl0 = flags[0];
   }
+  // the caller's loads go after these (loads complete in order, so waiting
+  // for the ones above does not wait for them)
+  __builtin_amdgcn_sched_barrier(0);
+  prefetch();
+  __builtin_amdgcn_sched_barrier(0);
   if (tid < d) {
     zr[tid] = zv;
     sr[tid] = sv0;
@@ -706,11 +713,11 @@ union Pack16 {
 // wave-uniform and come through the scalar path.  Padding rows (>= n, < ldu)
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
-template <typename TV, typename TW, int KIND>
+template <typename TV, typename TW, int KIND, int NPRE = 0>
 __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U, int64_t ldu,
                                             const TW* __restrict__ w, const double* __restrict__ coef,
                                             TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
-                                            double* bins) {
+                                            double* bins, const u32x4* pre = nullptr, bool use_pre = false) {
   constexpr int V = 16 / sizeof(TV);
   constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
   if (KIND != 3) bins_zero(bins, sp.d);
@@ -733,6 +740,18 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
     }
     const TV* col0 = U + i0;
     int l = 0;
+    if (NPRE > 0 && use_pre) {  // the first packet's leading columns, loaded before the least squares
+#pragma unroll
+      for (int q = 0; q < NPRE; ++q) {
+        Pack16<TV> pq;
+        pq.raw = pre[q];
+        const double cq = coef[q];
+#pragma unroll
+        for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(pq.v[r]);
+      }
+      l = NPRE;
+      use_pre = false;
+    }
     for (; l + 8 <= ncol; l += 8) {
       Pack16<TV> p[8];
 #pragma unroll
@@ -788,7 +807,7 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
 // latency-bound single workgroup, off the step's critical path.  LDS: the
 // coefficients (kMaxM + 2), then the least-squares scratch, reused afterwards
 // for the per-wave sketch bins.
-template <typename TV, typename TW, int KIND>
+template <typename TV, typename TW, int KIND, bool PRE>
 __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, const double* __restrict__ zraw,
                                                    const double* __restrict__ sraw, double* __restrict__ S,
                                                    double* __restrict__ B, int ldb, double* __restrict__ E,
@@ -800,8 +819,29 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
   extern __shared__ double smem[];
   double* hc = smem;
   double* work = smem + kMaxM + 2;
-  ls_solve(t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, blockIdx.x == 0, work, hc);
-  update_body<TV, TW, KIND>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work);
+  // the first kLsPreU basis columns of this thread's first packet are loaded
+  // right after the least squares' own loads, so that their latency (and
+  // HBM) is busy while the workgroup solves
+  // (PRE: only where the least squares has no global loads of its own after
+  // its first round, d <= 256 and t < 64, which would wait for these; and not
+  // for BF16, whose eight rows per packet leave no registers for it)
+  constexpr int V = 16 / sizeof(TV);
+  constexpr int NP = PRE && sizeof(TV) >= 4 ? kLsPreU : 0;
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool use_pre = NP > 0 && g0 < npk && t + 1 >= NP;
+  u32x4 pre[NP > 0 ? NP : 1];
+  // The loads are issued by every thread, from clamped (in-bounds) addresses
+  // when unused: a load under a branch would make the least squares wait for
+  // all of them (wait counts are merged over both paths).
+  const int64_t gl = g0 < npk ? g0 : npk - 1;
+  ls_solve(t, d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, blockIdx.x == 0, work, hc, [&] {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int qc = q <= t ? q : t;
+      pre[q] = __builtin_nontemporal_load((const u32x4*)(U + gl * V + (int64_t)qc * ldu));
+    }
+  });
+  update_body<TV, TW, KIND, NP>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
@@ -1283,6 +1323,17 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
   return G;
 }
 
+template <typename TV, typename TW, bool PRE>
+static void ls_update_t(const LaunchEnv& e, dim3 grid, size_t lds, int t, int pending, const double* zraw,
+                        const double* sraw, double* S, double* B, int ldb, double* E, double* cs, double* coef,
+                        double* scal, int* flags, double bd_rel, int64_t npk, const void* U, int64_t ldu,
+                        const void* w, void* unew, double* spart) {
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE>, lds);
+                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE>, grid, dim3(1024), lds, t, e.sp.d,
+                             pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+                             (const TV*)U, ldu, (const TW*)w, (TV*)unew, spart, e.sp));
+}
+
 int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw, const double* sraw, double* S,
                      double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
                      double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart) {
@@ -1292,27 +1343,20 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
   // workgroup per CU anyway, and fewer workgroups repeat the least squares
   // fewer times
   const int G = grid_for(npk, 1024, 256);
-  dim3 grid(G), block(1024);
   const size_t ls_work = ls_work_doubles(e.sp.d);
   const size_t bins = e.sp_kind != 0 ? (size_t)16 * e.sp.d : 0;
   const size_t lds = ((size_t)kMaxM + 2 + (ls_work > bins ? ls_work : bins)) * 8;
-  const int d = e.sp.d;
-  if (e.prec == 0) {
-    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<double, double, KIND>, lds);
-                      launch_k(e, true, e.sp_kind != 0, k_ls_update<double, double, KIND>, grid, block, lds, t, d, pending,
-                               zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                               (const double*)U, ldu, (const double*)w, (double*)unew, spart, e.sp));
-  } else if (e.prec == 1) {
-    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<float, float, KIND>, lds);
-                      launch_k(e, true, e.sp_kind != 0, k_ls_update<float, float, KIND>, grid, block, lds, t, d, pending,
-                               zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                               (const float*)U, ldu, (const float*)w, (float*)unew, spart, e.sp));
-  } else {
-    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<bf16_t, float, KIND>, lds);
-                      launch_k(e, true, e.sp_kind != 0, k_ls_update<bf16_t, float, KIND>, grid, block, lds, t, d, pending,
-                               zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                               (const bf16_t*)U, ldu, (const float*)w, (bf16_t*)unew, spart, e.sp));
-  }
+  // basis loads during the least squares where its own loads all come first
+  const bool pre = e.sp.d <= kRC * kLsPreS && t + 1 <= 64 && t + 1 >= kLsPreU;
+#define RKS_LSU(TV, TW)                                                                                          \
+  (pre ? ls_update_t<TV, TW, true>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, \
+                                   bd_rel, npk, U, ldu, w, unew, spart)                                         \
+       : ls_update_t<TV, TW, false>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, \
+                                    bd_rel, npk, U, ldu, w, unew, spart))
+  if (e.prec == 0) RKS_LSU(double, double);
+  else if (e.prec == 1) RKS_LSU(float, float);
+  else RKS_LSU(bf16_t, float);
+#undef RKS_LSU
   if (e.sp_kind == 0) {  // sketch of the stored value
     if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
     if (e.prec == 1) return gauss_t<float>(e, (const float*)unew, spart);
