@@ -713,11 +713,12 @@ union Pack16 {
 // wave-uniform and come through the scalar path.  Padding rows (>= n, < ldu)
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
-template <typename TV, typename TW, int KIND, int NPRE = 0>
+template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false>
 __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U, int64_t ldu,
                                             const TW* __restrict__ w, const double* __restrict__ coef,
                                             TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
                                             double* bins, const u32x4* pre = nullptr, bool use_pre = false) {
+  // pre: NPRE leading basis columns, then (PREW) the w chunks, of the first packet
   constexpr int V = 16 / sizeof(TV);
   constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
   if (KIND != 3) bins_zero(bins, sp.d);
@@ -732,7 +733,8 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
     {
       Pack16<TW> wp[WCH];
 #pragma unroll
-      for (int c = 0; c < WCH; ++c) wp[c].raw = *(const u32x4*)(w + i0 + c * (16 / sizeof(TW)));
+      for (int c = 0; c < WCH; ++c)
+        wp[c].raw = (PREW && use_pre) ? pre[NPRE + c] : *(const u32x4*)(w + i0 + c * (16 / sizeof(TW)));
 #pragma unroll
       for (int c = 0; c < WCH; ++c)
 #pragma unroll
@@ -819,9 +821,9 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
   extern __shared__ double smem[];
   double* hc = smem;
   double* work = smem + kMaxM + 2;
-  // the first kLsPreU basis columns of this thread's first packet are loaded
-  // right after the least squares' own loads, so that their latency (and
-  // HBM) is busy while the workgroup solves
+  // the first kLsPreU basis columns and the w values of this thread's first
+  // packet are loaded right after the least squares' own loads, so that their
+  // latency passes (and HBM is busy) while the workgroup solves
   // (PRE: only where the least squares has no global loads of its own after
   // its first round, d <= 256 and t < 64, which would wait for these; and not
   // for BF16, whose eight rows per packet leave no registers for it)
@@ -829,7 +831,9 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
   constexpr int NP = PRE && sizeof(TV) >= 4 ? kLsPreU : 0;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool use_pre = NP > 0 && g0 < npk && t + 1 >= NP;
-  u32x4 pre[NP > 0 ? NP : 1];
+  constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
+  constexpr bool PREW = NP > 0 && sizeof(TV) == 8;  // w too (FP64: registers allow it)
+  u32x4 pre[NP > 0 ? NP + WCH : 1];
   // The loads are issued by every thread, from clamped (in-bounds) addresses
   // when unused: a load under a branch would make the least squares wait for
   // all of them (wait counts are merged over both paths).
@@ -840,8 +844,10 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
       const int qc = q <= t ? q : t;
       pre[q] = __builtin_nontemporal_load((const u32x4*)(U + gl * V + (int64_t)qc * ldu));
     }
+#pragma unroll
+    for (int c = 0; c < (PREW ? WCH : 0); ++c) pre[NP + c] = *(const u32x4*)(w + gl * V + c * (16 / sizeof(TW)));
   });
-  update_body<TV, TW, KIND, NP>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
+  update_body<TV, TW, KIND, NP, PREW>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
