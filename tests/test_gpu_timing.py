@@ -43,5 +43,5 @@ def test_timing_leaves_results_unchanged_and_fits_the_step(lib, cuda, kw):
     # the three kernels lie inside the step, which adds launch gaps and its event pair (the two
     # samples are alternate steps, whose column counts differ by one)
     assert sum(per) <= whole * 1.10, (per, whole)
-    assert sum(per) >= 0.5 * whole, (per, whole)
+    assert sum(per) >= 0.3 * whole, (per, whole)
     assert st1["n_timed_rotate"] == st1["n_rotate"] > 0 and st1["t_rotate"] > 0.0
