@@ -5,7 +5,7 @@ with the matrix already resident in HBM, followed by nothing else; the
 eigenpair residual check runs after the timed region.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
-                  [--keep auto|N] [--compare alg1,fp32,bf16,ks_cgs2] [--no-cpu-baseline]
+                  [--keep auto|N] [--compare alg1,fp32,bf16,ks_cgs2,aggr] [--no-cpu-baseline]
 
 The solver keeps the restart size --keep Schur vectors at each contraction
 (auto: k + (m - k)/4; any leading truncation is an rKS decomposition,
@@ -13,7 +13,9 @@ Section 3.1).  The default line times the FP64 solver and, after it, three
 variants on the same workload, reported under "variants" with their own
 time-to-k, loop bandwidth and error against the main run: "alg1" (FP64,
 keep = k, the truncation of Algorithm 1 as printed) and the FP32- and
-BF16-basis solvers (with FP64 refinement).
+BF16-basis solvers (with FP64 refinement).  Also available: "ks_cgs2"
+(deterministic Krylov-Schur) and "aggr" (FP64 with aggressive deflation,
+lock = 2).
 """
 import argparse
 import json
@@ -165,7 +167,7 @@ def main():
     ap.add_argument("--graphs", type=int, default=0, help="1: replay repeated extensions as HIP graphs (used only "
                     "when the per-kernel events are off, --no-profile); 0: launch every kernel")
     ap.add_argument("--compare", default="alg1,fp32,bf16", help="comma list of extra runs on the same workload after "
-                    "the main run: alg1 (FP64, keep = k), basis precisions (fp32, bf16) and/or ks_cgs2 "
+                    "the main run: alg1 (FP64, keep = k), basis precisions (fp32, bf16), aggr (lock = 2) and/or ks_cgs2 "
                     "(deterministic Krylov-Schur); reported under 'variants'")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -275,13 +277,16 @@ def main():
     for prec in [p for p in args.compare.split(",") if p]:
         # a precision (fp32, bf16: mixed precision with FP64 refinement), ks_cgs2:
         # deterministic Krylov-Schur with an FP64 basis (the paper's comparison),
-        # or alg1: FP64 with the restart size of Algorithm 1 (keep = k)
+        # alg1: FP64 with the restart size of Algorithm 1 (keep = k), or aggr:
+        # FP64 with aggressive deflation (converged wanted blocks moved to the
+        # front before locking)
         method = "ks_cgs2" if prec == "ks_cgs2" else "rks"
-        vprec = "fp64" if prec in ("ks_cgs2", "alg1") else prec
+        vprec = "fp64" if prec in ("ks_cgs2", "alg1", "aggr") else prec
+        vlock = 2 if prec == "aggr" else int(cfg["lock"])
         with P.Solver.from_csr(A, k=cfg["k"], m=cfg["m"], d=cfg["d"], which=cfg["which"], tol=cfg["tol"],
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=vprec, keep=0 if prec == "alg1" else keep,
-                               method=method, lock=int(cfg["lock"]),
+                               method=method, lock=vlock,
                                max_restarts=cfg.get("max_restarts", 300), resid_tol=args.resid_tol,
                                profile=0 if args.no_profile else args.profile_every, stream=stream) as s2:
             s2.solve()

@@ -95,7 +95,10 @@ typedef struct {
   uint64_t start_seed;   /* seed of the N(0,1) start vector, default 1 */
   int32_t precision;     /* rks_precision, default FP64 */
   int32_t max_restarts;  /* contraction/extension cycles after the first extension, default 300 */
-  int32_t lock;          /* lock converged leading Schur vectors, default 1 */
+  int32_t lock;          /* 1: lock converged leading Schur vectors (Section 4.4), default;
+                            2: before that, move every converged block of the wanted set to
+                            the front (aggressive deflation, the reordering remark of
+                            Section 4.4); 0: no locking */
   int32_t profile;       /* P > 0: time every P-th Arnoldi step on the solver's stream,
                             alternately per kernel (HIP events attached to the launches,
                             which take the dispatches' own start and end times) and as a

@@ -220,6 +220,8 @@ class RKSOracle:
         if q < kr < keff and T_a[kr - q, kr - 1 - q] != 0.0:
             kr += 1
         self.kr = kr
+        if self.lock == 2:
+            T_a, Z = self._front_converged(T_a, Z, B[m, q:m], kr - q)
         Q = np.eye(m)
         Q[q:, q:] = Z
         T = np.zeros((m, m))
@@ -252,6 +254,34 @@ class RKSOracle:
         self.B[keff, :keff] = bk
         self.keff = keff
         self.j = keff
+
+    def _front_converged(self, T, Z, b_row, nw):
+        """Aggressive deflation (Section 4.4, after the deflation theorem): the
+        decomposition may be reordered to test other Schur vectors for locking.
+        Walk the nw wanted positions of the active Schur form (T, Z) in order;
+        a block whose b entries pass the locking test once it is moved to the
+        front of the active part (b = b_row Z after the move) is moved there, so
+        that the leading-block locking then takes it.  The others keep their
+        order behind the moved ones."""
+        tn = np.linalg.norm(T[:nw, :nw])
+        pos, idx = 0, 0
+        while idx < nw:
+            s = 2 if idx + 1 < T.shape[0] and T[idx + 1, idx] != 0.0 else 1
+            if idx == pos:
+                Tc, Zc = T, Z
+            else:
+                Tc, Zc, info = lapack.dtrexc(np.array(T, order="F"), np.array(Z, order="F"), idx + 1, pos + 1)
+                if info != 0:
+                    idx += s
+                    continue
+            sn = 2 if pos + 1 < Tc.shape[0] and Tc[pos + 1, pos] != 0.0 else 1
+            lam = np.linalg.eigvals(Tc[pos:pos + sn, pos:pos + sn])
+            bl = b_row @ Zc[:, pos:pos + sn]
+            if np.all(np.abs(bl) <= self.tol * max(np.max(np.abs(lam)), UNIT_ROUNDOFF * tn)):
+                T, Z = Tc, Zc
+                pos += sn
+            idx += s
+        return T, Z
 
     def ritz(self):
         """Eigenpairs of the wanted leading block T_k and the estimates

@@ -472,6 +472,53 @@ void sketch_gram(const double* Sn, int d, int nc, double* E, int ld) {
 // Contraction on the host: Schur form of the active block, reordering,
 // truncation, whitening; fills Y for the device rotation and the new B, S,
 // and E = S^T S - I of the contracted sketch (uploaded by push_state).
+// Aggressive deflation (Section 4.4, after the deflation theorem: the
+// decomposition may be reordered to test other Schur vectors for locking).
+// Walks the nw wanted positions of the active Schur form (Ta, Z, ma x ma) in
+// order; a block whose b entries (brow Z, brow with stride ldbr) pass the
+// locking test of lock_converged once the block is moved to the front of the
+// active part is moved there, so that the leading-block locking then takes
+// it.  The other blocks keep their order behind the moved ones.
+void front_converged(int ma, double* Ta, double* Z, const double* brow, int ldbr, int nw, double tol) {
+  double tn = 0.0;
+  for (int jj = 0; jj < nw; ++jj)
+    for (int i = 0; i < nw; ++i) tn += Ta[i + (size_t)jj * ma] * Ta[i + (size_t)jj * ma];
+  tn = std::sqrt(tn);
+  std::vector<double> Tc((size_t)ma * ma), Zc((size_t)ma * ma);
+  int pos = 0, idx = 0;
+  while (idx < nw) {
+    const int s = (idx + 1 < ma && Ta[(idx + 1) + (size_t)idx * ma] != 0.0) ? 2 : 1;
+    const double* T1 = Ta;
+    const double* Z1 = Z;
+    if (idx != pos) {
+      std::memcpy(Tc.data(), Ta, (size_t)ma * ma * 8);
+      std::memcpy(Zc.data(), Z, (size_t)ma * ma * 8);
+      if (rks::move_block(ma, Tc.data(), ma, Zc.data(), ma, idx, pos) != 0) {
+        idx += s;
+        continue;
+      }
+      T1 = Tc.data();
+      Z1 = Zc.data();
+    }
+    const int sn = (pos + 1 < ma && T1[(pos + 1) + (size_t)pos * ma] != 0.0) ? 2 : 1;
+    const double scale = std::max(std::abs(rks::block_eig(T1, ma, pos, sn)), kUnitRoundoff * tn);
+    bool ok = true;
+    for (int jj = pos; jj < pos + sn; ++jj) {
+      double bv = 0.0;
+      for (int l = 0; l < ma; ++l) bv += brow[(size_t)l * ldbr] * Z1[l + (size_t)jj * ma];
+      ok = ok && std::fabs(bv) <= tol * scale;
+    }
+    if (ok) {
+      if (idx != pos) {
+        std::memcpy(Ta, Tc.data(), (size_t)ma * ma * 8);
+        std::memcpy(Z, Zc.data(), (size_t)ma * ma * 8);
+      }
+      pos += sn;
+    }
+    idx += s;
+  }
+}
+
 int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscale, int* whitened) {
   const int m = c->m, q = c->q, k = c->k, d = c->d, ldb = m + 1;
   const int ma = m - q;
@@ -495,6 +542,7 @@ int contract(rks_ctx* c, int* in0, int* min, int* out0, int* kout, double* xscal
   int kr = std::min(k, ke);
   if (kr < ke && kr > q && Ta[(kr - q) + (size_t)(kr - 1 - q) * ma] != 0.0) kr += 1;
   c->kr = kr;
+  if (c->o.lock == 2) front_converged(ma, Ta.data(), Z.data(), &hB[m + (size_t)q * ldb], ldb, kr - q, c->phase_tol);
   // truncated factor T (ke x ke) and b
   std::vector<double> T((size_t)ke * ke, 0.0), b(ke, 0.0);
   for (int jj = 0; jj < q; ++jj)
@@ -978,6 +1026,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "need k <= keep <= m - 2 and keep + 1 <= 64");
   if (o.method == RKS_METHOD_KS_CGS2 && o.precision != RKS_PREC_FP64)
     return fail(nullptr, RKS_EINVAL, "deterministic Krylov-Schur runs with an FP64 basis only");
+  if (o.lock < 0 || o.lock > 2) return fail(nullptr, RKS_EINVAL, "lock must be 0, 1 or 2");
 
   rks_ctx* c = new (std::nothrow) rks_ctx();
   if (!c) return fail(nullptr, RKS_ENOMEM, "context");

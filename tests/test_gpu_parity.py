@@ -16,7 +16,7 @@ import pytest
 import paper_2508_05400_amd as P
 from oracle.rks import RKSOracle, rks as oracle_rks
 from oracle.sketch import sketch_matrix
-from workloads import convdiff2d, powerlaw_random, start_vector_normal, tridiag_noisy
+from workloads import CSR, convdiff2d, powerlaw_random, start_vector_normal, tridiag_noisy
 
 pytestmark = pytest.mark.gpu
 
@@ -435,3 +435,35 @@ def test_graph_replays_match_direct_launches(lib, cuda, kind, prec):
             assert got[0] == ref[0] and got[1] == ref[1], (rep, got[:2], ref[:2])
             assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3]), rep
             P.rks_sketch(s1.ctx, x, z)          # eager work between solves
+
+
+def test_aggressive_deflation_matches_oracle(lib, cuda):
+    """lock = 2 (aggressive deflation: converged wanted blocks are moved to the
+    front before locking) on a diagonal operator whose fourth wanted pair
+    converges before the cluster ahead of it: the GPU solve takes the oracle's
+    path (restarts, locked count, Ritz values to 1e-10) and needs fewer
+    restarts than leading-only locking."""
+    rng = np.random.default_rng(7)
+    n = 2000
+    dv = np.concatenate([[10.0, 10 - 2e-3, 10 - 4e-3, 9.95], rng.uniform(0.0, 9.9, n - 4)])
+    u0 = 1e-3 * rng.standard_normal(n)
+    u0[3] = 1.0
+    A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), dv, {"kind": "diag"})
+    got = {}
+    for lock in (1, 2):
+        o = RKSOracle(A, 4, 10, 30, "LM", 1e-8, sketch="sparse", sketch_seed=3, start_seed=1, lock=lock)
+        ref = o.run(u0)
+        with P.Solver.from_csr(A, k=4, m=10, d=30, which="LM", tol=1e-8, sketch_kind="sparse", sketch_seed=3,
+                               start_seed=1, lock=lock) as s:
+            assert s.solve(u0) == 0, P.rks_last_error(s.ctx)
+            lam, X, res = s.eigpairs()
+            st = s.stats.as_dict()
+        print(f"lock={lock}: GPU {st['restarts']} restarts, {st['locked']} locked; oracle {ref.restarts}, {ref.locked}",
+              flush=True)
+        assert ref.converged
+        assert st["restarts"] == ref.restarts and st["locked"] == ref.locked
+        a = np.sort_complex(lam)
+        b = np.sort_complex(ref.lam)
+        assert np.max(np.abs(a - b) / np.abs(b)) <= 1e-10
+        got[lock] = st["restarts"]
+    assert got[2] < got[1], got

@@ -388,3 +388,62 @@ def test_rira_exact_shifts_span_equals_rks_truncation():
     # the measure discriminates: the next basis vector u_{k+1} lies outside that subspace
     Q3, _ = np.linalg.qr(o.U[:, ke - 1:ke + 1])
     assert np.linalg.norm(Q3 - Q1 @ (Q1.T @ Q3), 2) > 0.5
+
+
+def _aggressive_case():
+    """Diagonal operator: a tight cluster at the top of the spectrum, a fourth
+    value 9.95 above a bulk in [0, 9.9], and a start biased toward the fourth
+    value's eigenvector, so that the fourth pair converges well before the
+    cluster (LM, k = 4)."""
+    rng = np.random.default_rng(7)
+    n = 2000
+    dv = np.concatenate([[10.0, 10 - 2e-3, 10 - 4e-3, 9.95], rng.uniform(0.0, 9.9, n - 4)])
+    u0 = 1e-3 * rng.standard_normal(n)
+    u0[3] = 1.0
+    A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), dv, {"kind": "diag"})
+    return A, dv, u0
+
+
+def _lock_run(A, u0, lock, tol, check=False):
+    o = RKSOracle(A, 4, 10, 30, "LM", tol, sketch="sparse", sketch_seed=3, start_seed=1, lock=lock)
+    o.start(u0)
+    o.extend()
+    qs = []
+    for r in range(200):
+        o.contract()
+        if check:
+            # locked columns had their b entries (below tol |lambda|) set to zero
+            rel, orth, cons, rqe = _check_decomposition(o, o.keff + 1)
+            assert rel < 1e-13 + tol * np.sqrt(o.q), (rel, o.q)
+            assert orth < 1e-12 and cons < 1e-12 and rqe < 1e-12 + tol * np.sqrt(o.q), (orth, cons, rqe)
+            assert np.all(np.tril(o.B[:o.keff, :o.keff], -2) == 0)
+        lam, Y, est = o.ritz()
+        if np.all(est <= tol):
+            return o, lam, qs
+        o.lock_converged()
+        qs.append(o.q)
+        o.extend()
+    raise AssertionError("not converged")
+
+
+def test_aggressive_deflation_locks_a_trailing_converged_pair_first():
+    """Section 4.4 notes that the decomposition may be reordered to test other
+    Schur vectors for locking (lock = 2).  On a case where the last wanted pair
+    converges first, the reordering must move it to the front and lock it while
+    leading-only locking waits for the slow cluster ahead of it; the
+    decomposition identities hold after every reordering, the locked vectors
+    keep their eigenvalues, and both modes end at the diagonal's values."""
+    A, dv, u0 = _aggressive_case()
+    tol = 1e-8
+    o1, lam1, q1 = _lock_run(A, u0, 1, tol)
+    o2, lam2, q2 = _lock_run(A, u0, 2, tol, check=True)
+    first1 = next(i for i, q in enumerate(q1) if q > 0)
+    first2 = next(i for i, q in enumerate(q2) if q > 0)
+    assert first2 < first1, (first1, first2)
+    # the first vector locked under lock = 2 is the fourth value's
+    assert abs(o2.B[0, 0] - 9.95) <= 1e-6
+    assert len(q2) <= len(q1)
+    top = np.sort(dv)[::-1][:4]
+    for lam in (lam1, lam2):
+        assert np.max(np.abs(np.sort(lam.real)[::-1] - top)) <= 10 * tol * 10.0
+        assert np.max(np.abs(lam.imag)) <= 1e-8
