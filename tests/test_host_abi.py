@@ -103,6 +103,10 @@ def test_create_rejects_bad_arguments(lib):
         P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 0.0)
     with pytest.raises(P.RksError):
         P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 1e-10, P.rks_opts_default(zeta=9))
+    for lock in (-1, 3):  # 0 off, 1 leading blocks, 2 aggressive
+        with pytest.raises(P.RksError) as ei:
+            P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 1e-10, P.rks_opts_default(lock=lock))
+        assert ei.value.code == -1
     # malformed CSR: decreasing row pointer, column out of range, unsorted row
     rp = A.row_ptr.copy(); rp[5] = rp[4] - 1
     with pytest.raises(P.RksError):
