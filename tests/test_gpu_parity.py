@@ -163,17 +163,20 @@ CONV = {
     "cd2d-40-LM-gauss": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LM", "gauss", 0),
     # restart size 14 of m = 24 (k = 6)
     "cd2d-40-LR-sparse-keep14": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 14),
+    # aggressive deflation (lock = 2) on a case with complex Ritz pairs
+    "cd2d-40-LR-sparse-aggr": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 14, 2),
 }
 
 
 @pytest.mark.parametrize("case", sorted(CONV))
 def test_solve_parity_converged(lib, cuda, case):
-    mk, k, m, d, which, kind, keep = CONV[case]
+    mk, k, m, d, which, kind, keep, *rest = CONV[case]
+    lock = rest[0] if rest else 1
     A = mk()
-    ref = oracle_rks(A, k, m, d, which, 1e-10, sketch=kind, sketch_seed=3, start_seed=1, keep=keep)
+    ref = oracle_rks(A, k, m, d, which, 1e-10, sketch=kind, sketch_seed=3, start_seed=1, keep=keep, lock=lock)
     assert ref.converged
     s = P.Solver.from_csr(A, k=k, m=m, d=d, which=which, tol=1e-10, sketch_kind=kind, sketch_seed=3,
-                          start_seed=1, keep=keep)
+                          start_seed=1, keep=keep, lock=lock)
     try:
         code = s.solve()
         assert code == 0, P.rks_last_error(s.ctx)
