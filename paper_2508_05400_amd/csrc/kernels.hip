@@ -1345,10 +1345,12 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
                      double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart) {
   const int V = 16 / e.vbytes();
   const int64_t npk = (e.n + V - 1) / V;
-  // one workgroup per CU (256): the kernel's registers allow one 1024-thread
-  // workgroup per CU anyway, and fewer workgroups repeat the least squares
-  // fewer times
-  const int G = grid_for(npk, 1024, 256);
+  // at most one workgroup per CU (256): the kernel's registers allow one
+  // 1024-thread workgroup per CU anyway, and fewer workgroups repeat the least
+  // squares fewer times; the count is trimmed so that every workgroup makes
+  // the same number of grid-stride passes
+  const int64_t passes = (npk + 256 * 1024 - 1) / (256 * 1024);
+  const int G = grid_for(npk, (int)(1024 * passes), 256);
   const size_t ls_work = ls_work_doubles(e.sp.d);
   const size_t bins = e.sp_kind != 0 ? (size_t)16 * e.sp.d : 0;
   const size_t lds = ((size_t)kMaxM + 2 + (ls_work > bins ? ls_work : bins)) * 8;
