@@ -165,3 +165,15 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
         py = structs[cname]
         got = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
         assert got == int(val), (cname, field, got, val)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with a message before
+    touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
