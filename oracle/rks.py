@@ -28,13 +28,18 @@ Readings where the paper is open (listed with the reasons in the design notes):
   * breakdown (an invariant subspace): when beta <= 1e-12 ||Omega w|| the new
     vector is replaced by a seeded random vector sketch-orthogonalised against
     U_j, and B(j+1, j) is set to 0.
-  * convergence: all effective-k estimates <= tol; at most max_restarts
+  * convergence: all effective-k estimates <= tol (or, with resid_tol > 0,
+    every wanted pair's FP64 residual <= resid_tol); at most max_restarts
     contraction/extension cycles after the first extension.
+  * restart size keep (Algorithm 1 truncates to k): any leading truncation is
+    again an rKS decomposition (Section 3.1); keep = -1 takes
+    k + (m - k) // 4, at most m - 2.
 
 Pins (tests/test_oracle_pins.py): the decomposition's identities through
 restarts, textbook Arnoldi for Omega = I, closed-form convection-diffusion
 spectra, dense brute force, the Section 4.1 residual bound, breakdown
-recovery, scale invariance.  Parity unpinned: the eigenvalues it returns for
+recovery, whitening of a decomposition with a non-orthonormal sketch,
+scale invariance.  Parity unpinned: the eigenvalues it returns for
 strongly non-normal operators (condition numbers 1e11-1e13, as on the 1000^2
 smallest-real-part workload) have no reference at that accuracy; only their
 residuals are checked there.
@@ -124,15 +129,15 @@ class RKSOracle:
 
     def __init__(self, A, k, m, d, which="LM", tol=1e-10, sketch="sparse", zeta=8,
                  sketch_seed=0, start_seed=1, lock=True, whiten_tol=1e-12,
-                 max_restarts=300, keep=None):
+                 max_restarts=300, keep=None, resid_tol=0.0):
         if hasattr(A, "row_ptr"):
             A = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
         self.A = sp.csr_matrix(A, dtype=np.float64)
         n = self.A.shape[0]
         if not (1 <= k and k + 2 <= m and m + 1 <= d and d <= n and m + 1 <= n):
             raise ValueError("need 1 <= k, k+2 <= m, m+1 <= d <= n")
-        if keep == -1:      # automatic: k + (m - k) / 4, at most m - 2 and 63 (as the library)
-            keep = max(k, min(k + (m - k) // 4, m - 2, 63))
+        if keep == -1:      # automatic: k + (m - k) / 4, at most m - 2
+            keep = max(k, min(k + (m - k) // 4, m - 2))
         keep = k if not keep else keep
         if not (k <= keep <= m - 2):
             raise ValueError("need k <= keep <= m-2")
@@ -143,6 +148,10 @@ class RKSOracle:
         self.keep = keep
         self.which, self.tol, self.lock = which, tol, lock
         self.whiten_tol, self.max_restarts = whiten_tol, max_restarts
+        # > 0: also stop once every wanted pair's FP64 residual
+        # ||A x - lambda x|| / (||A||_1 ||x||) is <= resid_tol (checked after
+        # every contraction)
+        self.resid_tol = resid_tol
         self.start_seed = start_seed
         self.Om = sketch_matrix(n, d, sketch, sketch_seed, zeta)
         self.normA1 = float(abs(self.A).sum(axis=0).max())
@@ -178,33 +187,39 @@ class RKSOracle:
         return sla.solve_triangular(Rs, Qs.T @ z)
 
     # -- Algorithm 2 ---------------------------------------------------------
+    def _new_direction(self, j, v):
+        """Sketched Gram-Schmidt of v against the first j+1 columns: the
+        coefficients h solve min ||S_j h - Omega v|| and the remainder
+        v - U_j h is returned with its sketch (taken from the remainder
+        itself, not updated from the sketches)."""
+        h = self.lstsq(self.S[:, :j + 1], self.sketch(v))
+        rem = v - self.U[:, :j + 1] @ h
+        return h, rem, self.sketch(rem)
+
     def extend(self):
-        """Grow the sketch-orthonormal Krylov decomposition from j+1 to m+1 columns."""
+        """Algorithm 2: grow the sketch-orthonormal Krylov decomposition
+        A U_m = U_{m+1} B from j+1 to m+1 columns.  Column j+1 is the
+        remainder of A u_j after the sketched projection onto U_j, scaled to a
+        unit sketch; its scale is the subdiagonal entry of B.  A remainder
+        whose sketch vanishes against that of A u_j (an invariant subspace,
+        Section 2.1) is replaced by a seeded random direction treated the same
+        way, with a zero subdiagonal entry."""
         for j in range(self.j, self.m):
-            w = self.A @ self.U[:, j]                      # apply A
+            Au = self.A @ self.U[:, j]
             self.matvecs += 1
-            z = self.sketch(w)                             # sketch
-            Sj = self.S[:, :j + 1]
-            h = self.lstsq(Sj, z)                          # low-dimensional projection
-            ut = w - self.U[:, :j + 1] @ h                 # high-dimensional update
-            st = self.sketch(ut)                           # re-sketch
-            beta = np.linalg.norm(st)
+            h, rem, srem = self._new_direction(j, Au)
             self.B[:j + 1, j] = h
-            if beta <= BREAKDOWN_REL * np.linalg.norm(z):
-                # invariant subspace: continue from a fresh direction, B(j+1, j) = 0
+            scale = np.linalg.norm(srem)
+            sub = scale
+            if scale <= BREAKDOWN_REL * np.linalg.norm(self.sketch(Au)):
                 self.breakdowns += 1
                 r = breakdown_vector(self.n, self.start_seed, self.breakdowns)
-                hr = self.lstsq(Sj, self.sketch(r))
-                ut = r - self.U[:, :j + 1] @ hr
-                st = self.sketch(ut)
-                nb = np.linalg.norm(st)
-                self.U[:, j + 1] = ut / nb
-                self.S[:, j + 1] = st / nb
-                self.B[j + 1, j] = 0.0
-            else:
-                self.U[:, j + 1] = ut / beta               # augment basis
-                self.S[:, j + 1] = st / beta               # augment sketched basis
-                self.B[j + 1, j] = beta                    # augment Rayleigh quotient
+                _, rem, srem = self._new_direction(j, r)
+                scale = np.linalg.norm(srem)
+                sub = 0.0
+            self.U[:, j + 1] = rem / scale
+            self.S[:, j + 1] = srem / scale
+            self.B[j + 1, j] = sub
         self.j = self.m
 
     # -- Algorithm 1, contraction -------------------------------------------
@@ -242,18 +257,25 @@ class RKSOracle:
         # whitening (Section 3.3)
         Sk = self.S[:, :keff]
         if np.linalg.norm(Sk.T @ Sk - np.eye(keff)) > self.whiten_tol:
-            Qs, R = np.linalg.qr(Sk, mode="reduced")
-            Rinv = sla.solve_triangular(R, np.eye(keff))
-            self.U[:, :keff] = self.U[:, :keff] @ Rinv
-            self.S[:, :keff] = Qs
-            Tk = R @ Tk @ Rinv
-            bk = bk @ Rinv
-            self.whitenings += 1
+            Tk, bk = self.whiten(Tk, bk)
         self.B[:] = 0.0
         self.B[:keff, :keff] = Tk
         self.B[keff, :keff] = bk
         self.keff = keff
         self.j = keff
+
+    def whiten(self, Tk, bk):
+        """Section 3.3: with S_k = Q_s R (thin QR), the decomposition
+        A U_k = U_k T + u bT is equivalent to one in U_k R^-1, whose sketch is
+        Q_s (orthonormal): T becomes R T R^-1 and bT becomes bT R^-1.
+        Updates U and S in place and returns the new (T, b)."""
+        keff = Tk.shape[0]
+        Qs, R = np.linalg.qr(self.S[:, :keff], mode="reduced")
+        Rinv = sla.solve_triangular(R, np.eye(keff))
+        self.U[:, :keff] = self.U[:, :keff] @ Rinv
+        self.S[:, :keff] = Qs
+        self.whitenings += 1
+        return R @ Tk @ Rinv, bk @ Rinv
 
     def _front_converged(self, T, Z, b_row, nw):
         """Aggressive deflation (Section 4.4, after the deflation theorem): the
@@ -323,6 +345,11 @@ class RKSOracle:
             lam, Y, est = self.ritz()
             history.append(float(np.max(est)))
             converged = bool(np.all(est <= self.tol))
+            if not converged and self.resid_tol > 0.0:
+                X = self.U[:, :self.kr] @ Y
+                R = self.A @ X - X * lam[None, :]
+                res = np.linalg.norm(R, axis=0) / (self.normA1 * np.linalg.norm(X, axis=0))
+                converged = bool(np.all(res <= self.resid_tol))
             if converged or restarts >= self.max_restarts:
                 break
             if self.lock:
