@@ -58,6 +58,32 @@ UNIT_ROUNDOFF = 2.0**-53
 BREAKDOWN_REL = 1e-12
 
 
+def round_storage(x, store):
+    """Round FP64 values to a basis storage format, to nearest with ties to
+    even: 'fp64' leaves them, 'fp32' rounds to binary32, 'bf16' rounds to
+    binary32 and then to bfloat16 (binary32's sign and exponent with an 8-bit
+    significand).  The bfloat16 step is written out from the definition: the
+    two neighbouring bfloat16 values bracket the binary32 value, the nearer
+    one is taken, and a tie goes to the one whose last significand bit is 0."""
+    x = np.asarray(x, dtype=np.float64)
+    if store == "fp64":
+        return x.copy()
+    x32 = x.astype(np.float32)
+    if store == "fp32":
+        return x32.astype(np.float64)
+    if store != "bf16":
+        raise ValueError(f"unknown storage format {store!r}")
+    bits = x32.view(np.uint32)
+    down = (bits & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)   # toward zero
+    up_bits = (bits & np.uint32(0xFFFF0000)) + np.uint32(0x10000)               # next magnitude
+    up = up_bits.view(np.float32).astype(np.float64)
+    v = x32.astype(np.float64)
+    dd, du = np.abs(v - down), np.abs(up - v)
+    down_even = ((bits >> np.uint32(16)) & np.uint32(1)) == 0
+    take_up = (du < dd) | ((du == dd) & ~down_even & (dd > 0))
+    return np.where(take_up, up, down)
+
+
 def which_key(lam: complex, which: str):
     """Sort key, larger = more wanted (ties: larger imaginary part first)."""
     lam = complex(lam)
@@ -129,7 +155,8 @@ class RKSOracle:
 
     def __init__(self, A, k, m, d, which="LM", tol=1e-10, sketch="sparse", zeta=8,
                  sketch_seed=0, start_seed=1, lock=True, whiten_tol=1e-12,
-                 max_restarts=300, keep=None, resid_tol=0.0):
+                 max_restarts=300, keep=None, resid_tol=0.0,
+                 store="fp64"):
         if hasattr(A, "row_ptr"):
             A = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
         self.A = sp.csr_matrix(A, dtype=np.float64)
@@ -152,6 +179,18 @@ class RKSOracle:
         # ||A x - lambda x|| / (||A||_1 ||x||) is <= resid_tol (checked after
         # every contraction)
         self.resid_tol = resid_tol
+        # storage format of the basis: 'fp64', or 'fp32' / 'bf16' for the
+        # low-precision pattern (the product with A then runs on binary32
+        # copies of A's values and its result is rounded to binary32; the
+        # stored column is the unnormalised remainder rounded to the format,
+        # its scale 1/beta is kept in FP64, and the sketch is taken of the
+        # stored value)
+        self.store = store
+        if store != "fp64":
+            self.A_low = sp.csr_matrix((round_storage(self.A.data, "fp32"), self.A.indices, self.A.indptr),
+                                       shape=self.A.shape)
+            self.stored = np.zeros((self.A.shape[0], m + 1))   # stored values v_j
+            self.cs = np.zeros(m + 1)                          # u_j = cs_j v_j
         self.start_seed = start_seed
         self.Om = sketch_matrix(n, d, sketch, sketch_seed, zeta)
         self.normA1 = float(abs(self.A).sum(axis=0).max())
@@ -173,9 +212,10 @@ class RKSOracle:
     # -- start (Algorithm 2 with no initial decomposition) -------------------
     def start(self, u0=None):
         ut = start_vector(self.n, self.start_seed) if u0 is None else np.asarray(u0, dtype=np.float64)
+        ut = round_storage(ut, self.store)
         s = self.sketch(ut)
         nrm = np.linalg.norm(s)
-        self.U[:, 0] = ut / nrm
+        self._set_column(0, ut, nrm)
         self.S[:, 0] = s / nrm
         self.j = 0
 
@@ -187,13 +227,32 @@ class RKSOracle:
         return sla.solve_triangular(Rs, Qs.T @ z)
 
     # -- Algorithm 2 ---------------------------------------------------------
+    def _set_column(self, j, v, scale):
+        """u_j = v / scale (with a low-precision basis v is the stored value
+        and 1/scale its FP64 scale)."""
+        if self.store == "fp64":
+            self.U[:, j] = v / scale
+        else:
+            self.stored[:, j] = v
+            self.cs[j] = 1.0 / scale
+            self.U[:, j] = v * self.cs[j]
+
+    def apply(self, j):
+        """A u_j.  With a low-precision basis, u_j = c_j v_j is a stored
+        vector v_j times its FP64 scale c_j: the product A v_j is formed from
+        binary32 copies of A's values and rounded to binary32, then scaled."""
+        if self.store == "fp64":
+            return self.A @ self.U[:, j]
+        w = round_storage(self.A_low @ self.stored[:, j], "fp32")
+        return self.cs[j] * w
+
     def _new_direction(self, j, v):
         """Sketched Gram-Schmidt of v against the first j+1 columns: the
         coefficients h solve min ||S_j h - Omega v|| and the remainder
         v - U_j h is returned with its sketch (taken from the remainder
         itself, not updated from the sketches)."""
         h = self.lstsq(self.S[:, :j + 1], self.sketch(v))
-        rem = v - self.U[:, :j + 1] @ h
+        rem = round_storage(v - self.U[:, :j + 1] @ h, self.store)
         return h, rem, self.sketch(rem)
 
     def extend(self):
@@ -205,7 +264,7 @@ class RKSOracle:
         Section 2.1) is replaced by a seeded random direction treated the same
         way, with a zero subdiagonal entry."""
         for j in range(self.j, self.m):
-            Au = self.A @ self.U[:, j]
+            Au = self.apply(j)
             self.matvecs += 1
             h, rem, srem = self._new_direction(j, Au)
             self.B[:j + 1, j] = h
@@ -217,7 +276,7 @@ class RKSOracle:
                 _, rem, srem = self._new_direction(j, r)
                 scale = np.linalg.norm(srem)
                 sub = 0.0
-            self.U[:, j + 1] = rem / scale
+            self._set_column(j + 1, rem, scale)
             self.S[:, j + 1] = srem / scale
             self.B[j + 1, j] = sub
         self.j = self.m
@@ -258,6 +317,14 @@ class RKSOracle:
         Sk = self.S[:, :keff]
         if np.linalg.norm(Sk.T @ Sk - np.eye(keff)) > self.whiten_tol:
             Tk, bk = self.whiten(Tk, bk)
+        if self.store != "fp64":
+            # the rotated columns and u_{k+1} are stored rounded with scale 1;
+            # S keeps the FP64 truncated sketch (not re-sketched)
+            self.U[:, :keff + 1] = round_storage(self.U[:, :keff + 1], self.store)
+            self.stored[:] = 0.0
+            self.stored[:, :keff + 1] = self.U[:, :keff + 1]
+            self.cs[:] = 0.0
+            self.cs[:keff + 1] = 1.0
         self.B[:] = 0.0
         self.B[:keff, :keff] = Tk
         self.B[keff, :keff] = bk

@@ -550,3 +550,90 @@ def test_algorithm1_truncation_stalls_on_the_small_2d_workload():
     auto = RKSOracle(A, 10, 40, 80, "LR", 1e-10, keep=-1, **kw).run()
     assert not alg1.converged and alg1.restarts == 300 and alg1.resid.max() > 1e-6
     assert auto.converged and auto.restarts <= 60 and auto.resid.max() <= 1e-8
+
+
+def _bf16_grid():
+    """Every finite non-negative bfloat16 value, ascending, with its bit pattern."""
+    pat = np.arange(0x7F80, dtype=np.uint32)
+    vals = (pat << np.uint32(16)).view(np.float32).astype(np.float64)
+    return vals, pat
+
+
+def test_round_storage_bf16_brute_force():
+    """bfloat16 rounding (through binary32) against a search over every
+    bfloat16 value: the nearest one, ties to the even bit pattern."""
+    from oracle.rks import round_storage
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(20000) * 10.0 ** rng.uniform(-35, 35, 20000)
+    # exact ties and near-ties around 1 and 2
+    x = np.concatenate([x, [1 + 2**-8, 1 + 3 * 2**-8, -(1 + 2**-8), 1 + 2**-8 + 2**-20, 2 - 2**-9, 3.0, 0.0]])
+    grid, pat = _bf16_grid()
+    x32 = x.astype(np.float32).astype(np.float64)   # the binary32 step
+    a = np.abs(x32)
+    i = np.clip(np.searchsorted(grid, a), 1, len(grid) - 1)
+    lo, hi = grid[i - 1], grid[i]
+    pick_hi = (hi - a < a - lo) | ((hi - a == a - lo) & (pat[i] % 2 == 0))
+    ref = np.where(pick_hi, hi, lo) * np.sign(x32)
+    got = round_storage(x, "bf16")
+    assert np.array_equal(got, ref)
+    assert got[-7] == 1.0 and got[-6] == 1 + 2**-6 and got[-5] == -1.0 and got[-4] == 1 + 2**-7
+    assert np.array_equal(round_storage(x, "fp32"), x32)
+
+
+@pytest.mark.parametrize("store,u_low", [("fp32", 2.0**-24), ("bf16", 2.0**-8)])
+def test_low_precision_extension_is_a_rounded_decomposition(store, u_low):
+    """Low-precision basis in the oracle: every stored column is exactly
+    representable in the storage format and is the normalised column times
+    its FP64 scale; the sketch is that of the stored value (S = Omega U to
+    FP64); and the Krylov relation misses, column by column and entry by
+    entry, only the rounding of the product with A (binary32 values and
+    result) and of the stored remainder (storage unit roundoff u_low)."""
+    A = convdiff2d(30, (20.0, 10.0))
+    k, m, d = 5, 16, 48
+    o = RKSOracle(A, k, m, d, "LR", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1, store=store)
+    o.start()
+    o.extend()
+    from oracle.rks import round_storage
+    V = o.stored[:, :m + 1]
+    assert np.array_equal(round_storage(V, store), V)
+    assert np.array_equal(o.U[:, :m + 1], V * o.cs[None, :m + 1])
+    assert np.linalg.norm(np.asarray(o.Om @ o.U) - o.S) < 1e-14
+    # entrywise relation bound from the rounding model
+    Ad = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    Aabs = abs(Ad)
+    u32 = 2.0**-24
+    for j in range(m):
+        res = Ad @ o.U[:, j] - o.U[:, :j + 2] @ o.B[:j + 2, j]
+        r = o.U[:, :j + 2] @ o.B[:j + 2, j]           # the stored remainder plus U_j h, as computed
+        bound = (u_low * np.abs(r) + o.U[:, :j + 1].__abs__() @ np.abs(o.B[:j + 1, j]) * u_low
+                 + 3 * u32 * (Aabs @ np.abs(o.U[:, j])) + 1e-14 * (Aabs @ np.abs(o.U[:, j])))
+        assert np.all(np.abs(res) <= bound), (j, np.max(np.abs(res) / bound))
+    # and it is not FP64: the relation error is of the storage roundoff's order
+    rel = np.linalg.norm(Ad @ o.U[:, :m] - o.U @ o.B) / (o.normA1 * np.linalg.norm(o.U[:, :m]))
+    assert 1e-3 * u_low < rel < 10 * u_low
+
+
+def test_store_fp64_is_the_plain_oracle():
+    A = convdiff2d(20, (6.0, 3.0))
+    a = rks(A, 4, 16, 40, "LR", 1e-10, sketch="sparse", sketch_seed=1, store="fp64")
+    b = rks(A, 4, 16, 40, "LR", 1e-10, sketch="sparse", sketch_seed=1)
+    assert np.array_equal(a.lam, b.lam) and a.restarts == b.restarts
+
+
+def test_low_precision_residual_floor():
+    """A basis stored in bfloat16 cannot carry eigenvectors below its
+    roundoff: the oracle's bfloat16 run stalls at a residual of the order of
+    u_low = 2^-8 (times a modest factor), while binary32 storage reaches
+    about its own u_low and FP64 goes to the tolerance.  This is why a
+    low-precision solve needs an FP64 phase to reach residual 1e-8."""
+    A = convdiff2d(30, (2.0, 1.0))
+    kw = dict(sketch="sparse", sketch_seed=3, start_seed=1, max_restarts=40)
+    r64 = rks(A, 4, 20, 50, "LR", 1e-12, **kw)
+    r32 = rks(A, 4, 20, 50, "LR", 1e-12, store="fp32", **kw)
+    r16 = rks(A, 4, 20, 50, "LR", 1e-12, store="bf16", **kw)
+    assert r64.converged and r64.resid.max() < 1e-11
+    # the estimates |b^T y| / |lambda| reach the tolerance in every format;
+    # they cannot see the rounding of the stored basis, the true residual can
+    assert r32.converged and r16.converged
+    assert 1e-9 < r32.resid.max() < 1e-5
+    assert 1e-5 < r16.resid.max() < 1e-1
