@@ -37,7 +37,7 @@ extern "C" {
 #define RKS_EHIP (-3)        /* a HIP runtime call failed */
 #define RKS_ENAN (-4)        /* NaN/Inf in A, in u0 or in the iteration */
 #define RKS_ESTATE (-5)      /* call order violated (e.g. eigpairs before solve) */
-#define RKS_EBREAKDOWN (-6)  /* an exact invariant subspace stopped the extension */
+#define RKS_EBREAKDOWN (-6)  /* an exact invariant subspace that could not be continued past */
 #define RKS_EDENSE (-7)      /* small dense step failed (QR iteration / reordering) */
 
 /* Which part of the spectrum (Section 5: largest / smallest modulus; also
@@ -153,6 +153,7 @@ typedef struct {
   int32_t locked;        /* locked (deflated) leading Schur vectors at exit */
   int32_t keff;          /* effective number of pairs (k or k+1, Section 3.1) */
   int32_t whitenings;    /* whitening steps applied */
+  int32_t breakdowns;    /* invariant subspaces met and continued past (Section 2.1) */
   int32_t dense_fail;    /* reorderings that had to stop early */
   double max_est;        /* max |b^T y| / |lambda| at exit (eq. "rks_reserror_bound") */
   int32_t stop_reason;   /* 0 restart cap, 1 estimates <= tol, 2 verified residuals <= resid_tol */
@@ -161,6 +162,7 @@ typedef struct {
   int32_t restarts_lo;   /* restarts of the low-precision phase (mixed precision) */
   int32_t refined;       /* 1 if an FP64 refinement phase ran */
   double t_lo;           /* seconds of the low-precision phase */
+  double max_resid_lo;   /* largest FP64 residual verified at the end of the low-precision phase */
   double t_total;        /* seconds, host wall clock of the solve */
   double t_host;         /* seconds spent in the host small dense steps */
   /* kernel timings (only when opts.profile > 0), seconds summed over the timed launches */
@@ -196,6 +198,12 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
  * Section 5), when opts.resid_tol > 0 and every FP64 residual is verified to
  * be <= resid_tol, or after max_restarts cycles (RKS_ENOTCONV).  Synchronises
  * with the host once per restart.
+ * An exact invariant subspace (a vanishing remainder in the extension,
+ * Section 2.1) is continued past: the column is replaced by a seeded random
+ * vector sketch-orthogonalised against the basis, with a zero subdiagonal
+ * entry in B, so the exact pairs stay in the decomposition; RKS_EBREAKDOWN
+ * only when that fails (the product with A of the replacement vanishes too,
+ * as for the zero operator).  Deterministic Krylov-Schur does not continue.
  * Errors: RKS_EINVAL, RKS_ENAN, RKS_EBREAKDOWN, RKS_EDENSE, RKS_EHIP. */
 int rks_solve(struct rks_ctx* ctx, const double* u0, int32_t u0_on_device, rks_stats* st);
 
@@ -234,7 +242,8 @@ int rks_spmv_sketch(struct rks_ctx* ctx, const double* x_dev, double* w_dev, dou
 
 /* Start from u0 (as in rks_solve) and run Algorithm 2 from one to m+1 basis
  * columns, leaving the extended sketch-orthonormal Krylov decomposition
- * A U_m = U_{m+1} B in the context (no contraction). */
+ * A U_m = U_{m+1} B in the context (no contraction); breakdowns are
+ * continued past as in rks_solve. */
 int rks_arnoldi(struct rks_ctx* ctx, const double* u0, int32_t u0_on_device);
 
 /* Copy the current decomposition to the host: *ncols basis columns

@@ -40,10 +40,11 @@ class RksOpts(ctypes.Structure):
 class RksStats(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("matvecs", ctypes.c_int64), ("locked", ctypes.c_int32), ("keff", ctypes.c_int32),
-                ("whitenings", ctypes.c_int32), ("dense_fail", ctypes.c_int32),
+                ("whitenings", ctypes.c_int32), ("breakdowns", ctypes.c_int32), ("dense_fail", ctypes.c_int32),
                 ("max_est", ctypes.c_double), ("stop_reason", ctypes.c_int32),
                 ("resid_checks", ctypes.c_int32), ("max_resid", ctypes.c_double),
                 ("restarts_lo", ctypes.c_int32), ("refined", ctypes.c_int32), ("t_lo", ctypes.c_double),
+                ("max_resid_lo", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("t_host", ctypes.c_double),
                 ("t_spmv", ctypes.c_double), ("t_reduce", ctypes.c_double), ("t_ls", ctypes.c_double),
                 ("t_update", ctypes.c_double), ("t_rotate", ctypes.c_double),

@@ -395,8 +395,15 @@ __global__ __launch_bounds__(1024) void k_ls(int t, int d, int pending, int fina
     if (tid == 0) {
       cs[t] = inv;
       if (t > 0) {
-        B[t + (size_t)(t - 1) * ldb] = beta;
-        if (!(beta > bd_rel * scal[0]) && flags[0] == 0) flags[0] = t;
+        // column t replaces a vanished remainder: its subdiagonal entry is 0
+        const bool repl = flags[1] == t;
+        B[t + (size_t)(t - 1) * ldb] = repl ? 0.0 : beta;
+        if (repl) flags[1] = 0;
+        const double sc = scal[0];
+        if (!(beta > bd_rel * sc) && flags[0] == 0) {
+          flags[0] = t;
+          flags[2] = sc == 0.0 ? 1 : 0;
+        }
       }
     }
     ct = inv;
@@ -554,10 +561,11 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
   const double csv = (tid < 64 && tid < t) ? cs[tid] : 0.0;
   const double etv = (!pending && tid < 64 && tid <= t) ? E[tid + (size_t)t * ldb] : 0.0;  // E(tid, t)
   double sc0 = 0.0;
-  int fl0 = 1;
+  int fl0 = 1, fl1 = -1;
   if (writer && tid == 0 && pending && t > 0) {
     sc0 = scal[0];
     fl0 = flags[0];
+    fl1 = flags[1];
   }
   // the caller's loads go after these (loads complete in order, so waiting
   // for the ones above does not wait for them)
@@ -653,8 +661,14 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
         if (pending) {
           cs[t] = inv;
           if (t > 0) {
-            B[t + (size_t)(t - 1) * ldb] = beta;
-            if (!(beta > bd_rel * sc0) && fl0 == 0) flags[0] = t;
+            // column t replaces a vanished remainder: its subdiagonal entry is 0
+            const bool repl = fl1 == t;
+            B[t + (size_t)(t - 1) * ldb] = repl ? 0.0 : beta;
+            if (repl) flags[1] = 0;
+            if (!(beta > bd_rel * sc0) && fl0 == 0) {
+              flags[0] = t;
+              flags[2] = sc0 == 0.0 ? 1 : 0;
+            }
           }
         }
       }
@@ -952,12 +966,13 @@ __global__ void k_ks_finalize(int t, const double* __restrict__ h, const double*
   }
 }
 
-// First column: u0 (device FP64) or the seeded N(0,1) start, stored in the
-// basis precision when `store`; partials of Omega of the stored value.
+// First column: u0 (device FP64) or a seeded N(0,1) vector (Philox counter
+// (i, c2, tag): tag 2 the start vector, tag 3 the replacement after a
+// breakdown), stored in TV when `store`; partials of Omega of the stored value.
 template <typename TV, int KIND>
 __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
-                                              uint32_t s0, uint32_t s1, double* __restrict__ spart, SketchP sp,
-                                              int store) {
+                                              uint32_t s0, uint32_t s1, uint32_t c2, uint32_t tag,
+                                              double* __restrict__ spart, SketchP sp, int store) {
   extern __shared__ double bins[];  // 8 waves x d (none for KIND 3)
   if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
@@ -970,7 +985,7 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
       v = u0[i];
     } else {
       double g1;
-      gauss_pair((uint64_t)i, 0u, 2u, s0, s1, v, g1);
+      gauss_pair((uint64_t)i, c2, tag, s0, s1, v, g1);
     }
     const TV st = Conv<TV>::st(v);
     if (store) u[i] = st;
@@ -1374,22 +1389,22 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
 }
 
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
-                int prec_override) {
+                int prec_override, uint32_t c2, uint32_t tag) {
   const int prec = prec_override >= 0 ? prec_override : e.prec;
   const int G = grid_for(e.n, 512, kMaxG);
   dim3 grid(G), block(512);
   const size_t lds = bins_lds(e, 8, e.sp_kind != 0);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<double, KIND>, lds);
-                      k_init<double, KIND><<<grid, block, lds, e.stream>>>(e.n, (double*)u, u0, s0, s1, spart, e.sp,
+                      k_init<double, KIND><<<grid, block, lds, e.stream>>>(e.n, (double*)u, u0, s0, s1, c2, tag, spart, e.sp,
                                                                         store));
   } else if (prec == 1) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<float, KIND>, lds);
-                      k_init<float, KIND><<<grid, block, lds, e.stream>>>(e.n, (float*)u, u0, s0, s1, spart, e.sp,
+                      k_init<float, KIND><<<grid, block, lds, e.stream>>>(e.n, (float*)u, u0, s0, s1, c2, tag, spart, e.sp,
                                                                         store));
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<bf16_t, KIND>, lds);
-                      k_init<bf16_t, KIND><<<grid, block, lds, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1, spart, e.sp,
+                      k_init<bf16_t, KIND><<<grid, block, lds, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1, c2, tag, spart, e.sp,
                                                                         store));
   }
   if (e.sp_kind == 0) {

@@ -52,8 +52,11 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
 int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw, const double* sraw, double* S,
                      double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
                      double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart);
+// u = u0, or the seeded N(0,1) vector of Philox counter (i, c2, tag) (tag 2:
+// start vector, tag 3: breakdown replacement), stored in the basis type (or
+// prec_override's); partials of Omega of the stored value.
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
-                int prec_override);
+                int prec_override, uint32_t c2 = 0, uint32_t tag = 2);
 void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,
                    int kout, const double* Y, int xsrc, int xdst, double xscale, int out_fp64);
 int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const double* axa, const double* axb,

@@ -93,6 +93,8 @@ struct rks_ctx {
   int j = 0, q = 0, keff = 0, pending = 0;
   int keep = 0;  // restart size (kept Schur vectors), k <= keep <= m - 2
   int kr = 0;    // leading pairs tested and returned: k, or k + 1 to keep a conjugate pair
+  int breakdowns = 0;  // replacement vectors drawn since the start (Philox counter of tag 3)
+  int replaced = -1;   // last column replaced after a breakdown
   int64_t step_count = 0;  // Arnoldi steps run by this context (profiling sample clock)
   int G_z = 1, G_s = 1;
   bool have_state = false, solved = false;
@@ -414,6 +416,8 @@ int start(rks_ctx* c, const double* u0, int u0_on_device) {
   c->pending = c->ks ? 0 : 1;
   c->j = 0;
   c->q = 0;
+  c->breakdowns = 0;
+  c->replaced = -1;
   c->keff = 0;
   c->kr = 0;
   c->have_state = true;
@@ -428,6 +432,60 @@ int pull_state(rks_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(st));
   flush_events(c);
   return RKS_OK;
+}
+
+// Continuation past an exact invariant subspace (Section 2.1: the Krylov
+// space has stopped growing, and the pairs it holds are exact).  The
+// extension that found it (flags[0] = t: the remainder of A u_{t-1} vanished
+// against its product) ran on to the end; its columns from t on are
+// discarded.  Column t is replaced by a seeded N(0,1) vector (Philox tag 3,
+// counter = number of replacements so far) sketch-orthogonalised against
+// U_t by one least-squares and update launch; that launch also overwrites
+// B(:, t-1) with the replacement's coefficients, so the pulled column is
+// copied back, and flags[1] = t makes the finalisation of column t store
+// B(t, t-1) = 0.  The extension then continues from column t.  It fails
+// (RKS_EBREAKDOWN) only when the product with A of a replacement vector
+// vanishes as well (flags[2]: the zero operator on that space).
+int recover_breakdown(rks_ctx* c, int t) {
+  const auto& e = c->env;
+  const int ldb = c->m + 1;
+  if (c->ks) return fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(t));
+  if (t < 1 || t > c->m || (c->hflags[2] != 0 && c->replaced == t - 1))
+    return fail(c, RKS_EBREAKDOWN, "the product with A vanished for the replacement vector at column " +
+                                       std::to_string(t - 1));
+  c->breakdowns += 1;
+  if (c->st) c->st->breakdowns += 1;
+  const uint64_t s = c->o.start_seed;
+  const int wprec = c->env.prec == RKS_PREC_FP64 ? 0 : 1;  // w is FP64, or FP32 with a low-precision basis
+  const int G = rks::launch_init(e, c->w, nullptr, (uint32_t)s, (uint32_t)(s >> 32), c->zpart, 1, wprec,
+                                 (uint32_t)c->breakdowns, 3u);
+  rks::launch_reduce(e, c->zpart, G, nullptr, 0, c->z, nullptr);
+  c->G_s = rks::launch_ls_update(e, t - 1, 0, c->z, c->sr, c->S, c->B, ldb, c->E, c->cs, c->coef, c->scal,
+                                 c->flags, kBreakdownRel, c->U, c->ldu, c->w, basis_col(c, t), c->spart);
+  HIPCHK(c, hipMemcpyAsync(c->B + (size_t)(t - 1) * ldb, c->hB + (size_t)(t - 1) * ldb, (size_t)t * 8,
+                           hipMemcpyHostToDevice, e.stream));
+  c->hflags[0] = 0;
+  c->hflags[1] = t;
+  c->hflags[2] = 0;
+  HIPCHK(c, hipMemcpyAsync(c->flags, c->hflags, 3 * sizeof(int), hipMemcpyHostToDevice, e.stream));
+  HIPCHK(c, hipGetLastError());
+  c->replaced = t;
+  c->j = t;
+  c->pending = 1;
+  return RKS_OK;
+}
+
+// Pull the state after an extension; while it reports a breakdown, replace
+// the column and extend again (at most m times in a row).
+int pull_and_recover(rks_ctx* c) {
+  int rc = pull_state(c);
+  for (int tries = 0; rc == RKS_OK && c->hflags[0] != 0; ++tries) {
+    if (tries > c->m) return fail(c, RKS_EBREAKDOWN, "breakdown recovery did not end");
+    rc = recover_breakdown(c, c->hflags[0]);
+    if (rc == RKS_OK) rc = extend(c);
+    if (rc == RKS_OK) rc = pull_state(c);
+  }
+  return rc;
 }
 
 // Ritz values/vectors of the truncated factor and the estimates.
@@ -811,6 +869,20 @@ int device_residuals(rks_ctx* c, const Packed& P, double* Xd, double* resid, boo
   return RKS_OK;
 }
 
+// Largest FP64 residual of the current wanted pairs, verified on the device.
+int verified_max_resid(rks_ctx* c, double* out) {
+  int rc = ensure_resid_scratch(c);
+  if (rc) return rc;
+  Packed P = pack_ritz(c);
+  std::vector<double> res(c->kr, 0.0);
+  rc = device_residuals(c, P, c->Xr, res.data(), false);
+  if (rc) return rc;
+  double mr = 0.0;
+  for (double v : res) mr = std::max(mr, v);
+  *out = mr;
+  return RKS_OK;
+}
+
 // Switch the basis in use between the requested precision and FP64.
 int set_basis(rks_ctx* c, int prec) {
   c->env.prec = prec;
@@ -857,12 +929,8 @@ int run_phase(rks_ctx* c, const double* u0, int u0_on_device, double tol, double
   // of ||u_{k+1}|| / ||x||, so the two differ by a slowly varying factor)
   double ratio = 1.0;
   while (true) {
-    rc = pull_state(c);
+    rc = pull_and_recover(c);
     if (rc) break;
-    if (c->hflags[0] != 0) {
-      rc = fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(c->hflags[0]));
-      break;
-    }
     const auto h0 = std::chrono::steady_clock::now();
     int in0, min, out0, kout, wh;
     double xscale;
@@ -1317,6 +1385,13 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
     st->restarts_lo = p1.restarts;
     st->t_lo = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc == RKS_OK) {
+      // the low-precision phase's FP64 residual, verified on the device when
+      // its estimates stopped it (a verified stop already has it)
+      double mr = p1.maxres;
+      if (!(mr > 0.0)) rc = verified_max_resid(c, &mr);
+      st->max_resid_lo = mr;
+    }
+    if (rc == RKS_OK) {
       // FP64 refinement from a fixed combination of the low-precision Schur vectors
       rc = refine_start(c);
       if (rc == RKS_OK) {
@@ -1409,10 +1484,9 @@ int rks_arnoldi(rks_ctx* c, const double* u0, int32_t u0_on_device) {
   if (rc) return rc;
   rc = extend(c);
   if (rc) return rc;
+  rc = pull_and_recover(c);
+  if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->env.stream));
-  HIPCHK(c, hipMemcpy(c->hflags, c->flags, sizeof(int) * 4, hipMemcpyDeviceToHost));
-  if (c->hflags[0] != 0)
-    return fail(c, RKS_EBREAKDOWN, "invariant subspace at column " + std::to_string(c->hflags[0]));
   return RKS_OK;
 }
 

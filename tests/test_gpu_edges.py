@@ -87,24 +87,74 @@ def _diag_csr(d):
                {"kind": "diag"})
 
 
-def test_exact_invariant_subspace_reports_breakdown(lib, cuda):
-    """A start inside a 3-dimensional invariant subspace: the extension finds
-    beta = 0 at column 3 and the solver reports RKS_EBREAKDOWN (-6)."""
+def _invariant_case():
+    """A diagonal operator whose three largest eigenvalues (10, 9, 8) are
+    isolated, and a start supported on their three coordinates: the Krylov
+    space is that exact invariant subspace, so the remainder vanishes at
+    column 3 (Section 2.1)."""
     n = 2000
-    A = _diag_csr(np.linspace(1.0, 2.0, n))
+    diag = np.concatenate([np.linspace(1.0, 2.0, n - 5), [10.0, 9.0, 8.0, 5.0, 4.0]])
     u0 = np.zeros(n)
-    u0[[5, 700, 1500]] = [1.0, 2.0, -1.0]
-    with P.Solver.from_csr(A, k=2, m=10, d=40, which="LM", tol=1e-10) as s:
-        with pytest.raises(P.RksError) as ei:
-            s.solve(u0)
-        assert ei.value.code == -6
-        assert "column 3" in P.rks_last_error(s.ctx)
+    u0[[n - 5, n - 4, n - 3]] = [1.0, 2.0, -1.0]
+    return _diag_csr(diag), diag, u0
+
+
+def test_exact_invariant_subspace_is_continued_past(lib, cuda):
+    """The extension meets the vanishing remainder at column 3, replaces it
+    with the seeded tag-3 vector sketch-orthogonalised against U_3 and sets
+    B(3, 2) = 0, as the oracle does: the whole decomposition equals the
+    oracle's (entrywise 1e-9 ||A||_1) and satisfies the exact identities, and
+    its Rayleigh quotient holds the three exact eigenvalues to 1e-12."""
+    A, diag, u0 = _invariant_case()
+    k, m, d = 5, 12, 40
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
+                       P.rks_opts_default(sketch_kind="sparse", sketch_seed=3, start_seed=1))
+    try:
+        P.rks_arnoldi(ctx, u0)
+        B = np.zeros((m + 1, m), order="F")
+        S = np.zeros((d, m + 1), order="F")
+        U = np.zeros((A.n, m + 1), order="F")
+        assert P.rks_get_state(ctx, B, S, U) == m + 1
+    finally:
+        P.rks_destroy(ctx)
+    o = RKSOracle(A, k, m, d, "LM", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1)
+    o.start(u0)
+    o.extend()
+    assert o.breakdowns == 1 and o.B[3, 2] == 0.0
+    assert B[3, 2] == 0.0
+    nA = _identities(A, B, S, U, m, d, "sparse", 3)
+    assert np.abs(B - o.B).max() <= 1e-9 * nA, np.abs(B - o.B).max() / nA
+    assert np.abs(U - o.U).max() <= 1e-9 * np.abs(o.U).max()
+    ev = np.linalg.eigvals(B[:m, :m])
+    for lam in (10.0, 9.0, 8.0):
+        assert np.min(np.abs(ev - lam)) <= 1e-12 * lam
+
+
+def test_breakdown_solve_matches_oracle(lib, cuda):
+    """A whole solve through the breakdown: the exact pairs stay in the
+    decomposition, the two further wanted pairs are found after it, and the
+    five eigenvalues equal the oracle's (1e-10) and the exact ones."""
+    A, diag, u0 = _invariant_case()
+    k, m, d = 5, 12, 40
+    ref = RKSOracle(A, k, m, d, "LM", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1).run(u0)
+    assert ref.converged
+    with P.Solver.from_csr(A, k=k, m=m, d=d, which="LM", tol=1e-10, sketch_kind="sparse", sketch_seed=3,
+                           start_seed=1) as s:
+        assert s.solve(u0) == 0, P.rks_last_error(s.ctx)
+        assert s.stats.breakdowns >= 1
+        lam, X, res = s.eigpairs()
+    assert np.max(np.abs(lam - ref.lam) / np.abs(ref.lam)) <= 1e-10
+    assert np.max(np.abs(lam.real - np.array([10.0, 9.0, 8.0, 5.0, 4.0])) / 10.0) <= 1e-10
+    assert res.max() <= 1e-8
 
 
 def test_zero_matrix_reports_breakdown(lib, cuda):
+    """The zero operator: the replacement vector's product with A vanishes
+    too, so the continuation fails and the solver reports RKS_EBREAKDOWN."""
     n = 500
     A = _diag_csr(np.zeros(n))
     with P.Solver.from_csr(A, k=2, m=8, d=20, which="LM", tol=1e-10) as s:
         with pytest.raises(P.RksError) as ei:
             s.solve()
         assert ei.value.code == -6
+        assert "replacement" in P.rks_last_error(s.ctx)
