@@ -236,6 +236,23 @@ const char* rks_last_error(const struct rks_ctx* ctx);
 /* z = Omega x for a device FP64 vector x (n) -> device z (d). */
 int rks_sketch(struct rks_ctx* ctx, const double* x_dev, double* z_dev);
 
+/* z = Omega x as rks_sketch, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context; the embedding is given by d, sketch_kind, zeta and
+ * sketch_seed as in rks_opts, x (n FP64) and z (d FP64) are device buffers
+ * of the caller, and the work is enqueued on `stream` (hipStream_t, NULL =
+ * default) without synchronising it.  The call allocates nothing: its
+ * partial sums go to a fixed device array of the library (512 x 1024 FP64,
+ * 4 MiB per GPU, held until the process ends), so d <= 1024.  Every call on
+ * one GPU uses that one array: calls in stream order are fine, calls that
+ * overlap on one GPU (other streams, other host threads) race.  Results are
+ * those of rks_sketch on a context with the same embedding, to the bit.
+ * Errors (rks_last_error(NULL) describes them): RKS_EINVAL (NULL pointer,
+ * n < 1, d outside 1..1024, sketch_kind, zeta outside 1..min(8, d)),
+ * RKS_EHIP. */
+int rks_sketch_noalloc(int64_t n, int32_t d, int32_t sketch_kind, int32_t zeta, uint64_t sketch_seed,
+                       const double* x_dev, double* z_dev, void* stream);
+
 /* w = A x and z = Omega w (Algorithm 2, apply A and sketch) for device FP64
  * x (n) -> device w (n), device z (d); the fused SpMV + sketch kernel. */
 int rks_spmv_sketch(struct rks_ctx* ctx, const double* x_dev, double* w_dev, double* z_dev);

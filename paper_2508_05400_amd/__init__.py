@@ -10,13 +10,13 @@ import numpy as np
 from . import _binding as rks
 from ._binding import (RksError, RksOpts, RksStats, load, rks_opts_default, rks_create, rks_solve,
                        rks_num_pairs, rks_eigpairs, rks_destroy, rks_strerror, rks_last_error,
-                       rks_sketch, rks_spmv_sketch, rks_arnoldi, rks_get_state, rks_rotate,
+                       rks_sketch, rks_sketch_noalloc, rks_spmv_sketch, rks_arnoldi, rks_get_state, rks_rotate,
                        rks_host_schur, rks_host_order, rks_net_conv3x3_forward, rks_net_conv3x3_backward,
                        rks_net_subspace_loss, rks_net_adam, rks_net_upsample, rks_copy_probe, rks_read_probe)
 
 __all__ = ["Solver", "RksError", "RksOpts", "RksStats", "load", "rks_opts_default", "rks_create",
            "rks_solve", "rks_num_pairs", "rks_eigpairs", "rks_destroy", "rks_strerror",
-           "rks_last_error", "rks_sketch", "rks_spmv_sketch", "rks_arnoldi", "rks_get_state",
+           "rks_last_error", "rks_sketch", "rks_sketch_noalloc", "rks_spmv_sketch", "rks_arnoldi", "rks_get_state",
            "rks_rotate", "rks_host_schur", "rks_host_order", "rks_net_conv3x3_forward",
            "rks_net_conv3x3_backward", "rks_net_subspace_loss", "rks_net_adam", "rks_net_upsample",
            "rks_copy_probe", "rks_read_probe"]

@@ -79,6 +79,7 @@ SIGNATURES = {
     "rks_last_error": (ctypes.c_char_p, [_P]),
     "rks_sketch": (ctypes.c_int, [_P, _P, _P]),
     "rks_spmv_sketch": (ctypes.c_int, [_P, _P, _P, _P]),
+    "rks_sketch_noalloc": (ctypes.c_int, [_I64, _I32, _I32, _I32, ctypes.c_uint64, _P, _P, _P]),
     "rks_arnoldi": (ctypes.c_int, [_P, _P, _I32]),
     "rks_get_state": (ctypes.c_int, [_P, ctypes.POINTER(_I32), _P, _P, _P]),
     "rks_rotate": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
@@ -232,6 +233,13 @@ def rks_last_error(ctx) -> str:
 
 def rks_sketch(ctx, x_dev, z_dev) -> int:
     return _check(ctx, load().rks_sketch(ctx, _ptr(x_dev), _ptr(z_dev)))
+
+
+def rks_sketch_noalloc(n, d, sketch_kind, zeta, sketch_seed, x_dev, z_dev, stream=None) -> int:
+    if isinstance(sketch_kind, str):
+        sketch_kind = SKETCH[sketch_kind]
+    return _check(None, load().rks_sketch_noalloc(int(n), int(d), int(sketch_kind), int(zeta), int(sketch_seed),
+                                                  _ptr(x_dev), _ptr(z_dev), _stream(stream)))
 
 
 def rks_spmv_sketch(ctx, x_dev, w_dev, z_dev) -> int:

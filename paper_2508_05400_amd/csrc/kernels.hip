@@ -1510,6 +1510,46 @@ void launch_ks_finalize(const LaunchEnv& e, int t, const double* h, const double
   k_ks_finalize<<<1, 256, 0, e.stream>>>(t, h, nrm2, B, ldb, cs, flags, bd_rel);
 }
 
+// ---------------------------------------------------------------------------
+// No-allocation sketch: the partial rows live in a fixed device array of the
+// library instead of a context's buffer.  In host code `scratch` names a
+// host-side stand-in, not a device address: its address on the current
+// device is obtained once per device with hipGetSymbolAddress and only that
+// address is passed to kernels.
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[(size_t)kMaxG * kMaxD];
+
+int scratch_address(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return -1;
+  static std::mutex mu;
+  static double* addr[kScratchDevices] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return -2;
+    addr[dev] = (double*)p;
+  }
+  *out = addr[dev];
+  return 0;
+}
+
+int launch_sketch_scratch(const LaunchEnv& e, const double* x, double* part, double* z) {
+  // the kernels and grid of launch_init (store = 0) and launch_reduce, with
+  // no host-side bookkeeping: the bins of 8 waves x d <= 1024 FP64 fit the
+  // default 64 KB of dynamic LDS
+  int G;
+  if (e.sp_kind == 0) {
+    G = gauss_t<double>(e, x, part);
+  } else {
+    G = grid_for(e.n, 512, kMaxG);
+    const size_t lds = bins_lds(e, 8, true);
+    k_init<double, 1><<<G, 512, lds, e.stream>>>(e.n, nullptr, x, 0u, 0u, 0u, 2u, part, e.sp, 0);
+  }
+  launch_reduce(e, part, G, nullptr, 0, z, nullptr);
+  return G;
+}
+
 void launch_read16(hipStream_t stream, const void* src, int64_t packets) {
   k_read16<<<grid_for(packets, 256, 8192), 256, 0, stream>>>((const u32x4*)src, packets);
 }

@@ -75,5 +75,11 @@ void launch_ks_coef(const LaunchEnv& e, int ncol, const double* cs, const double
 void launch_ks_finalize(const LaunchEnv& e, int t, const double* h, const double* nrm2, double* B, int ldb, double* cs,
                         int* flags, double bd_rel);
 void launch_ks_start(const LaunchEnv& e, const double* nrm2, double* cs);
+// Device address of the library's fixed sketch scratch (kMaxG x kMaxD FP64)
+// on the current device, resolved once per device; 0 on success.
+int scratch_address(double** out);
+// z = Omega x with partial rows in `part` (at least kMaxG x d FP64): the
+// kernels of launch_init (store = 0) and launch_reduce, no host allocation.
+int launch_sketch_scratch(const LaunchEnv& e, const double* x, double* part, double* z);
 
 }  // namespace rks

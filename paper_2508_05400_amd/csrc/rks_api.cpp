@@ -1464,6 +1464,36 @@ int rks_sketch(rks_ctx* c, const double* x_dev, double* z_dev) {
   return RKS_OK;
 }
 
+int rks_sketch_noalloc(int64_t n, int32_t d, int32_t sketch_kind, int32_t zeta, uint64_t sketch_seed,
+                       const double* x_dev, double* z_dev, void* stream) {
+  g_create_err.clear();
+  if (!x_dev || !z_dev) return fail(nullptr, RKS_EINVAL, "x or z is NULL");
+  if (n < 1 || n >= ((int64_t)1 << 40)) return fail(nullptr, RKS_EINVAL, "need 1 <= n < 2^40");
+  if (d < 1 || d > rks::kMaxD)
+    return fail(nullptr, RKS_EINVAL, "need 1 <= d <= 1024 (the fixed scratch holds 512 x 1024 partial sums)");
+  if (sketch_kind != RKS_SKETCH_GAUSS && sketch_kind != RKS_SKETCH_SPARSE)
+    return fail(nullptr, RKS_EINVAL, "sketch_kind");
+  if (sketch_kind == RKS_SKETCH_SPARSE && (zeta < 1 || zeta > 8 || zeta > d))
+    return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
+  double* part = nullptr;
+  const int sr = rks::scratch_address(&part);
+  if (sr != 0) return fail(nullptr, RKS_EHIP, "resolving the device scratch array");
+  rks::LaunchEnv e{};
+  e.stream = (hipStream_t)stream;
+  e.n = n;
+  e.prec = 0;
+  e.sp_kind = sketch_kind;
+  e.sp.d = d;
+  e.sp.zeta = zeta;
+  e.sp.k0 = (uint32_t)sketch_seed;
+  e.sp.k1 = (uint32_t)(sketch_seed >> 32);
+  e.sp.scale = (sketch_kind == RKS_SKETCH_SPARSE) ? 1.0 / std::sqrt((double)zeta) : 1.0 / std::sqrt((double)d);
+  rks::launch_sketch_scratch(e, x_dev, part, z_dev);
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return fail(nullptr, RKS_EHIP, std::string("sketch launch -> ") + hipGetErrorString(he));
+  return RKS_OK;
+}
+
 int rks_spmv_sketch(rks_ctx* c, const double* x_dev, double* w_dev, double* z_dev) {
   if (!c || !x_dev || !w_dev || !z_dev) return RKS_EINVAL;
   if (c->ks) return fail(c, RKS_EINVAL, "deterministic Krylov-Schur has no sketch");
