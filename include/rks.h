@@ -121,7 +121,7 @@ typedef struct {
   int32_t spmv_layout;   /* rks_spmv_layout, default AUTO */
   int32_t method;        /* rks_method, default RKS */
   int32_t keep;          /* restart size: Schur vectors kept at each contraction,
-                            k <= keep <= min(m - 2, 63) (keep + 1 when a conjugate
+                            k <= keep <= min(m - 2, 127) (keep + 1 when a conjugate
                             pair would be split); 0 = k, the truncation of
                             Algorithm 1; RKS_KEEP_AUTO (-1) = k + (m - k) / 4,
                             clamped to that range.  Any leading truncation of an
@@ -183,9 +183,11 @@ typedef struct {
 
 /* Create a solver for k eigenpairs of A with Krylov dimension m and sketch
  * size d, targeting `which`, with tolerance tol on the estimates
- * |b^T y| / |lambda| (Section 4.1).  Requires 1 <= k, k + 2 <= m,
- * m + 1 <= d <= n (Omega must embed the (m+1)-dimensional Krylov space,
- * Algorithm 1 input), tol > 0, a valid CSR.  opts may be NULL (defaults).
+ * |b^T y| / |lambda| (Section 4.1).  Requires 1 <= k, k + 2 <= m <= 255,
+ * m + 1 <= d <= min(n, 1024) (Omega must embed the (m+1)-dimensional Krylov
+ * space, Algorithm 1 input), k + 1 <= 128 and keep + 1 <= 128 (the
+ * rotation writes at most 128 columns), tol > 0, a valid CSR.  opts may be
+ * NULL (defaults).
  * Allocates the basis U (n x (m+1)), the sketch S (d x (m+1)), the Rayleigh
  * quotient B ((m+1) x m) and scratch on the device.
  * Errors: RKS_EINVAL, RKS_ENAN (non-finite value in A), RKS_ENOMEM, RKS_EHIP. */
@@ -271,7 +273,7 @@ int rks_get_state(struct rks_ctx* ctx, int32_t* ncols, double* B, double* S, dou
 
 /* Restart rotation U[:, out0:out0+kout] <- U[:, in0:in0+min] * Y on the
  * device basis (Algorithm 1, truncation line), with Y (min x kout, host,
- * column-major).  Output columns may overlap input columns. */
+ * column-major), kout <= 128.  Output columns may overlap input columns. */
 int rks_rotate(struct rks_ctx* ctx, int32_t in0, int32_t min, int32_t out0, int32_t kout,
                const double* Y);
 

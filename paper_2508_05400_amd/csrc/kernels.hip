@@ -712,12 +712,24 @@ __device__ __forceinline__ void ls_solve(int t, int d, int pending, const double
   }
 }
 
-// 16-byte packets of the basis: V = 16 / sizeof(TV) consecutive rows.
+// Packets of the basis: PB bytes (16, or 8 for columns too short to give
+// every CU a workgroup of 16-byte packets), V = PB / sizeof(TV) consecutive rows.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-template <typename T>
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <int PB>
+struct RawOf;
+template <>
+struct RawOf<16> {
+  typedef u32x4 type;
+};
+template <>
+struct RawOf<8> {
+  typedef u32x2 type;
+};
+template <typename T, int PB = 16>
 union Pack16 {
-  u32x4 raw;
-  T v[16 / sizeof(T)];
+  typename RawOf<PB>::type raw;
+  T v[PB / sizeof(T)];
 };
 
 // u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
@@ -727,14 +739,17 @@ union Pack16 {
 // wave-uniform and come through the scalar path.  Padding rows (>= n, < ldu)
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
-template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false>
+template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false, int PB = 16>
 __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U, int64_t ldu,
                                             const TW* __restrict__ w, const double* __restrict__ coef,
                                             TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
-                                            double* bins, const u32x4* pre = nullptr, bool use_pre = false) {
+                                            double* bins, const typename RawOf<PB>::type* pre = nullptr,
+                                            bool use_pre = false) {
   // pre: NPRE leading basis columns, then (PREW) the w chunks, of the first packet
-  constexpr int V = 16 / sizeof(TV);
-  constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
+  typedef typename RawOf<PB>::type Raw;
+  constexpr int V = PB / sizeof(TV);
+  constexpr int WCH = (V * (int)sizeof(TW)) / PB;  // PB-byte chunks of w per packet
+  constexpr int WV = PB / (int)sizeof(TW);          // w values per chunk
   if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
   double* wb = wave_bins(bins, sp.d);
@@ -745,21 +760,21 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
     const int64_t i0 = g * V;
     double a[V];
     {
-      Pack16<TW> wp[WCH];
+      Pack16<TW, PB> wp[WCH];
 #pragma unroll
       for (int c = 0; c < WCH; ++c)
-        wp[c].raw = (PREW && use_pre) ? pre[NPRE + c] : *(const u32x4*)(w + i0 + c * (16 / sizeof(TW)));
+        wp[c].raw = (PREW && use_pre) ? pre[NPRE + c] : *(const Raw*)(w + i0 + c * WV);
 #pragma unroll
       for (int c = 0; c < WCH; ++c)
 #pragma unroll
-        for (int r = 0; r < 16 / (int)sizeof(TW); ++r) a[c * (16 / sizeof(TW)) + r] = ws * (double)wp[c].v[r];
+        for (int r = 0; r < WV; ++r) a[c * WV + r] = ws * (double)wp[c].v[r];
     }
     const TV* col0 = U + i0;
     int l = 0;
     if (NPRE > 0 && use_pre) {  // the first packet's leading columns, loaded before the least squares
 #pragma unroll
       for (int q = 0; q < NPRE; ++q) {
-        Pack16<TV> pq;
+        Pack16<TV, PB> pq;
         pq.raw = pre[q];
         const double cq = coef[q];
 #pragma unroll
@@ -769,9 +784,9 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
       use_pre = false;
     }
     for (; l + 8 <= ncol; l += 8) {
-      Pack16<TV> p[8];
+      Pack16<TV, PB> p[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) p[q].raw = __builtin_nontemporal_load((const u32x4*)(col0 + (int64_t)(l + q) * ldu));
+      for (int q = 0; q < 8; ++q) p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q) * ldu));
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const double cq = coef[l + q];
@@ -780,16 +795,16 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
       }
     }
     for (; l < ncol; ++l) {
-      Pack16<TV> p;
-      p.raw = __builtin_nontemporal_load((const u32x4*)(col0 + (int64_t)l * ldu));
+      Pack16<TV, PB> p;
+      p.raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)l * ldu));
       const double cq = coef[l];
 #pragma unroll
       for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p.v[r]);
     }
-    Pack16<TV> o;
+    Pack16<TV, PB> o;
 #pragma unroll
     for (int r = 0; r < V; ++r) o.v[r] = Conv<TV>::st(a[r]);
-    __builtin_nontemporal_store(o.raw, (u32x4*)(unew + i0));
+    __builtin_nontemporal_store(o.raw, (Raw*)(unew + i0));
 #pragma unroll
     for (int r = 0; r < V; ++r) {
       if (i0 + r >= n) continue;
@@ -823,7 +838,7 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
 // latency-bound single workgroup, off the step's critical path.  LDS: the
 // coefficients (kMaxM + 2), then the least-squares scratch, reused afterwards
 // for the per-wave sketch bins.
-template <typename TV, typename TW, int KIND, bool PRE>
+template <typename TV, typename TW, int KIND, bool PRE, int PB>
 __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, const double* __restrict__ zraw,
                                                    const double* __restrict__ sraw, double* __restrict__ S,
                                                    double* __restrict__ B, int ldb, double* __restrict__ E,
@@ -841,13 +856,14 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
   // (PRE: only where the least squares has no global loads of its own after
   // its first round, d <= 256 and t < 64, which would wait for these; and not
   // for BF16, whose eight rows per packet leave no registers for it)
-  constexpr int V = 16 / sizeof(TV);
+  typedef typename RawOf<PB>::type Raw;
+  constexpr int V = PB / sizeof(TV);
   constexpr int NP = PRE && sizeof(TV) >= 4 ? kLsPreU : 0;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool use_pre = NP > 0 && g0 < npk && t + 1 >= NP;
-  constexpr int WCH = (V * (int)sizeof(TW)) / 16;  // 16-byte chunks of w per packet
+  constexpr int WCH = (V * (int)sizeof(TW)) / PB;  // PB-byte chunks of w per packet
   constexpr bool PREW = NP > 0 && sizeof(TV) == 8;  // w too (FP64: registers allow it)
-  u32x4 pre[NP > 0 ? NP + WCH : 1];
+  Raw pre[NP > 0 ? NP + WCH : 1];
   // The loads are issued by every thread, from clamped (in-bounds) addresses
   // when unused: a load under a branch would make the least squares wait for
   // all of them (wait counts are merged over both paths).
@@ -856,12 +872,12 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const int qc = q <= t ? q : t;
-      pre[q] = __builtin_nontemporal_load((const u32x4*)(U + gl * V + (int64_t)qc * ldu));
+      pre[q] = __builtin_nontemporal_load((const Raw*)(U + gl * V + (int64_t)qc * ldu));
     }
 #pragma unroll
-    for (int c = 0; c < (PREW ? WCH : 0); ++c) pre[NP + c] = *(const u32x4*)(w + gl * V + c * (16 / sizeof(TW)));
+    for (int c = 0; c < (PREW ? WCH : 0); ++c) pre[NP + c] = *(const Raw*)(w + gl * V + c * (PB / sizeof(TW)));
   });
-  update_body<TV, TW, KIND, NP, PREW>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
+  update_body<TV, TW, KIND, NP, PREW, PB>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
@@ -1013,18 +1029,23 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
 // (in-place restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename TI, typename TO, int NT>
+// YG: Y (minp x 16 NT FP64) does not fit in LDS (more than 160 KB: min and
+// kout both large); each lane then reads its Y entries from global memory
+// (Y is small and stays in L2).
+template <typename TI, typename TO, int NT, bool YG>
 __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
                                                 int64_t ldo, int out0, int kout, const double* __restrict__ Y,
                                                 int xsrc, int xdst, double xscale) {
-  extern __shared__ double Ys[];  // minp x (16 NT), zero padded
+  extern __shared__ double Ys[];  // minp x (16 NT), zero padded (unused when YG)
   constexpr int KC = 16 * NT;
   const int minp = (min + 15) & ~15;
-  for (int idx = threadIdx.x; idx < minp * KC; idx += blockDim.x) {
-    const int l = idx / KC, o = idx - l * KC;
-    Ys[idx] = (l < min && o < kout) ? Y[l + (size_t)o * min] : 0.0;
+  if (!YG) {
+    for (int idx = threadIdx.x; idx < minp * KC; idx += blockDim.x) {
+      const int l = idx / KC, o = idx - l * KC;
+      Ys[idx] = (l < min && o < kout) ? Y[l + (size_t)o * min] : 0.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -1047,9 +1068,19 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const double* yk = Ys + (size_t)(k0 + 4 * s + lk) * KC + lr;
+        if (YG) {
+          const int kk = k0 + 4 * s + lk;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yk[16 * t], a[s], acc[t], 0, 0, 0);
+          for (int t = 0; t < NT; ++t) {
+            const int oc = 16 * t + lr;
+            const double yv = (kk < min && oc < kout) ? Y[kk + (size_t)oc * min] : 0.0;
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, a[s], acc[t], 0, 0, 0);
+          }
+        } else {
+          const double* yk = Ys + (size_t)(k0 + 4 * s + lk) * KC + lr;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yk[16 * t], a[s], acc[t], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
@@ -1344,21 +1375,25 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
   return G;
 }
 
-template <typename TV, typename TW, bool PRE>
+template <typename TV, typename TW, bool PRE, int PB>
 static void ls_update_t(const LaunchEnv& e, dim3 grid, size_t lds, int t, int pending, const double* zraw,
                         const double* sraw, double* S, double* B, int ldb, double* E, double* cs, double* coef,
                         double* scal, int* flags, double bd_rel, int64_t npk, const void* U, int64_t ldu,
                         const void* w, void* unew, double* spart) {
-  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE>, lds);
-                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE>, grid, dim3(1024), lds, t, e.sp.d,
-                             pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE, PB>, lds);
+                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE, PB>, grid, dim3(1024), lds, t,
+                             e.sp.d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
                              (const TV*)U, ldu, (const TW*)w, (TV*)unew, spart, e.sp));
 }
 
 int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw, const double* sraw, double* S,
                      double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
                      double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart) {
-  const int V = 16 / e.vbytes();
+  // 16-byte packets, or 8-byte packets when a column is too short to give
+  // 200 CUs a workgroup of 16-byte packets (then twice as many workgroups)
+  const int64_t npk16 = (e.n + 16 / e.vbytes() - 1) / (16 / e.vbytes());
+  const int PBy = npk16 < 200 * 1024 ? 8 : 16;
+  const int V = PBy / e.vbytes();
   const int64_t npk = (e.n + V - 1) / V;
   // at most one workgroup per CU (256): the kernel's registers allow one
   // 1024-thread workgroup per CU anyway, and fewer workgroups repeat the least
@@ -1371,15 +1406,17 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
   const size_t lds = ((size_t)kMaxM + 2 + (ls_work > bins ? ls_work : bins)) * 8;
   // basis loads during the least squares where its own loads all come first
   const bool pre = e.sp.d <= kRC * kLsPreS && t + 1 <= 64 && t + 1 >= kLsPreU;
-#define RKS_LSU(TV, TW)                                                                                          \
-  (pre ? ls_update_t<TV, TW, true>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, \
-                                   bd_rel, npk, U, ldu, w, unew, spart)                                         \
-       : ls_update_t<TV, TW, false>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, \
-                                    bd_rel, npk, U, ldu, w, unew, spart))
+#define RKS_LSU_PB(TV, TW, PB)                                                                                       \
+  (pre ? ls_update_t<TV, TW, true, PB>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, \
+                                       bd_rel, npk, U, ldu, w, unew, spart)                                         \
+       : ls_update_t<TV, TW, false, PB>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal,     \
+                                        flags, bd_rel, npk, U, ldu, w, unew, spart))
+#define RKS_LSU(TV, TW) (PBy == 8 ? RKS_LSU_PB(TV, TW, 8) : RKS_LSU_PB(TV, TW, 16))
   if (e.prec == 0) RKS_LSU(double, double);
   else if (e.prec == 1) RKS_LSU(float, float);
   else RKS_LSU(bf16_t, float);
 #undef RKS_LSU
+#undef RKS_LSU_PB
   if (e.sp_kind == 0) {  // sketch of the stored value
     if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
     if (e.prec == 1) return gauss_t<float>(e, (const float*)unew, spart);
@@ -1423,24 +1460,30 @@ static void rotate_nt(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int
   const int64_t ntile = (e.n + 15) / 16;
   const int G = grid_for(ntile, 4, 2048);
   const size_t lds = (size_t)((min + 15) & ~15) * 16 * NT * 8;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)k_rotate<TI, TO, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  launch_k(e, true, true, k_rotate<TI, TO, NT>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O, ldo, out0, kout,
-           Y, xsrc, xdst, xscale);
+  if (lds > kRotLdsMax) {
+    launch_k(e, true, true, k_rotate<TI, TO, NT, true>, dim3(G), dim3(256), 0, e.n, U, ldu, in0, min, O, ldo, out0,
+             kout, Y, xsrc, xdst, xscale);
+    return;
+  }
+  lds_allow((const void*)k_rotate<TI, TO, NT, false>, lds);
+  launch_k(e, true, true, k_rotate<TI, TO, NT, false>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O, ldo, out0,
+           kout, Y, xsrc, xdst, xscale);
 }
 
 template <typename TI, typename TO>
 static void rotate_t(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
                      int kout, const double* Y, int xsrc, int xdst, double xscale) {
-  if (kout <= 16)
-    rotate_nt<TI, TO, 1>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
-  else if (kout <= 32)
-    rotate_nt<TI, TO, 2>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
-  else if (kout <= 48)
-    rotate_nt<TI, TO, 3>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
-  else
-    rotate_nt<TI, TO, 4>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale);
+  switch ((kout + 15) / 16) {
+    case 0:
+    case 1: rotate_nt<TI, TO, 1>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 2: rotate_nt<TI, TO, 2>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 3: rotate_nt<TI, TO, 3>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 4: rotate_nt<TI, TO, 4>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 5: rotate_nt<TI, TO, 5>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 6: rotate_nt<TI, TO, 6>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 7: rotate_nt<TI, TO, 7>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    default: rotate_nt<TI, TO, 8>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+  }
 }
 
 void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,

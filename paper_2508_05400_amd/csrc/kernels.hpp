@@ -27,7 +27,8 @@ constexpr int kTileNnz = 512;    // nonzeros staged per SpMV wave tile (LDS slic
 constexpr int kTileFill = kTileNnz - 2;  // nonzeros a tile may hold: paired loads start at the even
                                          // index at or below its first nonzero
 constexpr int kCsrPad = 2;       // readable padding entries after col[] and val[] (paired loads)
-constexpr int kRotMax = 64;      // output columns per rotation pass
+constexpr int kRotMax = 128;     // output columns per rotation pass (8 MFMA column tiles)
+constexpr size_t kRotLdsMax = 160 * 1024;  // Y in LDS up to this size, else read from global memory
 constexpr size_t kLsLdsMax = 150 * 1024;  // LDS budget of the least-squares kernel
 
 struct bf16_t {

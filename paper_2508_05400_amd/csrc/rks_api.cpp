@@ -1076,7 +1076,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "need 4 <= n < 2^31 and nnz < 2^31");
   if (k < 1 || k + 2 > m || m > rks::kMaxM || m + 1 > d || d > n || d > rks::kMaxD)
     return fail(nullptr, RKS_EINVAL, "need 1 <= k, k+2 <= m <= 255, m+1 <= d <= min(n, 1024)");
-  if (k + 1 > rks::kRotMax) return fail(nullptr, RKS_EINVAL, "need k + 1 <= 64");
+  if (k + 1 > rks::kRotMax) return fail(nullptr, RKS_EINVAL, "need k + 1 <= 128");
   if (!(tol > 0.0) || which < 0 || which > 3) return fail(nullptr, RKS_EINVAL, "tol or which");
   if (o.sketch_kind != RKS_SKETCH_GAUSS && o.sketch_kind != RKS_SKETCH_SPARSE)
     return fail(nullptr, RKS_EINVAL, "sketch_kind");
@@ -1091,7 +1091,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (o.keep == RKS_KEEP_AUTO)
     keep = std::max(k, std::min({k + (m - k) / 4, m - 2, rks::kRotMax - 1}));
   if (keep < k || keep + 2 > m || keep + 1 > rks::kRotMax)
-    return fail(nullptr, RKS_EINVAL, "need k <= keep <= m - 2 and keep + 1 <= 64");
+    return fail(nullptr, RKS_EINVAL, "need k <= keep <= m - 2 and keep + 1 <= 128");
   if (o.method == RKS_METHOD_KS_CGS2 && o.precision != RKS_PREC_FP64)
     return fail(nullptr, RKS_EINVAL, "deterministic Krylov-Schur runs with an FP64 basis only");
   if (o.lock < 0 || o.lock > 2) return fail(nullptr, RKS_EINVAL, "lock must be 0, 1 or 2");

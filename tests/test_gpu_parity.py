@@ -139,7 +139,8 @@ def test_rotate_parity(lib, cuda):
         U0 = np.zeros((A.n, m + 1), order="F")
         P.rks_get_state(ctx, None, None, U0)
         rng = np.random.default_rng(4)
-        for (in0, mi, out0, ko) in [(0, 40, 0, 11), (3, 37, 3, 17), (0, 40, 5, 33), (2, 30, 0, 64 - 30)]:
+        for (in0, mi, out0, ko) in [(0, 40, 0, 11), (3, 37, 3, 17), (0, 40, 5, 33), (2, 30, 0, 64 - 30),
+                                    (0, 41, 0, 41), (1, 40, 0, 41)]:
             Y = rng.standard_normal((mi, ko))
             P.rks_get_state(ctx, None, None, U0)
             before = U0.copy()
@@ -152,6 +153,37 @@ def test_rotate_parity(lib, cuda):
             err = np.abs(after[:, out0:out0 + ko] - ref[:, out0:out0 + ko])
             assert np.all(err <= 64 * U64 * bound + 1e-300)
             untouched = [c for c in range(m + 1) if not (out0 <= c < out0 + ko)]
+            assert np.array_equal(after[:, untouched], ref[:, untouched])
+    finally:
+        P.rks_destroy(ctx)
+
+
+@pytest.mark.parametrize("m,kout", [(150, 100), (255, 128)])
+def test_rotate_parity_wide(lib, cuda, m, kout):
+    """Rotations writing more than 64 columns: 7 or 8 MFMA column tiles, with
+    Y in LDS (150 x 112 values) or, when it does not fit (256 x 128 FP64 is
+    256 KB), read from global memory; in place, overlapping columns."""
+    A = powerlaw_random(3001, 4)
+    d = min(m + 40, 1024)
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 10, m, d, "LM", 1e-10, P.rks_opts_default(sketch_kind="sparse"))
+    try:
+        P.rks_arnoldi(ctx, None)
+        U0 = np.zeros((A.n, m + 1), order="F")
+        P.rks_get_state(ctx, None, None, U0)
+        rng = np.random.default_rng(7)
+        for (in0, mi, out0) in [(0, m, 0), (1, m - 1, 1)]:
+            Y = rng.standard_normal((mi, kout))
+            P.rks_get_state(ctx, None, None, U0)
+            before = U0.copy()
+            P.rks_rotate(ctx, in0, mi, out0, kout, Y)
+            after = np.zeros_like(U0)
+            P.rks_get_state(ctx, None, None, after)
+            ref = before.copy()
+            ref[:, out0:out0 + kout] = before[:, in0:in0 + mi] @ Y
+            bound = np.abs(before[:, in0:in0 + mi]) @ np.abs(Y)
+            err = np.abs(after[:, out0:out0 + kout] - ref[:, out0:out0 + kout])
+            assert np.all(err <= 64 * U64 * bound + 1e-300)
+            untouched = [c for c in range(m + 1) if not (out0 <= c < out0 + kout)]
             assert np.array_equal(after[:, untouched], ref[:, untouched])
     finally:
         P.rks_destroy(ctx)
@@ -514,16 +546,17 @@ def test_forced_whitening_matches_oracle(lib, cuda, restarts):
 
 
 def test_restart_size_resolution_and_limits(lib, cuda):
-    """keep = RKS_KEEP_AUTO resolves to k + (m - k)/4 (clamped to m - 2 and 63);
-    sizes outside [k, min(m - 2, 63)] are rejected at create."""
+    """keep = RKS_KEEP_AUTO resolves to k + (m - k)/4 (clamped to m - 2 and
+    127, the oracle's rule below 127); sizes outside [k, min(m - 2, 127)] are
+    rejected at create."""
     A = convdiff2d(30, (2.0, 1.0))
-    for (k, m, want) in [(6, 24, 10), (10, 40, 17), (50, 120, 63), (6, 8, 6)]:
+    for (k, m, want) in [(6, 24, 10), (10, 40, 17), (50, 120, 67), (6, 8, 6), (100, 250, 127)]:
         with P.Solver.from_csr(A, k=k, m=m, d=m + 20, which="LR", tol=1e-6, keep=-1, max_restarts=1) as s:
             s.solve()
             assert s.stats.keep == want, (k, m, s.stats.keep)
-    for bad in (5, 23, 64):
+    for bad, m in ((5, 24), (23, 24), (128, 200)):
         with pytest.raises(P.RksError) as ei:
-            P.Solver.from_csr(A, k=6, m=24 if bad != 64 else 100, d=130, which="LR", tol=1e-6, keep=bad)
+            P.Solver.from_csr(A, k=6, m=m, d=m + 20, which="LR", tol=1e-6, keep=bad)
         assert ei.value.code == -1
 
 
