@@ -175,6 +175,56 @@ def _cpu_model():
     return "unknown"
 
 
+# The paper's synthetic experiment (Section 5.1): tridiagonal matrices with the
+# spectra of Table "SynthTestMatrices" on the diagonal and N(0,1)/100 noise on
+# both off-diagonals; k = 40 eigenpairs, m = 2k = 80, sparse-sign sketch with
+# d = 2m, the paper's stop (every estimate <= 1e-10, at most 300 restarts);
+# eight panels: the four spectra LM, three of them SM, and "Exponential SM,
+# 10 iterations" (restarts fixed at 10).
+PANELS = [("exponential", "LM", 300), ("logarithmic", "LM", 300), ("harmonic", "LM", 300),
+          ("geometric", "LM", 300), ("exponential", "SM", 300), ("logarithmic", "SM", 300),
+          ("harmonic", "SM", 300), ("exponential", "SM", 10)]
+
+
+def run_panels(sizes, methods, keeps, stream):
+    """One solve per (panel, n, method, restart size); one JSON line each."""
+    import numpy as np
+    import torch
+
+    import paper_2508_05400_amd as P
+    from workloads import tridiag_noisy
+
+    # load every kernel once before timing anything
+    A = tridiag_noisy(4000, "exponential", 7)
+    with P.Solver.from_csr(A, k=40, m=80, d=160, which="LM", tol=1e-10, sketch_kind="sparse", sketch_seed=7,
+                           max_restarts=1, stream=stream) as s:
+        s.solve()
+    for n in sizes:
+        mats = {}
+        for spec, which, cap in PANELS:
+            if spec not in mats:
+                mats[spec] = tridiag_noisy(n, spec, 7)
+            A = mats[spec]
+            for method in methods:
+                for keep in keeps:
+                    with P.Solver.from_csr(A, k=40, m=80, d=160, which=which, tol=1e-10, sketch_kind="sparse",
+                                           sketch_seed=7, start_seed=1, max_restarts=cap, keep=keep, method=method,
+                                           stream=stream) as s:
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        code = s.solve()
+                        torch.cuda.synchronize()
+                        dt = time.perf_counter() - t0
+                        st = s.stats.as_dict()
+                        lam, _, res = s.eigpairs(want_vectors=False, want_resid=True)
+                    rec = {"panel": f"{spec} {which}" + (f", {cap} restarts" if cap != 300 else ""), "n": n,
+                           "method": method, "keep": st["keep"], "keep_rule": "k (Algorithm 1)" if keep == 0 else
+                           "auto", "time_s": dt, "restarts": st["restarts"], "converged": bool(st["converged"]),
+                           "code": code, "max_est": st["max_est"], "max_resid": float(np.max(res)),
+                           "matvecs": st["matvecs"], "lam_top": [float(lam[0].real), float(lam[-1].real)]}
+                    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +249,10 @@ def main():
                     "'variants'")
     ap.add_argument("--compare-steps", type=int, default=2, help="timed solves per variant (after one untimed solve); "
                     "alg1 and eta, which may run to the restart cap, are timed once without the untimed one")
+    ap.add_argument("--panels", default=None, help="run the synthetic tridiagonal experiment instead (comma list of "
+                    "n, e.g. 100000,1000000,5000000); prints one JSON line per solve")
+    ap.add_argument("--panel-methods", default="rks,ks_cgs2")
+    ap.add_argument("--panel-keeps", default="0,-1", help="restart sizes of the panel runs: 0 = k, -1 = auto")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU row-block "
@@ -212,6 +266,10 @@ def main():
     from workloads import named_config
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.panels:
+        run_panels([int(float(x)) for x in args.panels.split(",")], args.panel_methods.split(","),
+                   [int(x) for x in args.panel_keeps.split(",")], torch.cuda.current_stream())
+        return
     cfg = named_config(args.workload)
     if args.precision:
         cfg["precision"] = args.precision
