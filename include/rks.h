@@ -140,6 +140,10 @@ typedef struct {
                             Default 0: on the measured workloads the host stays
                             ahead of the GPU, so replays save no time; they
                             save host launch work. */
+  int32_t stall_restarts; /* S > 0: stop (RKS_ENOTCONV, stop_reason 3) when the largest
+                            estimate |b^T y| / |lambda| has not fallen below half of its
+                            level S restarts earlier (stagnation, as on operators whose
+                            wanted eigenvalues are packed together); 0 = off (default) */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -156,7 +160,8 @@ typedef struct {
   int32_t breakdowns;    /* invariant subspaces met and continued past (Section 2.1) */
   int32_t dense_fail;    /* reorderings that had to stop early */
   double max_est;        /* max |b^T y| / |lambda| at exit (eq. "rks_reserror_bound") */
-  int32_t stop_reason;   /* 0 restart cap, 1 estimates <= tol, 2 verified residuals <= resid_tol */
+  int32_t stop_reason;   /* 0 restart cap, 1 estimates <= tol, 2 verified residuals <= resid_tol,
+                            3 stagnation (opts.stall_restarts) */
   int32_t resid_checks;  /* device residual verifications performed */
   double max_resid;      /* largest verified residual at exit (0 if never verified) */
   int32_t restarts_lo;   /* restarts of the low-precision phase (mixed precision) */

@@ -34,7 +34,8 @@ class RksOpts(ctypes.Structure):
                 ("whiten_tol", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("resid_tol", ctypes.c_double), ("refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("spmv_layout", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("keep", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("keep", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("stall_restarts", ctypes.c_int32)]
 
 
 class RksStats(ctypes.Structure):

@@ -924,6 +924,9 @@ int run_phase(rks_ctx* c, const double* u0, int u0_on_device, double tol, double
   if (rc) return rc;
   int restarts = 0, reason = 0;
   double maxest = 0.0, maxres = 0.0, last_fail_pred = INFINITY, thost = 0.0;
+  // stagnation: the restart at which the largest estimate last halved
+  double stall_mark = INFINITY;
+  int stall_at = 0;
   // true max residual / predicted max residual at the last failed verification
   // (the predicted residual |b^T y| / ||A||_1 misses the embedding's distortion
   // of ||u_{k+1}|| / ||x||, so the two differ by a slowly varying factor)
@@ -973,6 +976,14 @@ int run_phase(rks_ctx* c, const double* u0, int u0_on_device, double tol, double
       } else {
         last_fail_pred = pred;
         ratio = std::max(mr / std::max(pred, 1e-300), 1e-3);
+      }
+    }
+    if (reason == 0 && allfinite) {
+      if (maxest < 0.5 * stall_mark) {
+        stall_mark = maxest;
+        stall_at = restarts;
+      } else if (c->o.stall_restarts > 0 && restarts - stall_at >= c->o.stall_restarts) {
+        reason = 3;
       }
     }
     const bool stop = reason != 0 || restarts >= max_restarts;
@@ -1084,9 +1095,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
       !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
-      o.method > 1 || o.graphs < 0 || o.graphs > 1)
+      o.method > 1 || o.graphs < 0 || o.graphs > 1 || o.stall_restarts < 0)
     return fail(nullptr, RKS_EINVAL,
-                "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout, method or graphs");
+                "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout, method, graphs or "
+                "stall_restarts");
   int keep = o.keep == 0 ? k : o.keep;
   if (o.keep == RKS_KEEP_AUTO)
     keep = std::max(k, std::min({k + (m - k) / 4, m - 2, rks::kRotMax - 1}));
@@ -1412,7 +1424,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
     if (hipStreamSynchronize(c->env.stream) != hipSuccess) rc = fail(c, RKS_EHIP, "stream synchronize");
     flush_events(c);
   }
-  st->converged = p1.reason != 0 ? 1 : 0;
+  st->converged = (p1.reason == 1 || p1.reason == 2) ? 1 : 0;
   st->stop_reason = p1.reason;
   st->max_resid = p1.maxres;
   st->resid_checks = p1.resid_checks;
@@ -1427,6 +1439,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   c->st = nullptr;
   if (rc) return rc;
   c->solved = true;
+  if (p1.reason == 3) return fail(c, RKS_ENOTCONV, "stagnation: the estimates stopped falling");
   return p1.reason != 0 ? RKS_OK : fail(c, RKS_ENOTCONV, "max_restarts reached");
 }
 

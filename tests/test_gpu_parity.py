@@ -197,6 +197,9 @@ CONV = {
     "cd2d-40-LR-sparse-keep14": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 14),
     # aggressive deflation (lock = 2) on a case with complex Ritz pairs
     "cd2d-40-LR-sparse-aggr": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 14, 2),
+    # a 4000-row twin of the power-law workload (its k, m, d; automatic restart
+    # size 67, which takes more than 64 columns through the rotation)
+    "powerlaw-4000-LM-keepauto": (lambda: powerlaw_random(4000, 4), 50, 120, 480, "LM", "sparse", -1),
 }
 
 
@@ -287,6 +290,31 @@ def test_error_paths(lib, cuda):
         assert ei.value.code == -4  # RKS_ENAN
     finally:
         s.close()
+
+
+def test_stagnation_stop(lib, cuda):
+    """stall_restarts = S stops a solve whose largest estimate has not halved
+    within S restarts (RKS_ENOTCONV, stop_reason 3).  On the 100^2 workload
+    with Algorithm 1's truncation, which stalls (the oracle pin
+    test_algorithm1_truncation_stalls_on_the_small_2d_workload), the solve
+    stops well before the cap, with the estimate history showing no halving
+    over its last S restarts; with S = 0 it runs to the cap."""
+    A = convdiff2d(100, (20.0, 10.0))
+    kw = dict(k=10, m=40, d=80, which="LR", tol=1e-10, sketch_kind="gauss", sketch_seed=0, start_seed=1,
+              resid_tol=1e-8, max_restarts=300)
+    S = 25
+    with P.Solver.from_csr(A, stall_restarts=S, **kw) as s1:
+        assert s1.solve() == 1
+        st = s1.stats.as_dict()
+        assert "stagnation" in P.rks_last_error(s1.ctx)
+    assert st["stop_reason"] == 3 and st["converged"] == 0
+    r = st["restarts"]
+    assert S <= r < 300
+    h = np.array(st["hist_est"][:r + 1])
+    assert h[r - S:].min() >= 0.5 * h[:r - S + 1].min() * (1 - 1e-12)
+    with P.Solver.from_csr(A, **kw) as s2:
+        assert s2.solve() == 1
+        assert s2.stats.stop_reason == 0 and s2.stats.restarts == 300
 
 
 def test_verified_residual_stop(lib, cuda):
