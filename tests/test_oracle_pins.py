@@ -637,3 +637,41 @@ def test_low_precision_residual_floor():
     assert r32.converged and r16.converged
     assert 1e-9 < r32.resid.max() < 1e-5
     assert 1e-5 < r16.resid.max() < 1e-1
+
+
+def _true_resid(o):
+    lam, Y, _ = o.ritz()
+    X = o.U[:, :o.kr] @ Y
+    R = o.A @ X - X * lam[None, :]
+    return float(np.max(np.linalg.norm(R, axis=0) / (o.normA1 * np.linalg.norm(X, axis=0))))
+
+
+def test_fp64_phase_after_low_precision_gains_no_restarts():
+    """Why the mixed-precision solve cannot beat FP64 on these operators (a
+    finding of this build, on the oracle; mixed precision is the paper's
+    future work).  After a BF16 phase has reached its floor (residual ~1e-2),
+    (a) continuing that same decomposition in FP64 keeps the floor: the
+    rounding errors of the stored columns sit in the Krylov relation of the
+    kept Schur vectors, where later FP64 steps cannot reach them, while the
+    estimates |b^T y| / |lambda| keep falling; (b) restarting FP64 from one
+    vector, a fixed combination of the BF16 Schur vectors, needs as many
+    restarts to reach residual 1e-8 as FP64 from the random start."""
+    A = convdiff2d(60, (20.0, 10.0))
+    kw = dict(sketch="sparse", sketch_seed=3, start_seed=1, keep=-1, max_restarts=100)
+    r64 = RKSOracle(A, 10, 40, 80, "LR", 1e-10, resid_tol=1e-8, **kw).run()
+    assert r64.converged and r64.restarts >= 15
+    lo = RKSOracle(A, 10, 40, 80, "LR", 1e-10, resid_tol=1e-2, store="bf16", **kw)
+    rl = lo.run()
+    assert rl.converged and rl.restarts < r64.restarts
+    c = 1.0 + 0.25 * (np.arange(lo.kr) % 3)
+    refined = RKSOracle(A, 10, 40, 80, "LR", 1e-10, resid_tol=1e-8, **kw).run(lo.U[:, :lo.kr] @ c)
+    assert refined.converged and refined.restarts >= 0.8 * r64.restarts
+    lo.store = "fp64"
+    res, est = [], []
+    for _ in range(15):
+        lo.lock_converged()
+        lo.extend()
+        lo.contract()
+        res.append(_true_resid(lo))
+        est.append(float(np.max(lo.ritz()[2])))
+    assert min(res) > 1e-4 and est[-1] < 1e-5, (min(res), est[-1])
