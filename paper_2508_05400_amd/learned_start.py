@@ -196,7 +196,7 @@ def solve(A, u0=None, resid_tol=1e-5, want_vectors=True, keep=0):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=1000)
+    ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=32)
