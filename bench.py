@@ -241,6 +241,8 @@ def main():
                     help="time the kernels of every P-th Arnoldi step with HIP events (the events "
                          "around whole steps cost a few microseconds each, so the sample is sparse)")
     ap.add_argument("--keep", default="auto", help="restart size: auto (k + (m-k)/4), or a number in [k, m-2]")
+    ap.add_argument("--refine", type=int, default=1, help="low-precision main run: 1 = FP64 refinement phase, "
+                    "0 = none (the run stops at its own verified residual --resid-tol)")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay repeated extensions as HIP graphs (used only "
                     "when the per-kernel events are off, --no-profile); 0: launch every kernel")
     ap.add_argument("--compare", default="fp32,bf16,alg1,eta", help="comma list of extra runs on the same workload "
@@ -282,7 +284,8 @@ def main():
                                sketch_kind=cfg["sketch"], zeta=cfg["zeta"], sketch_seed=cfg["sketch_seed"],
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else args.profile_every,
-                               resid_tol=args.resid_tol, keep=keep, graphs=args.graphs, stream=stream)
+                               resid_tol=args.resid_tol, keep=keep, graphs=args.graphs, refine=args.refine,
+                               stream=stream)
     for _ in range(args.warmup):
         solver.solve()
     torch.cuda.synchronize()
