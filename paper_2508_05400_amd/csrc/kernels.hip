@@ -154,13 +154,17 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
 // Omega w.  Workgroups are dealt to the 8 XCDs round-robin (block b runs on
 // XCD b % 8); giving each XCD one contiguous eighth of the tiles keeps the x
 // entries that neighbouring rows share (stencil offsets) inside one XCD's L2.
+// The kernel is bound by the latency of its two dependent loads per tile
+// (nonzeros, then the gathered x), so it wants many resident waves: small
+// workgroups (kSpmvWaves waves, each with its LDS slice and d sketch bins)
+// let five of them share a CU, where two 8-wave workgroups fit before.
 template <typename TV, typename TW, typename TA, int KIND>
-__global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
+__global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
                                                      const TA* __restrict__ val, const int4* __restrict__ tdesc,
                                                      int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
                                                      double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
-  extern __shared__ double bins[];  // 8 waves x d
-  __shared__ TA prod[8][kTileNnz];
+  extern __shared__ double bins[];  // kSpmvWaves waves x d
+  __shared__ TA prod[kSpmvWaves][kTileNnz];
   const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -173,13 +177,13 @@ __global__ __launch_bounds__(512) void k_spmv_sketch(const int* __restrict__ rp,
   if (Gx > 0 && (gridDim.x & 7) == 0) {
     const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
     const int chunk = (ntiles + 7) >> 3;
-    t0 = xcd * chunk + lb * 8 + wv;
+    t0 = xcd * chunk + lb * kSpmvWaves + wv;
     tend = min(ntiles, (xcd + 1) * chunk);
-    tstep = Gx * 8;
+    tstep = Gx * kSpmvWaves;
   } else {
-    t0 = blockIdx.x * 8 + wv;
+    t0 = blockIdx.x * kSpmvWaves + wv;
     tend = ntiles;
-    tstep = gridDim.x * 8;
+    tstep = gridDim.x * kSpmvWaves;
   }
   for (int t = t0; t < tend; t += tstep) {
     const int4 dsc = tdesc[t];  // wave-uniform
@@ -1300,10 +1304,10 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
     if (prec == 1) return spmv_cb_t<float, float, float>(e, e.val32_cb, (const float*)x, (float*)w, zpart, do_sketch);
     return spmv_cb_t<bf16_t, float, float>(e, e.val32_cb, (const bf16_t*)x, (float*)w, zpart, do_sketch);
   }
-  int G = grid_for(e.ntiles, 8, kMaxG);
+  int G = grid_for(e.ntiles, kSpmvWaves, kSpmvMaxG);
   if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the tile mapping)
-  dim3 grid(G), block(512);
-  const size_t lds = bins_lds(e, 8, do_sketch && e.sp_kind == 1);
+  dim3 grid(G), block(64 * kSpmvWaves);
+  const size_t lds = bins_lds(e, kSpmvWaves, do_sketch && e.sp_kind == 1);
   if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<double, double, double, KIND>, lds);
                       launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<double, double, double, KIND>, grid, block, lds,

@@ -22,6 +22,9 @@ namespace rks {
 constexpr int kMaxD = 1024;      // largest sketch size (LDS bins)
 constexpr int kMaxM = 255;       // largest Krylov dimension
 constexpr int kMaxG = 512;       // largest number of partial-sum rows (producer blocks)
+constexpr int kSpmvWaves = 4;    // waves per SpMV workgroup
+constexpr int kSpmvMaxG = 1280;  // SpMV workgroups at most (5 per CU: LDS-bound for FP64 with d <= 360)
+constexpr int kMaxPart = kSpmvMaxG > kMaxG ? kSpmvMaxG : kMaxG;  // partial rows of the SpMV's sketch
 constexpr int kTileRows = 64;    // rows per SpMV wave tile
 constexpr int kTileNnz = 512;    // nonzeros staged per SpMV wave tile (LDS slice)
 constexpr int kTileFill = kTileNnz - 2;  // nonzeros a tile may hold: paired loads start at the even

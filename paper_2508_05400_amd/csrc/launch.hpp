@@ -38,7 +38,8 @@ struct LaunchEnv {
   int vbytes() const { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 };
 
-// w = A x, partials of Omega w (returns the number of partial rows).
+// w = A x, partials of Omega w (returns the number of partial rows, at most
+// kMaxPart: zpart holds kMaxPart x d).
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override);
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob);
 // E = S^T S - I ((m+1) x (m+1), leading dimension ldb), kept current column by column.

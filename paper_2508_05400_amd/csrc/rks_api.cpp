@@ -1276,7 +1276,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->coef, (size_t)(m + 2) * 8);
   dm((void**)&c->z, (size_t)d * 8);
   dm((void**)&c->sr, (size_t)d * 8);
-  dm((void**)&c->zpart, (size_t)rks::kMaxG * d * 8);
+  dm((void**)&c->zpart, (size_t)rks::kMaxPart * d * 8);
   dm((void**)&c->spart, (size_t)rks::kMaxG * d * 8);
   dm((void**)&c->scal, 8 * 8);
   dm((void**)&c->Yd, (size_t)(m + 1) * (m + 1) * 8);
