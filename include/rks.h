@@ -57,12 +57,15 @@ typedef enum { RKS_SKETCH_GAUSS = 0, RKS_SKETCH_SPARSE = 1 } rks_sketch_kind;
  * Rayleigh quotient and all small dense steps stay FP64). */
 typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2 } rks_precision;
 
-/* SpMV layout.  ROWS: wave tiles of consecutive rows.  COLUMN_BLOCKS: the
- * columns split into 8 contiguous blocks, one per XCD, each multiplied on its
- * own and the 8 partial vectors added (for rows that gather x from everywhere,
- * with x larger than an XCD's L2; it stores a second, column-blocked copy of
- * A and 8 partial vectors).  AUTO picks COLUMN_BLOCKS when n >= 2^20 and the
- * median column span of a row tile exceeds n/4. */
+/* SpMV layout.  ROWS: wave tiles of consecutive rows.  COLUMN_BLOCKS: for
+ * rows that gather x from everywhere, with x larger than an XCD's L2: the
+ * columns split into 8 contiguous blocks and the rows into panels, one
+ * workgroup per panel, which multiplies its rows block after block (all
+ * workgroups on the same block at about the same time, so the gathered part
+ * of x stays in L2) and keeps the row sums in LDS until w is written (it
+ * stores a second copy of A, reordered by panel and block, with 16-bit row
+ * offsets).  AUTO picks COLUMN_BLOCKS when n >= 2^20 and the median column
+ * span of a row tile exceeds n/4. */
 typedef enum { RKS_SPMV_AUTO = 0, RKS_SPMV_ROWS = 1, RKS_SPMV_COLUMN_BLOCKS = 2 } rks_spmv_layout;
 
 /* RKS: randomized Krylov-Schur (Algorithm 1 with Algorithm 2).  KS_CGS2:

@@ -26,6 +26,7 @@ SOURCES = [
     ("net.hip", ["hipcc", "-x", "hip"] + HIP_FLAGS),
     ("rks_api.cpp", ["hipcc"] + HOST_FLAGS + ["-D__HIP_PLATFORM_AMD__"]),
     ("dense.cpp", ["g++"] + HOST_FLAGS),
+    ("panels.cpp", ["g++"] + HOST_FLAGS),
 ]
 
 

@@ -218,54 +218,129 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
   if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
 }
 
-// Column-blocked SpMV for operators whose rows gather x from everywhere (x
-// larger than an XCD's L2 and no locality to exploit).  The columns are split
-// into kCb contiguous blocks; block c of A is a CSR matrix of its own (all n
-// rows) with its own wave tiles.  Workgroup b runs on XCD b % kCb and
-// multiplies column block b % kCb only, so the x entries it gathers span
-// n / kCb values that stay in that XCD's L2.  Row sums go to P(:, c); a second
-// kernel adds the kCb partial vectors in a fixed order and sketches w.
-template <typename TV, typename TW, typename TA>
-__global__ __launch_bounds__(512) void k_spmv_cb(int64_t n, const int* __restrict__ rp, const int* __restrict__ col,
-                                                 const TA* __restrict__ val, const int4* __restrict__ tdesc,
-                                                 CbTiles cb, const TV* __restrict__ x, TW* __restrict__ P,
-                                                 int64_t ldp) {
-  __shared__ TA prod[8][kTileNnz];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  TA* pw = prod[wv];
-  const int c = blockIdx.x % kCb, lb = blockIdx.x / kCb, Gc = gridDim.x / kCb;
-  const int* rpc = rp + (int64_t)c * (n + 1);  // this block's row pointers (global offsets)
-  TW* Pc = P + (int64_t)c * ldp;
-  for (int t = cb.off[c] + lb * 8 + wv; t < cb.off[c + 1]; t += Gc * 8) {
-    const int4 dsc = tdesc[t];
-    int rr, sub;
-    const TA s = tile_rows<TV, TA>(rpc, col, val, x, dsc, pw, lane, rr, sub, [](int, int) {});
-    if (rr < dsc.y && sub == 0) Pc[dsc.x + rr] = (TW)s;
+// Row sums of one panel tile {first row r0 (within the panel), rows nr, first
+// nonzero e0, nonzeros ne} of the column-blocked layout, added to the panel's
+// row sums acc (LDS).  As in tile_rows, a lane loads up to 4 pairs of
+// nonzeros and gathers x for them, all issued before any use, and the products
+// go to the wave's LDS slice pw; here a lane also loads the 16-bit row
+// offsets of its rows (lane + 64 j, j < kPanelTileRows / 64) with them, and
+// then sums each of its rows from LDS in order.  A long tile (ob < 0: one row
+// with more than kTileFill nonzeros) is summed by the whole wave.  Only the
+// lane that sums a row touches acc for it, and rows of different tiles of one
+// column block are disjoint, so no two waves write the same sum between the
+// workgroup's barriers.
+template <typename TV, typename TA>
+__device__ __forceinline__ void panel_tile(const int* __restrict__ col, const TA* __restrict__ val,
+                                           const uint16_t* __restrict__ off, int ob, const TV* __restrict__ x,
+                                           int4 dsc, TA* pw, double* acc, int lane) {
+  typedef TA TA2 __attribute__((ext_vector_type(2)));
+  constexpr int NP = kTileNnz / 128;       // pairs per lane
+  constexpr int RL = kPanelTileRows / 64;  // rows per lane
+  const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
+  if (ob < 0) {
+    TA s = 0;
+    for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) acc[r0] += (double)s;
+    return;
   }
+  int ra[RL], rb[RL];
+#pragma unroll
+  for (int j = 0; j < RL; ++j) {
+    const int r = lane + 64 * j;
+    ra[j] = 0;
+    rb[j] = 0;
+    if (r < nr) {
+      ra[j] = off[ob + r];
+      rb[j] = off[ob + r + 1];
+    }
+  }
+  // pair p covers tile entries 2p - sh and 2p + 1 - sh (ne + sh <= 2 NP 64)
+  const int e0a = e0 & ~1, sh = e0 - e0a, nea = ne + sh;
+  int2 ci[NP];
+  TA2 vv[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int p2 = 2 * (lane + 64 * u);
+    if (p2 < nea) {
+      ci[u] = *(const int2*)(col + e0a + p2);
+      vv[u] = *(const TA2*)(val + e0a + p2);
+    }
+  }
+  TA xa[NP], xb[NP];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int p2 = 2 * (lane + 64 * u);
+    if (p2 < nea) {
+      if (p2 >= sh) xa[u] = (TA)Conv<TV>::ld(x[ci[u].x]);
+      if (p2 + 1 < nea) xb[u] = (TA)Conv<TV>::ld(x[ci[u].y]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    const int p2 = 2 * (lane + 64 * u);
+    if (p2 < nea) {
+      if (p2 >= sh) pw[p2 - sh] = vv[u].x * xa[u];
+      if (p2 + 1 < nea) pw[p2 + 1 - sh] = vv[u].y * xb[u];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < RL; ++j) {
+    const int r = lane + 64 * j;
+    if (r < nr) {
+      TA s = 0;
+      for (int e = ra[j]; e < rb[j]; ++e) s += pw[e];
+      acc[r0 + r] += (double)s;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
-// w = sum_c P(:, c) (c in order) and partials of Omega w.
-template <typename TW, int KIND>
-__global__ __launch_bounds__(512) void k_cb_combine(int64_t n, const TW* __restrict__ P, int64_t ldp,
-                                                    TW* __restrict__ w, double* __restrict__ zpart, SketchP sp,
-                                                    int do_sketch_arg) {
-  extern __shared__ double bins[];  // 8 waves x d
+// Column-blocked SpMV for operators whose rows gather x from everywhere (x
+// larger than an XCD's L2, no locality to exploit), on the layout of
+// panels.hpp: kCb column blocks of n / kCb columns (that much of x fits in an
+// XCD's L2) and one workgroup per row panel.  The workgroup multiplies block
+// 0 of its rows, then block 1, and so on, streaming its panel's nonzeros in
+// one contiguous pass and keeping the panel's row sums in LDS, with a barrier
+// between blocks (so each row adds its block sums in block order).  All
+// workgroups start on block 0 and move on at about the same pace, so the x
+// entries the chip gathers at any moment lie in one or two blocks, held in
+// every XCD's L2.  The sums leave the workgroup once, as w, with the sketch of
+// w added on the way.  LDS: the row sums (rows_pp FP64, rounded up to even),
+// then either the waves' product slices (during the blocks) or their sketch
+// bins (afterwards) in the same space.
+template <typename TV, typename TW, typename TA, int KIND>
+__global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_panel(
+    int64_t n, int rows_pp, const int* __restrict__ col, const TA* __restrict__ val, const int4* __restrict__ tdesc,
+    const int* __restrict__ toff, const uint16_t* __restrict__ off, const int* __restrict__ ptile,
+    const TV* __restrict__ x, TW* __restrict__ w, double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
+  extern __shared__ double smem[];
+  const int accn = (rows_pp + 1) & ~1;
+  double* acc = smem;
+  TA* stage = (TA*)(smem + accn);
+  double* bins = smem + accn;
   const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t R0 = (int64_t)blockIdx.x * rows_pp;
+  const int nrows = (int)min((int64_t)rows_pp, n - R0);
+  for (int i = tid; i < nrows; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  TA* pw = stage + wv * kTileNnz;
+  const int* pt = ptile + (size_t)blockIdx.x * (kCb + 1);
+  for (int c = 0; c < kCb; ++c) {
+    const int t1 = pt[c + 1];
+    for (int t = pt[c] + wv; t < t1; t += kSpmvWaves) panel_tile<TV, TA>(col, val, off, toff[t], x, tdesc[t], pw, acc, lane);
+    __syncthreads();
+  }
   if (do_sketch) bins_zero(bins, sp.d);
   __syncthreads();
   double* wb = wave_bins(bins, sp.d);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    TW v[kCb];
-#pragma unroll
-    for (int c = 0; c < kCb; ++c) v[c] = P[i + (int64_t)c * ldp];
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < kCb; ++c) s += (double)v[c];
-    const TW ws = (TW)s;
-    w[i] = ws;
-    if (do_sketch) sketch_add<KIND>(wb, (uint64_t)i, (double)ws, sp);
+  for (int i = tid; i < nrows; i += blockDim.x) {
+    const TW ws = (TW)acc[i];
+    w[R0 + i] = ws;
+    if (do_sketch) sketch_add<KIND>(wb, (uint64_t)(R0 + i), (double)ws, sp);
   }
   __syncthreads();
   if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
@@ -1282,27 +1357,25 @@ static int gauss_t(const LaunchEnv& e, const TX* x, double* part) {
 }
 
 template <typename TV, typename TW, typename TA>
-static int spmv_cb_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, double* zpart, int do_sketch) {
-  const int ntiles = e.cbt.off[kCb];
-  int G1 = grid_for(ntiles, 8, 2048);
-  G1 = (G1 + kCb - 1) / kCb * kCb;  // every column block gets the same number of workgroups
-  launch_k(e, true, false, k_spmv_cb<TV, TW, TA>, dim3(G1), dim3(512), 0, e.n, e.rp_cb, e.col_cb, val,
-           (const int4*)e.tiles_cb, e.cbt, x, (TW*)e.P, e.ldu);
-  const int G2 = grid_for(e.n, 512, kMaxG);
-  const size_t lds = bins_lds(e, 8, do_sketch && e.sp_kind == 1);
-  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_cb_combine<TW, KIND>, lds);
-                    launch_k(e, false, !(do_sketch && e.sp_kind == 0), k_cb_combine<TW, KIND>, dim3(G2),
-                             dim3(512), lds, e.n, (const TW*)e.P, e.ldu, w, zpart, e.sp, do_sketch));
+static int spmv_panel_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, double* zpart, int do_sketch) {
+  const size_t accn = (size_t)((e.rows_pp + 1) & ~1);
+  const size_t stage = (size_t)kSpmvWaves * kTileNnz * sizeof(TA);
+  const size_t bins = bins_lds(e, kSpmvWaves, do_sketch && e.sp_kind == 1);
+  const size_t lds = accn * 8 + (stage > bins ? stage : bins);
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_panel<TV, TW, TA, KIND>, lds);
+                    launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_panel<TV, TW, TA, KIND>,
+                             dim3(e.npanels), dim3(64 * kSpmvWaves), lds, e.n, e.rows_pp, e.col_pn, val,
+                             (const int4*)e.tiles_pn, e.toff_pn, e.off_pn, e.ptile, x, w, zpart, e.sp, do_sketch));
   if (do_sketch && e.sp_kind == 0) return gauss_t<TW>(e, w, zpart);
-  return G2;
+  return e.npanels;
 }
 
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
   const int prec = prec_override >= 0 ? prec_override : e.prec;
   if (e.cb) {
-    if (prec == 0) return spmv_cb_t<double, double, double>(e, e.val_cb, (const double*)x, (double*)w, zpart, do_sketch);
-    if (prec == 1) return spmv_cb_t<float, float, float>(e, e.val32_cb, (const float*)x, (float*)w, zpart, do_sketch);
-    return spmv_cb_t<bf16_t, float, float>(e, e.val32_cb, (const bf16_t*)x, (float*)w, zpart, do_sketch);
+    if (prec == 0) return spmv_panel_t<double, double, double>(e, e.val_pn, (const double*)x, (double*)w, zpart, do_sketch);
+    if (prec == 1) return spmv_panel_t<float, float, float>(e, e.val32_pn, (const float*)x, (float*)w, zpart, do_sketch);
+    return spmv_panel_t<bf16_t, float, float>(e, e.val32_pn, (const bf16_t*)x, (float*)w, zpart, do_sketch);
   }
   int G = grid_for(e.ntiles, kSpmvWaves, kSpmvMaxG);
   if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the tile mapping)

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.hpp"
 #include "philox.hpp"
 
 namespace rks {
@@ -22,14 +23,7 @@ namespace rks {
 constexpr int kMaxD = 1024;      // largest sketch size (LDS bins)
 constexpr int kMaxM = 255;       // largest Krylov dimension
 constexpr int kMaxG = 512;       // largest number of partial-sum rows (producer blocks)
-constexpr int kSpmvWaves = 4;    // waves per SpMV workgroup
-constexpr int kSpmvMaxG = 1280;  // SpMV workgroups at most (5 per CU: LDS-bound for FP64 with d <= 360)
-constexpr int kMaxPart = kSpmvMaxG > kMaxG ? kSpmvMaxG : kMaxG;  // partial rows of the SpMV's sketch
-constexpr int kTileRows = 64;    // rows per SpMV wave tile
-constexpr int kTileNnz = 512;    // nonzeros staged per SpMV wave tile (LDS slice)
-constexpr int kTileFill = kTileNnz - 2;  // nonzeros a tile may hold: paired loads start at the even
-                                         // index at or below its first nonzero
-constexpr int kCsrPad = 2;       // readable padding entries after col[] and val[] (paired loads)
+constexpr int kMaxPart = kSpmvMaxG > kMaxG ? kSpmvMaxG : kMaxG;  // partial rows of the row-tile SpMV's sketch
 constexpr int kRotMax = 128;     // output columns per rotation pass (8 MFMA column tiles)
 constexpr size_t kRotLdsMax = 160 * 1024;  // Y in LDS up to this size, else read from global memory
 constexpr size_t kLsLdsMax = 150 * 1024;  // LDS budget of the least-squares kernel
@@ -61,13 +55,6 @@ struct Conv<bf16_t> {
     r.b = (uint16_t)(u >> 16);
     return r;
   }
-};
-
-constexpr int kCb = 8;  // column blocks of the column-blocked SpMV (one per XCD)
-
-// First wave tile of each column block (tiles of block c are off[c] .. off[c+1]-1).
-struct CbTiles {
-  int off[kCb + 1];
 };
 
 struct SketchP {

@@ -21,15 +21,18 @@ struct LaunchEnv {
   int64_t ldu;         // basis leading dimension (n rounded up to 128; padding rows are zero)
   int sp_kind;         // 0 Gaussian (applied by k_gauss_sketch), 1 sparse-sign, 2 none (deterministic KS)
   SketchP sp;
-  // column-blocked SpMV (used when cb = 1): kCb CSR blocks with global offsets
+  // column-blocked SpMV (used when cb = 1): the layout of panels.hpp, one
+  // workgroup per row panel of rows_pp rows
   int cb = 0;
-  const int* rp_cb = nullptr;       // kCb x (n+1) row pointers into col_cb / val_cb
-  const int* col_cb = nullptr;
-  const double* val_cb = nullptr;
-  const float* val32_cb = nullptr;  // mixed precision only
-  const int* tiles_cb = nullptr;    // wave tiles of all blocks, block after block
-  CbTiles cbt{};
-  void* P = nullptr;                // kCb partial vectors, leading dimension ldu (FP64 or FP32)
+  int npanels = 0;
+  int rows_pp = 0;
+  const int* col_pn = nullptr;
+  const double* val_pn = nullptr;
+  const float* val32_pn = nullptr;  // mixed precision only
+  const int* tiles_pn = nullptr;    // 4 per tile: first row within the panel, rows, first nonzero, nonzeros
+  const int* toff_pn = nullptr;     // per tile: first row offset, -1 for a long tile
+  const uint16_t* off_pn = nullptr; // row offsets of the tiles
+  const int* ptile = nullptr;       // (kCb + 1) per panel: first tile of each column block, then the end
   // Timing (null when off): a launcher that runs with these set records ev0 at
   // the start of its first kernel and ev1 at the end of its last one, from the
   // dispatches' own timestamps (no marker packets between the kernels).
@@ -38,8 +41,8 @@ struct LaunchEnv {
   int vbytes() const { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 };
 
-// w = A x, partials of Omega w (returns the number of partial rows, at most
-// kMaxPart: zpart holds kMaxPart x d).
+// w = A x, partials of Omega w (returns the number of partial rows: at most
+// kMaxPart for the row tiles, npanels for the column-blocked layout).
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override);
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob);
 // E = S^T S - I ((m+1) x (m+1), leading dimension ldb), kept current column by column.

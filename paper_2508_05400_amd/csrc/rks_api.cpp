@@ -21,6 +21,7 @@
 
 #include "dense.h"
 #include "launch.hpp"
+#include "panels.hpp"
 #include "rks.h"
 
 using rks::cplx;
@@ -75,11 +76,11 @@ struct rks_ctx {
   double* E = nullptr;  // S^T S - I, (m+1) x (m+1), leading dimension m+1
   double* kpart = nullptr;  // deterministic Krylov-Schur: partial rows of U^T x (kMaxG x (m+1))
   bool ks = false;          // deterministic Krylov-Schur (RKS_METHOD_KS_CGS2)
-  // column-blocked SpMV layout (when chosen): blocks of A, their tiles, partial vectors
-  int *rp_cb = nullptr, *col_cb = nullptr, *tiles_cb = nullptr;
-  double* val_cb = nullptr;
-  float* val32_cb = nullptr;
-  void* P = nullptr;
+  // column-blocked SpMV layout (when chosen): A by row panel and column block, its tiles
+  int *col_pn = nullptr, *tiles_pn = nullptr, *toff_pn = nullptr, *ptile = nullptr;
+  uint16_t* off_pn = nullptr;
+  double* val_pn = nullptr;
+  float* val32_pn = nullptr;
   double *Xr = nullptr, *ax1 = nullptr, *ax2 = nullptr, *rpart = nullptr;  // residual scratch (lazy)
   // E, B, S, cs and flags live in one device block and one pinned host block
   // of the same layout, so a restart moves them with one copy each way
@@ -1032,7 +1033,7 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->dstate, c->val, c->val32, c->U_lo, c->U64, c->w,
                  c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->kpart,
-                 c->rp_cb, c->col_cb, c->tiles_cb, c->val_cb, c->val32_cb, c->P,
+                 c->col_pn, c->tiles_pn, c->toff_pn, c->ptile, c->off_pn, c->val_pn, c->val32_pn,
                  c->Xr, c->ax1, c->ax2, c->rpart};
   for (void* p : dev)
     if (p) (void)hipFree(p);
@@ -1188,39 +1189,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
       use_cb = spans[spans.size() / 2] > n / 4;
     }
   }
-  std::vector<int32_t> rp_cb, col_cb, tdesc_cb;
-  std::vector<double> val_cb;
-  rks::CbTiles cbt{};
-  if (use_cb) {
-    const int64_t bw = (n + rks::kCb - 1) / rks::kCb;  // columns per block
-    rp_cb.assign((size_t)rks::kCb * (n + 1), 0);
-    for (int64_t r = 0; r < n; ++r)  // count, then exclusive prefix over (block, row)
-      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) rp_cb[(size_t)(col[e] / bw) * (n + 1) + r] += 1;
-    int64_t pos = 0;
-    for (int cb = 0; cb < rks::kCb; ++cb)
-      for (int64_t r = 0; r <= n; ++r) {
-        int32_t& slot = rp_cb[(size_t)cb * (n + 1) + r];
-        const int32_t cnt = (r < n) ? slot : 0;
-        slot = (int32_t)pos;
-        pos += cnt;
-      }
-    col_cb.resize(nnz);
-    val_cb.resize(nnz);
-    std::vector<int32_t> fill(rks::kCb, 0);
-    for (int64_t r = 0; r < n; ++r) {
-      for (int cb = 0; cb < rks::kCb; ++cb) fill[cb] = rp_cb[(size_t)cb * (n + 1) + r];
-      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {  // columns stay increasing inside each block row
-        const int cb = (int)(col[e] / bw);
-        col_cb[fill[cb]] = col[e];
-        val_cb[fill[cb]] = val[e];
-        ++fill[cb];
-      }
-    }
-    for (int cb = 0; cb < rks::kCb; ++cb) {
-      cbt.off[cb] = (int)(tdesc_cb.size() / 4);
-      build_tiles(&rp_cb[(size_t)cb * (n + 1)], tdesc_cb);
-    }
-    cbt.off[rks::kCb] = (int)(tdesc_cb.size() / 4);
+  rks::PanelLayout pl;
+  if (use_cb && !rks::build_panels(n, rp.data(), col.data(), val.data(), pl, why)) {
+    delete c;
+    return fail(nullptr, RKS_EINVAL, why);
   }
   c->vbytes = (o.precision == RKS_PREC_FP64) ? 8 : (o.precision == RKS_PREC_V32 ? 4 : 2);
   c->wbytes = (o.precision == RKS_PREC_FP64) ? 8 : 4;
@@ -1250,12 +1222,13 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nzp * 4);
   dm((void**)&c->tiles, tdesc.size() * 4);
   if (use_cb) {
-    dm((void**)&c->rp_cb, rp_cb.size() * 4);
-    dm((void**)&c->col_cb, (size_t)nzp * 4);
-    dm((void**)&c->val_cb, (size_t)nzp * 8);
-    if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32_cb, (size_t)nzp * 4);
-    dm((void**)&c->tiles_cb, tdesc_cb.size() * 4);
-    dm(&c->P, (size_t)rks::kCb * c->ldu * 8);
+    dm((void**)&c->col_pn, (size_t)nzp * 4);
+    dm((void**)&c->val_pn, (size_t)nzp * 8);
+    if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32_pn, (size_t)nzp * 4);
+    dm((void**)&c->tiles_pn, pl.tiles.size() * 4);
+    dm((void**)&c->toff_pn, pl.toff.size() * 4);
+    dm((void**)&c->off_pn, pl.off.size() * 2);
+    dm((void**)&c->ptile, pl.ptile.size() * 4);
   }
   dm(&c->U_lo, (size_t)c->ldu * (m + 1) * c->vbytes);
   c->U = c->U_lo;
@@ -1276,7 +1249,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->coef, (size_t)(m + 2) * 8);
   dm((void**)&c->z, (size_t)d * 8);
   dm((void**)&c->sr, (size_t)d * 8);
-  dm((void**)&c->zpart, (size_t)rks::kMaxPart * d * 8);
+  dm((void**)&c->zpart, (size_t)std::max<int64_t>(rks::kMaxPart, pl.npanels) * d * 8);
   dm((void**)&c->spart, (size_t)rks::kMaxG * d * 8);
   dm((void**)&c->scal, 8 * 8);
   dm((void**)&c->Yd, (size_t)(m + 1) * (m + 1) * 8);
@@ -1301,14 +1274,16 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   }
   cp(c->tiles, tdesc.data(), tdesc.size() * 4);
   if (use_cb) {
-    cp(c->rp_cb, rp_cb.data(), rp_cb.size() * 4);
-    cp(c->col_cb, col_cb.data(), (size_t)nnz * 4);
-    cp(c->val_cb, val_cb.data(), (size_t)nnz * 8);
-    if (c->val32_cb) {
-      std::vector<float> v32(val_cb.begin(), val_cb.end());
-      cp(c->val32_cb, v32.data(), (size_t)nnz * 4);
+    cp(c->col_pn, pl.col.data(), (size_t)nnz * 4);
+    cp(c->val_pn, pl.val.data(), (size_t)nnz * 8);
+    if (c->val32_pn) {
+      std::vector<float> v32(pl.val.begin(), pl.val.end());
+      cp(c->val32_pn, v32.data(), (size_t)nnz * 4);
     }
-    cp(c->tiles_cb, tdesc_cb.data(), tdesc_cb.size() * 4);
+    cp(c->tiles_pn, pl.tiles.data(), pl.tiles.size() * 4);
+    cp(c->toff_pn, pl.toff.data(), pl.toff.size() * 4);
+    cp(c->off_pn, pl.off.data(), pl.off.size() * 2);
+    cp(c->ptile, pl.ptile.data(), pl.ptile.size() * 4);
   }
   auto zero_pad = [&](void* p, size_t esz) {
     if (rc == RKS_OK && p && hipMemset((char*)p + (size_t)nnz * esz, 0, rks::kCsrPad * esz) != hipSuccess)
@@ -1317,9 +1292,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   zero_pad(c->col, 4);
   zero_pad(c->val, 8);
   zero_pad(c->val32, 4);
-  zero_pad(c->col_cb, 4);
-  zero_pad(c->val_cb, 8);
-  zero_pad(c->val32_cb, 4);
+  zero_pad(c->col_pn, 4);
+  zero_pad(c->val_pn, 8);
+  zero_pad(c->val32_pn, 4);
   if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
   // padding rows of U and w stay zero for the whole life of the context
   if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
@@ -1341,13 +1316,15 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.ntiles = ntiles;
   if (use_cb) {
     e.cb = 1;
-    e.rp_cb = c->rp_cb;
-    e.col_cb = c->col_cb;
-    e.val_cb = c->val_cb;
-    e.val32_cb = c->val32_cb;
-    e.tiles_cb = c->tiles_cb;
-    e.cbt = cbt;
-    e.P = c->P;
+    e.npanels = pl.npanels;
+    e.rows_pp = (int)pl.rows_pp;
+    e.col_pn = c->col_pn;
+    e.val_pn = c->val_pn;
+    e.val32_pn = c->val32_pn;
+    e.tiles_pn = c->tiles_pn;
+    e.toff_pn = c->toff_pn;
+    e.off_pn = c->off_pn;
+    e.ptile = c->ptile;
   }
   e.ldu = c->ldu;
   c->ks = o.method == RKS_METHOD_KS_CGS2;

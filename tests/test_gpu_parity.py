@@ -40,7 +40,37 @@ SMALL = {
     "tridiag-4099": (lambda: tridiag_noisy(4099, "exponential", 5), "sparse", 64),
     # d = 700: per-wave sketch bins of 44.8 KB (SpMV) and 89.6 KB (update) of dynamic LDS
     "powerlaw-5003-d700": (lambda: powerlaw_random(5003, 4), "sparse", 700),
+    # empty rows and rows longer than a tile, some inside a single column block
+    "longrows-9001": (lambda: long_rows(9001, 7), "sparse", 120),
 }
+
+
+def long_rows(n, seed):
+    """Random rows of 1..40 nonzeros (some 8 times longer), every 97th row
+    empty, and every 1000th row 700 nonzeros inside the first eighth of the
+    columns (one column block), or 511 or 510 inside a narrow column range."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for r in range(n):
+        if r % 97 == 5:
+            continue
+        if r % 1000 == 7:
+            c = rng.choice(n // 8, 700, replace=False)
+        elif r % 1000 == 8:
+            c = n // 2 + rng.choice(1100, 511, replace=False)
+        elif r % 1000 == 9:
+            c = 3 * n // 8 + 1 + rng.choice(n // 8 - 11, 510, replace=False)
+        else:
+            c = rng.choice(n, int(rng.integers(1, 41)) * (8 if rng.random() < 1 / 7 else 1), replace=False)
+        rows.append(np.full(len(c), r))
+        cols.append(np.sort(c))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    vals = rng.standard_normal(len(rows))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    A = CSR(n, np.cumsum(rp).astype(np.int32), cols.astype(np.int32), vals, {"kind": "long_rows", "n": n})
+    A.check()
+    return A
 
 
 @pytest.mark.parametrize("case", sorted(SMALL))
@@ -446,6 +476,56 @@ def test_mixed_precision_extension(lib, cuda, prec):
             assert np.linalg.norm(U[:, j] - o.U[:, j]) <= 16 * U32 * np.linalg.norm(o.U[:, j])
         assert np.abs(B[:7, :6] - o.B[:7, :6]).max() <= 1e-6 * nA
         assert np.abs(S[:, :7] - o.S[:, :7]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_precision_extension_column_blocks(lib, cuda, prec):
+    """The low-precision product of the column-blocked layout (binary32
+    values, FP32 or BF16 x, binary32 w) against the oracle with the same
+    storage rounding, on a power-law matrix.  Each stored column up to and
+    including the first one whose stored values differ from the oracle's lies
+    within the binary32 product's reordering noise plus one step of the
+    format (stored_diff), the start vector is identical, and B agrees to
+    binary32 level before that column; the decomposition's identities hold on
+    the GPU's own output."""
+    u_low = LOWP[prec][0]
+    A = powerlaw_random(5003, 4)
+    k, m, d = 8, 30, 120
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
+                       P.rks_opts_default(sketch_kind="sparse", sketch_seed=2, precision=prec,
+                                          spmv_layout="column_blocks"))
+    try:
+        P.rks_arnoldi(ctx, None)
+        B = np.zeros((m + 1, m), order="F")
+        S = np.zeros((d, m + 1), order="F")
+        U = np.zeros((A.n, m + 1), order="F")
+        P.rks_get_state(ctx, B, S, U)
+    finally:
+        P.rks_destroy(ctx)
+    om = sketch_matrix(A.n, d, "sparse", 2)
+    OU = np.asarray(om @ U)
+    assert np.linalg.norm(OU - S) < 1e-12
+    assert np.abs(np.diag(OU.T @ OU - np.eye(m + 1))).max() < 1e-13
+    Sp = sp_of(A)
+    nA = abs(Sp).sum(axis=0).max()
+    rel = np.linalg.norm(Sp @ U[:, :m] - U @ B) / (nA * np.linalg.norm(U[:, :m]))
+    assert rel < 50 * u_low, rel
+    o = RKSOracle(A, k, m, d, "LM", 1e-10, sketch="sparse", sketch_seed=2, start_seed=1, store=prec)
+    o.start(None)
+    o.extend()
+    Aabs = abs(Sp)
+    nnz_row = int(np.diff(A.row_ptr).max())
+    first = m + 1
+    for j in range(m + 1):
+        nd, bad = stored_diff(U[:, j], o.U[:, j], prec, spmv_noise(Aabs, o.U, o.B, j, nnz_row))
+        assert bad == 0, (j, nd, bad)
+        if nd:
+            first = j
+            break
+    assert first >= 1, "the rounded start vector must be identical"
+    c = first - 1
+    if c >= 1:
+        assert np.abs(B[:c + 1, :c] - o.B[:c + 1, :c]).max() <= 1e-7 * nA, first
 
 
 def _exact_lr(N, beta, count):
