@@ -1098,20 +1098,44 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
 }
 
 // O(:, out0 + o) = sum_l U(:, in0 + l) Y(l, o) for o < kout on the FP64
-// matrix cores (v_mfma_f64_16x16x4f64), computed transposed: D = Y^T U^T
-// for a 16-row tile.  Lane (r, k) = (lane % 16, lane / 16) feeds
-// A(r, k) = Y(k0 + k, 16 nt + r) and B(k, c) = U(row0 + c, in0 + k0 + k) for
-// c = lane % 16; the accumulator holds D(lane / 16 + 4 i, lane % 16), i.e.
-// output column 16 nt + lane / 16 + 4 i of row row0 + lane % 16, so one store
-// instruction writes 16 consecutive rows (128 bytes) of each of 4 columns.  The wave reads every input column
-// of its rows before it writes any output, so outputs may overlap inputs
-// (in-place restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
+// matrix cores (v_mfma_f64_16x16x4f64), computed transposed: D = Y^T U^T.
+// A wave owns 16 R consecutive rows; lane (c, k) = (lane % 16, lane / 16)
+// owns rows R c .. R c + R - 1 of them and loads those R values of input
+// column k0 + k with one load (R sizeof(TI) bytes, up to 16).  Each of the R
+// rows feeds its own MFMA: A(c', k) = Y(k0 + k, 16 nt + c') (from LDS, shared
+// by the R products) and B(k, c) = the row's value, so accumulator r holds
+// D(lane / 16 + 4 i, lane % 16) = output column 16 nt + lane / 16 + 4 i of row
+// R (lane % 16) + r, and the lane stores its R rows of a column with one
+// store.  For 2- and 4-byte inputs this trades many narrow loads for fewer
+// wide ones (the vector-memory data path is the busiest unit here, the
+// matrix cores less than half busy).  Loads may read rows
+// past n (every leading dimension passed is a multiple of 128 >= n for the
+// inputs); stores skip rows >= n.  The wave reads every input column of its
+// rows before it writes any output, so outputs may overlap inputs (in-place
+// restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int R>
+struct __attribute__((aligned(sizeof(T) * R))) RowPack {
+  T v[R];
+};
+
+// Rows per lane of the rotation.  FP64 inputs: one (two rows per 16-byte
+// load measured no faster).  FP32 and BF16 inputs: the largest power of two
+// with at most 16 bytes per load and at most 6 accumulator tiles (R NT) per
+// lane; more tiles cost occupancy and measured slower.
+template <typename TI>
+__host__ __device__ constexpr int rot_rows(int nt) {
+  int r = 1;
+  if (sizeof(TI) < 8)
+    while (2 * r * (int)sizeof(TI) <= 16 && 2 * r * nt <= 6) r *= 2;
+  return r;
+}
 
 // YG: Y (minp x 16 NT FP64) does not fit in LDS (more than 160 KB: min and
 // kout both large); each lane then reads its Y entries from global memory
 // (Y is small and stays in L2).
-template <typename TI, typename TO, int NT, bool YG>
+template <typename TI, typename TO, int NT, bool YG, int R>
 __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
                                                 int64_t ldo, int out0, int kout, const double* __restrict__ Y,
                                                 int xsrc, int xdst, double xscale) {
@@ -1128,37 +1152,45 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const int64_t ntile = (n + 15) / 16;
+  const int64_t ntile = (n + 16 * R - 1) / (16 * R);
+  const bool vec_out = ldo % R == 0;
   for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntile; tile += (int64_t)gridDim.x * 4) {
-    const int64_t row = tile * 16 + lr;
-    const bool rin = row < n;
-    double xe = 0.0;
-    if (xsrc >= 0 && lk == 0 && rin) xe = Conv<TI>::ld(U[row + (int64_t)xsrc * ldu]) * xscale;
-    f64x4 acc[NT];
+    const int64_t row = tile * 16 * R + (int64_t)R * lr;  // this lane's first row
+    const bool full = row + R <= n;
+    RowPack<TI, R> xe;
+    if (xsrc >= 0 && lk == 0) xe = *(const RowPack<TI, R>*)(U + row + (int64_t)xsrc * ldu);
+    f64x4 acc[R][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[r][t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     const TI* urow = U + row + (int64_t)in0 * ldu;
     for (int k0 = 0; k0 < minp; k0 += 16) {
-      double a[4];
+      RowPack<TI, R> a[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int kk = k0 + 4 * s + lk;
-        a[s] = (rin && kk < min) ? Conv<TI>::ld(urow[(int64_t)kk * ldu]) : 0.0;
+        if (kk < min) {
+          a[s] = *(const RowPack<TI, R>*)(urow + (int64_t)kk * ldu);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) a[s].v[r] = Conv<TI>::st(0.0);
+        }
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        if (YG) {
-          const int kk = k0 + 4 * s + lk;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const int oc = 16 * t + lr;
-            const double yv = (kk < min && oc < kout) ? Y[kk + (size_t)oc * min] : 0.0;
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, a[s], acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) {
+          double yv;
+          if (YG) {
+            const int kk = k0 + 4 * s + lk, oc = 16 * t + lr;
+            yv = (kk < min && oc < kout) ? Y[kk + (size_t)oc * min] : 0.0;
+          } else {
+            yv = Ys[(size_t)(k0 + 4 * s + lk) * KC + 16 * t + lr];
           }
-        } else {
-          const double* yk = Ys + (size_t)(k0 + 4 * s + lk) * KC + lr;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yk[16 * t], a[s], acc[t], 0, 0, 0);
+          for (int r = 0; r < R; ++r)
+            acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, Conv<TI>::ld(a[s].v[r]), acc[r][t], 0, 0, 0);
         }
       }
     }
@@ -1167,10 +1199,26 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int oc = 16 * t + lk + 4 * i;
-        if (rin && oc < kout) O[row + (int64_t)(out0 + oc) * ldo] = Conv<TO>::st(acc[t][i]);
+        if (oc >= kout) continue;
+        TO* dst = O + row + (int64_t)(out0 + oc) * ldo;
+        if (full && vec_out) {
+          RowPack<TO, R> o;
+#pragma unroll
+          for (int r = 0; r < R; ++r) o.v[r] = Conv<TO>::st(acc[r][t][i]);
+          *(RowPack<TO, R>*)dst = o;
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (row + r < n) dst[r] = Conv<TO>::st(acc[r][t][i]);
+        }
       }
     }
-    if (xsrc >= 0 && lk == 0 && rin) ((TI*)U)[row + (int64_t)xdst * ldu] = Conv<TI>::st(xe);
+    if (xsrc >= 0 && lk == 0) {
+      TI* xd = (TI*)U + row + (int64_t)xdst * ldu;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (row + r < n) xd[r] = Conv<TI>::st(Conv<TI>::ld(xe.v[r]) * xscale);
+    }
   }
 }
 
@@ -1534,17 +1582,18 @@ int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint
 template <typename TI, typename TO, int NT>
 static void rotate_nt(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
                       int kout, const double* Y, int xsrc, int xdst, double xscale) {
-  const int64_t ntile = (e.n + 15) / 16;
+  constexpr int R = rot_rows<TI>(NT);
+  const int64_t ntile = (e.n + 16 * R - 1) / (16 * R);
   const int G = grid_for(ntile, 4, 2048);
   const size_t lds = (size_t)((min + 15) & ~15) * 16 * NT * 8;
   if (lds > kRotLdsMax) {
-    launch_k(e, true, true, k_rotate<TI, TO, NT, true>, dim3(G), dim3(256), 0, e.n, U, ldu, in0, min, O, ldo, out0,
-             kout, Y, xsrc, xdst, xscale);
+    launch_k(e, true, true, k_rotate<TI, TO, NT, true, R>, dim3(G), dim3(256), 0, e.n, U, ldu, in0, min, O, ldo,
+             out0, kout, Y, xsrc, xdst, xscale);
     return;
   }
-  lds_allow((const void*)k_rotate<TI, TO, NT, false>, lds);
-  launch_k(e, true, true, k_rotate<TI, TO, NT, false>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O, ldo, out0,
-           kout, Y, xsrc, xdst, xscale);
+  lds_allow((const void*)k_rotate<TI, TO, NT, false, R>, lds);
+  launch_k(e, true, true, k_rotate<TI, TO, NT, false, R>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O, ldo,
+           out0, kout, Y, xsrc, xdst, xscale);
 }
 
 template <typename TI, typename TO>

@@ -61,6 +61,8 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
 // prec_override's); partials of Omega of the stored value.
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
                 int prec_override, uint32_t c2 = 0, uint32_t tag = 2);
+// O(:, out0 .. out0 + kout) = U(:, in0 .. in0 + min) Y.  ldu must be a multiple of
+// 128 (the kernel reads whole row tiles up to ldu); O's rows >= n are not written.
 void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,
                    int kout, const double* Y, int xsrc, int xdst, double xscale, int out_fp64);
 int launch_resid(const LaunchEnv& e, const double* xa, const double* xb, const double* axa, const double* axb,

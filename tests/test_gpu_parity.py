@@ -219,6 +219,42 @@ def test_rotate_parity_wide(lib, cuda, m, kout):
         P.rks_destroy(ctx)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_rotate_parity_low_precision(lib, cuda, prec):
+    """In-place rotations of an FP32 or BF16 basis (n = 2025: the last row
+    tile is partial for 1, 2 and 4 rows per lane).  The lazy scales are folded
+    into Y, the product runs in FP64 and each output is rounded once to the
+    storage format (BF16 through binary32), so every output value lies within
+    one rounding of the FP64 product of the stored inputs (unit roundoff
+    u_low, relative) plus the FP64 summation noise; columns outside the
+    output range keep their stored values.  kout = 11, 17, 33 and 50 take 4,
+    2, 2 and 1 rows per lane of the 2- and 4-byte kernels."""
+    u_low = LOWP[prec][0]
+    A = convdiff2d(45, (20.0, 10.0))
+    m, d = 60, 120
+    ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, 10, m, d, "LR", 1e-10,
+                       P.rks_opts_default(sketch_kind="sparse", precision=prec))
+    try:
+        P.rks_arnoldi(ctx, None)
+        rng = np.random.default_rng(5)
+        for (in0, mi, out0, ko) in [(0, 40, 0, 11), (3, 37, 3, 17), (0, 61, 5, 33), (2, 58, 0, 50), (0, 61, 0, 33)]:
+            Y = rng.standard_normal((mi, ko))
+            before = np.zeros((A.n, m + 1), order="F")
+            P.rks_get_state(ctx, None, None, before)
+            P.rks_rotate(ctx, in0, mi, out0, ko, Y)
+            after = np.zeros_like(before)
+            P.rks_get_state(ctx, None, None, after)
+            ref = before[:, in0:in0 + mi] @ Y
+            noise = 64 * U64 * (np.abs(before[:, in0:in0 + mi]) @ np.abs(Y))
+            err = np.abs(after[:, out0:out0 + ko] - ref)
+            assert np.all(err <= 1.01 * u_low * np.abs(ref) + noise + 1e-300), (prec, in0, mi, out0, ko)
+            assert np.count_nonzero(err) > 0      # the outputs were written (rounded values differ)
+            untouched = [c for c in range(m + 1) if not (out0 <= c < out0 + ko)]
+            assert np.array_equal(after[:, untouched], before[:, untouched])
+    finally:
+        P.rks_destroy(ctx)
+
+
 CONV = {
     # mildly non-normal operators on which rKS converges within the cap
     "cd2d-40-LR-sparse": (lambda: convdiff2d(40, (2.0, 1.0)), 6, 24, 50, "LR", "sparse", 0),
