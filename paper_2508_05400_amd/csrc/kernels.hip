@@ -814,11 +814,17 @@ union Pack16 {
 // u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
 // basis precision) as the new column; partials of Omega of the stored value.
 // Each thread owns V consecutive rows and streams every basis column once
-// with one 16-byte non-temporal load per column; the coefficients are
-// wave-uniform and come through the scalar path.  Padding rows (>= n, < ldu)
+// with one 16-byte non-temporal load per column, in groups of 8 (8 loads,
+// then their FMAs).  ROLL: a rolling window of 8 instead, where the slot of
+// column l is refilled with column l + 8 as soon as it is consumed.  Measured:
+// the window pays in k_ls_update without its prefetch (one 16-wave workgroup
+// per CU; 393 -> 364 us per launch on the 160^3 operator) and costs 1-8% in
+// the prefetching k_ls_update and in k_update (more waves per CU), which keep
+// the groups.  Either way the columns are added in order, one FMA chain per
+// row, so both give the same bits.  The coefficients are wave-uniform.  Padding rows (>= n, < ldu)
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
-template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false, int PB = 16>
+template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false, int PB = 16, bool ROLL = false>
 __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U, int64_t ldu,
                                             const TW* __restrict__ w, const double* __restrict__ coef,
                                             TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
@@ -862,23 +868,43 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
       l = NPRE;
       use_pre = false;
     }
-    for (; l + 8 <= ncol; l += 8) {
+    if (ROLL) {
       Pack16<TV, PB> p[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q) * ldu));
+      for (int q = 0; q < 8; ++q)
+        if (l + q < ncol) p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q) * ldu));
+      for (; l < ncol; l += 8) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double cq = coef[l + q];
+        for (int q = 0; q < 8; ++q) {
+          if (l + q < ncol) {
+            const Pack16<TV, PB> cur = p[q];
+            if (l + q + 8 < ncol)
+              p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q + 8) * ldu));
+            const double cq = coef[l + q];
 #pragma unroll
-        for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p[q].v[r]);
+            for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(cur.v[r]);
+          }
+        }
       }
-    }
-    for (; l < ncol; ++l) {
-      Pack16<TV, PB> p;
-      p.raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)l * ldu));
-      const double cq = coef[l];
+    } else {
+      for (; l + 8 <= ncol; l += 8) {
+        Pack16<TV, PB> p[8];
 #pragma unroll
-      for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p.v[r]);
+        for (int q = 0; q < 8; ++q) p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q) * ldu));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double cq = coef[l + q];
+#pragma unroll
+          for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p[q].v[r]);
+        }
+      }
+      for (; l < ncol; ++l) {
+        Pack16<TV, PB> p;
+        p.raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)l * ldu));
+        const double cq = coef[l];
+#pragma unroll
+        for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p.v[r]);
+      }
     }
     Pack16<TV, PB> o;
 #pragma unroll
@@ -956,7 +982,7 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
 #pragma unroll
     for (int c = 0; c < (PREW ? WCH : 0); ++c) pre[NP + c] = *(const Raw*)(w + gl * V + c * (PB / sizeof(TW)));
   });
-  update_body<TV, TW, KIND, NP, PREW, PB>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
+  update_body<TV, TW, KIND, NP, PREW, PB, NP == 0>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
