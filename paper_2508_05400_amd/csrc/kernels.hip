@@ -817,11 +817,12 @@ union Pack16 {
 // with one 16-byte non-temporal load per column, in groups of 8 (8 loads,
 // then their FMAs).  ROLL: a rolling window of 8 instead, where the slot of
 // column l is refilled with column l + 8 as soon as it is consumed.  Measured:
-// the window pays in k_ls_update without its prefetch (one 16-wave workgroup
-// per CU; 393 -> 364 us per launch on the 160^3 operator) and costs 1-8% in
-// the prefetching k_ls_update and in k_update (more waves per CU), which keep
-// the groups.  Either way the columns are added in order, one FMA chain per
-// row, so both give the same bits.  The coefficients are wave-uniform.  Padding rows (>= n, < ldu)
+// the window pays in k_ls_update without its prefetch when each thread walks
+// 4 or more packets (one 16-wave workgroup per CU; 393 -> 364 us per launch
+// on the 160^3 operator in FP64, 212 -> 198 us in FP32) and costs 1-8% with 1
+// or 2 packets per thread and in k_update (more waves per CU), which keep the
+// groups.  Either way the columns are added in order, one FMA chain per row,
+// so both give the same bits.  The coefficients are wave-uniform.  Padding rows (>= n, < ldu)
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
 template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false, int PB = 16, bool ROLL = false>
@@ -943,7 +944,7 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
 // latency-bound single workgroup, off the step's critical path.  LDS: the
 // coefficients (kMaxM + 2), then the least-squares scratch, reused afterwards
 // for the per-wave sketch bins.
-template <typename TV, typename TW, int KIND, bool PRE, int PB>
+template <typename TV, typename TW, int KIND, bool PRE, int PB, bool ROLL>
 __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, const double* __restrict__ zraw,
                                                    const double* __restrict__ sraw, double* __restrict__ S,
                                                    double* __restrict__ B, int ldb, double* __restrict__ E,
@@ -982,7 +983,8 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
 #pragma unroll
     for (int c = 0; c < (PREW ? WCH : 0); ++c) pre[NP + c] = *(const Raw*)(w + gl * V + c * (PB / sizeof(TW)));
   });
-  update_body<TV, TW, KIND, NP, PREW, PB, NP == 0>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre, use_pre);
+  update_body<TV, TW, KIND, NP, PREW, PB, ROLL && NP == 0>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre,
+                                                     use_pre);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
@@ -1526,13 +1528,13 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
   return G;
 }
 
-template <typename TV, typename TW, bool PRE, int PB>
+template <typename TV, typename TW, bool PRE, int PB, bool ROLL>
 static void ls_update_t(const LaunchEnv& e, dim3 grid, size_t lds, int t, int pending, const double* zraw,
                         const double* sraw, double* S, double* B, int ldb, double* E, double* cs, double* coef,
                         double* scal, int* flags, double bd_rel, int64_t npk, const void* U, int64_t ldu,
                         const void* w, void* unew, double* spart) {
-  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE, PB>, lds);
-                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE, PB>, grid, dim3(1024), lds, t,
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE, PB, ROLL>, lds);
+                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE, PB, ROLL>, grid, dim3(1024), lds, t,
                              e.sp.d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
                              (const TV*)U, ldu, (const TW*)w, (TV*)unew, spart, e.sp));
 }
@@ -1557,11 +1559,17 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
   const size_t lds = ((size_t)kMaxM + 2 + (ls_work > bins ? ls_work : bins)) * 8;
   // basis loads during the least squares where its own loads all come first
   const bool pre = e.sp.d <= kRC * kLsPreS && t + 1 <= 64 && t + 1 >= kLsPreU;
-#define RKS_LSU_PB(TV, TW, PB)                                                                                       \
-  (pre ? ls_update_t<TV, TW, true, PB>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, \
-                                       bd_rel, npk, U, ldu, w, unew, spart)                                         \
-       : ls_update_t<TV, TW, false, PB>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal,     \
-                                        flags, bd_rel, npk, U, ldu, w, unew, spart))
+  // rolling window of column loads (update_body) when each thread walks at
+  // least 4 packets: measured faster there (FP64 and FP32 on the 160^3
+  // operator), slower with 1 or 2 packets per thread
+  const bool roll = !pre && passes >= 4;
+#define RKS_LSU_PB(TV, TW, PB)                                                                                        \
+  (pre ? ls_update_t<TV, TW, true, PB, false>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal,  \
+                                              flags, bd_rel, npk, U, ldu, w, unew, spart)                            \
+   : roll ? ls_update_t<TV, TW, false, PB, true>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef,    \
+                                                 scal, flags, bd_rel, npk, U, ldu, w, unew, spart)                   \
+          : ls_update_t<TV, TW, false, PB, false>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef,   \
+                                                  scal, flags, bd_rel, npk, U, ldu, w, unew, spart))
 #define RKS_LSU(TV, TW) (PBy == 8 ? RKS_LSU_PB(TV, TW, 8) : RKS_LSU_PB(TV, TW, 16))
   if (e.prec == 0) RKS_LSU(double, double);
   else if (e.prec == 1) RKS_LSU(float, float);
