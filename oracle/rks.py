@@ -64,10 +64,16 @@ def round_storage(x, store):
     binary32 and then to bfloat16 (binary32's sign and exponent with an 8-bit
     significand).  The bfloat16 step is written out from the definition: the
     two neighbouring bfloat16 values bracket the binary32 value, the nearer
-    one is taken, and a tie goes to the one whose last significand bit is 0."""
+    one is taken, and a tie goes to the one whose last significand bit is 0.
+    'fp32+bf16' stores a pair: hi, the binary32 rounding, and lo, the bfloat16
+    rounding (as above) of the remainder x - hi, which FP64 holds exactly; the
+    stored value is hi + lo, within 2^-32 |x| of x."""
     x = np.asarray(x, dtype=np.float64)
     if store == "fp64":
         return x.copy()
+    if store == "fp32+bf16":
+        hi = round_storage(x, "fp32")
+        return hi + round_storage(x - hi, "bf16")
     x32 = x.astype(np.float32)
     if store == "fp32":
         return x32.astype(np.float64)
@@ -184,7 +190,8 @@ class RKSOracle:
         # copies of A's values and its result is rounded to binary32; the
         # stored column is the unnormalised remainder rounded to the format,
         # its scale 1/beta is kept in FP64, and the sketch is taken of the
-        # stored value)
+        # stored value); 'fp32+bf16' stores the remainder as such a pair and
+        # forms the product with A in FP64 from the stored value
         self.store = store
         if store != "fp64":
             self.A_low = sp.csr_matrix((round_storage(self.A.data, "fp32"), self.A.indices, self.A.indptr),
@@ -240,9 +247,12 @@ class RKSOracle:
     def apply(self, j):
         """A u_j.  With a low-precision basis, u_j = c_j v_j is a stored
         vector v_j times its FP64 scale c_j: the product A v_j is formed from
-        binary32 copies of A's values and rounded to binary32, then scaled."""
+        binary32 copies of A's values and rounded to binary32, then scaled
+        ('fp32+bf16': in FP64 from A's values and the stored value)."""
         if self.store == "fp64":
             return self.A @ self.U[:, j]
+        if self.store == "fp32+bf16":
+            return self.cs[j] * (self.A @ self.stored[:, j])
         w = round_storage(self.A_low @ self.stored[:, j], "fp32")
         return self.cs[j] * w
 

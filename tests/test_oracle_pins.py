@@ -613,6 +613,76 @@ def test_low_precision_extension_is_a_rounded_decomposition(store, u_low):
     assert 1e-3 * u_low < rel < 10 * u_low
 
 
+def test_round_storage_fp32_bf16_pair_brute_force():
+    """The FP32 + BF16 pair: hi is the binary32 rounding of x, lo the
+    bfloat16 rounding (through binary32, found by a search over every
+    bfloat16 value, ties to the even bit pattern) of the remainder x - hi,
+    which FP64 holds exactly; the stored value hi + lo is within 2^-32 |x|
+    of x (unit roundoff 2^-24 of hi times 2^-8 of lo)."""
+    from oracle.rks import round_storage
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(20000) * 10.0 ** rng.uniform(-25, 25, 20000)
+    tie = 1 + 2.0**-30 * (1 + 2.0**-8)        # remainder at a bfloat16 midpoint: lo rounds to 2^-30
+    x = np.concatenate([x, [tie, 3.0, 0.0, 1 + 2.0**-23]])
+    hi = x.astype(np.float32).astype(np.float64)
+    r = x - hi
+    assert np.array_equal(r + hi, x)           # the remainder is exact
+    grid, pat = _bf16_grid()
+    r32 = r.astype(np.float32).astype(np.float64)
+    a = np.abs(r32)
+    i = np.clip(np.searchsorted(grid, a), 1, len(grid) - 1)
+    lo_, hi_ = grid[i - 1], grid[i]
+    pick_hi = (hi_ - a < a - lo_) | ((hi_ - a == a - lo_) & (pat[i] % 2 == 0))
+    lo = np.where(pick_hi, hi_, lo_) * np.sign(r32)
+    got = round_storage(x, "fp32+bf16")
+    assert np.array_equal(got, hi + lo)
+    assert np.all(np.abs(got - x) <= 2.0**-32 * np.abs(x))
+    assert got[-4] == 1 + 2.0**-30 and got[-3] == 3.0 and got[-2] == 0.0 and got[-1] == 1 + 2.0**-23
+
+
+def test_fp32_bf16_extension_is_a_rounded_decomposition():
+    """The FP32 + BF16 basis in the oracle: the product with A is FP64 (from
+    the stored value), the stored remainder carries the pair rounding, and
+    the sketch is that of the stored value.  The Krylov relation then misses,
+    entry by entry, only the rounding of the stored remainder (unit roundoff
+    2^-32) and FP64 noise: four orders of magnitude closer than binary32
+    storage, and still not FP64."""
+    A = convdiff2d(30, (20.0, 10.0))
+    k, m, d = 5, 16, 48
+    u_low = 2.0**-32
+    o = RKSOracle(A, k, m, d, "LR", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1, store="fp32+bf16")
+    o.start()
+    o.extend()
+    assert np.array_equal(o.U[:, :m + 1], o.stored[:, :m + 1] * o.cs[None, :m + 1])
+    assert np.linalg.norm(np.asarray(o.Om @ o.U) - o.S) < 1e-14
+    Ad = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    Aabs = abs(Ad)
+    for j in range(m):
+        res = Ad @ o.U[:, j] - o.U[:, :j + 2] @ o.B[:j + 2, j]
+        r = o.U[:, :j + 2] @ o.B[:j + 2, j]
+        bound = (u_low * np.abs(r) + np.abs(o.U[:, :j + 1]) @ np.abs(o.B[:j + 1, j]) * u_low
+                 + 1e-14 * (Aabs @ np.abs(o.U[:, j])))
+        assert np.all(np.abs(res) <= bound), (j, np.max(np.abs(res) / bound))
+    rel = np.linalg.norm(Ad @ o.U[:, :m] - o.U @ o.B) / (o.normA1 * np.linalg.norm(o.U[:, :m]))
+    assert 1e-3 * u_low < rel < 10 * u_low
+
+
+def test_fp32_bf16_storage_reaches_below_1e9():
+    """The FP32 + BF16 basis has its residual floor near its own unit
+    roundoff 2^-32 (2.3e-10): on the small 2D workload it converges to
+    residual ~1e-10 in FP64's number of restarts, where binary32 storage
+    stalls near 1e-7.  So a solve to residual 1e-8 needs no FP64 phase."""
+    A = convdiff2d(30, (2.0, 1.0))
+    kw = dict(sketch="sparse", sketch_seed=3, start_seed=1, max_restarts=40)
+    r64 = rks(A, 4, 20, 50, "LR", 1e-12, **kw)
+    rpr = rks(A, 4, 20, 50, "LR", 1e-12, store="fp32+bf16", **kw)
+    r32 = rks(A, 4, 20, 50, "LR", 1e-12, store="fp32", **kw)
+    assert rpr.converged and 2.0**-36 < rpr.resid.max() < 1e-9
+    assert r32.resid.max() > 1e-8
+    assert abs(rpr.restarts - r64.restarts) <= 2
+    assert np.abs(rpr.lam - r64.lam).max() <= 1e-8 * np.abs(r64.lam).max()
+
+
 def test_store_fp64_is_the_plain_oracle():
     A = convdiff2d(20, (6.0, 3.0))
     a = rks(A, 4, 16, 40, "LR", 1e-10, sketch="sparse", sketch_seed=1, store="fp64")
