@@ -54,8 +54,14 @@ typedef enum { RKS_SKETCH_GAUSS = 0, RKS_SKETCH_SPARSE = 1 } rks_sketch_kind;
 
 /* Storage precision of the n-dimensional basis U (mixed precision is the
  * paper's future-work direction of Section 6; sketch-space quantities, the
- * Rayleigh quotient and all small dense steps stay FP64). */
-typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2 } rks_precision;
+ * Rayleigh quotient and all small dense steps stay FP64).  V32 and VBF16
+ * store binary32 or bfloat16 columns and multiply them with binary32 copies
+ * of A's values.  V32_BF16 stores each element as a pair, 6 bytes: hi, its
+ * binary32 rounding, and lo, the bfloat16 rounding of the remainder (both to
+ * nearest even), with value hi + lo within 2^-32 of the element relative to
+ * it; arithmetic stays FP64, the products with A read an FP64 copy of the
+ * column last written (n doubles more device memory). */
+typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2, RKS_PREC_V32_BF16 = 3 } rks_precision;
 
 /* SpMV layout.  ROWS: wave tiles of consecutive rows.  COLUMN_BLOCKS: for
  * rows that gather x from everywhere, with x larger than an XCD's L2: the
@@ -115,7 +121,7 @@ typedef struct {
                             estimates predict it; after a failed check, when they
                             do so scaled by the true/estimated ratio seen there,
                             or have halved); default 0 = off */
-  int32_t refine;        /* low-precision basis only: 1 = after the low-precision
+  int32_t refine;        /* V32 and VBF16 bases only: 1 = after the low-precision
                             phase reaches refine_tol, continue in FP64 from a
                             combination of its Schur vectors; default 1 */
   double refine_tol;     /* verified-residual target of the low-precision phase

@@ -805,14 +805,56 @@ template <>
 struct RawOf<8> {
   typedef u32x2 type;
 };
+template <>
+struct RawOf<4> {
+  typedef unsigned int type;
+};
 template <typename T, int PB = 16>
 union Pack16 {
   typename RawOf<PB>::type raw;
   T v[PB / sizeof(T)];
 };
 
+// The FP32 + BF16 pair of x: hi = x rounded to binary32, lo = the remainder
+// x - hi (exact in FP64) rounded to bfloat16 through binary32, both to
+// nearest even; the stored value hi + lo is within 2^-32 |x| of x.
+__device__ __forceinline__ void split_pair(double x, float& hi, bf16_t& lo) {
+  hi = (float)x;
+  lo = Conv<bf16_t>::st(x - (double)hi);
+}
+
+// One packet of a basis column: PB bytes of TV values and, for the FP32 + BF16
+// pair basis (SPLIT, TV = float), the bfloat16 remainders of the same rows
+// from the second array (PB / 2 bytes); the value of a row is hi + lo.
+template <typename TV, int PB, bool SPLIT>
+struct ColPk {
+  typedef typename RawOf<PB>::type Raw;
+  typedef typename RawOf<SPLIT ? PB / 2 : 4>::type RawL;
+  Pack16<TV, PB> h;
+  union {
+    RawL raw;
+    bf16_t v[SPLIT ? PB / 4 : 2];
+  } l;
+  __device__ __forceinline__ void load(const TV* hi, const bf16_t* lo, int64_t off) {
+    h.raw = __builtin_nontemporal_load((const Raw*)(hi + off));
+    if constexpr (SPLIT) l.raw = __builtin_nontemporal_load((const RawL*)(lo + off));
+  }
+  __device__ __forceinline__ double val(int r) const {
+    if constexpr (SPLIT) return (double)h.v[r] + Conv<bf16_t>::ld(l.v[r]);
+    else return Conv<TV>::ld(h.v[r]);
+  }
+  // stores a (rounded to the basis format) as row r of the packet
+  __device__ __forceinline__ void set(int r, double a) {
+    if constexpr (SPLIT) split_pair(a, h.v[r], l.v[r]);
+    else h.v[r] = Conv<TV>::st(a);
+  }
+};
+
 // u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
 // basis precision) as the new column; partials of Omega of the stored value.
+// SPLIT: the basis is the FP32 + BF16 pair (U, Ulo; the new column to unew,
+// unew_lo), and the stored value of the new column also goes to xout in FP64
+// (the next product with A reads it there).
 // Each thread owns V consecutive rows and streams every basis column once
 // with one 16-byte non-temporal load per column, in groups of 8 (8 loads,
 // then their FMAs).  ROLL: a rolling window of 8 instead, where the slot of
@@ -825,12 +867,14 @@ union Pack16 {
 // so both give the same bits.  The coefficients are wave-uniform.  Padding rows (>= n, < ldu)
 // are zero in U and w, so packets may run past n; they stay zero and are
 // left out of the sketch.
-template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false, int PB = 16, bool ROLL = false>
+template <typename TV, typename TW, int KIND, int NPRE = 0, bool PREW = false, int PB = 16, bool ROLL = false,
+          bool SPLIT = false>
 __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, const TV* __restrict__ U, int64_t ldu,
                                             const TW* __restrict__ w, const double* __restrict__ coef,
                                             TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
                                             double* bins, const typename RawOf<PB>::type* pre = nullptr,
-                                            bool use_pre = false) {
+                                            bool use_pre = false, const bf16_t* __restrict__ Ulo = nullptr,
+                                            bf16_t* __restrict__ unew_lo = nullptr, double* __restrict__ xout = nullptr) {
   // pre: NPRE leading basis columns, then (PREW) the w chunks, of the first packet
   typedef typename RawOf<PB>::type Raw;
   constexpr int V = PB / sizeof(TV);
@@ -856,6 +900,7 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
         for (int r = 0; r < WV; ++r) a[c * WV + r] = ws * (double)wp[c].v[r];
     }
     const TV* col0 = U + i0;
+    const bf16_t* col0l = SPLIT ? Ulo + i0 : nullptr;
     int l = 0;
     if (NPRE > 0 && use_pre) {  // the first packet's leading columns, loaded before the least squares
 #pragma unroll
@@ -870,51 +915,57 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
       use_pre = false;
     }
     if (ROLL) {
-      Pack16<TV, PB> p[8];
+      ColPk<TV, PB, SPLIT> p[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (l + q < ncol) p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q) * ldu));
+        if (l + q < ncol) p[q].load(col0, col0l, (int64_t)(l + q) * ldu);
       for (; l < ncol; l += 8) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           if (l + q < ncol) {
-            const Pack16<TV, PB> cur = p[q];
-            if (l + q + 8 < ncol)
-              p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q + 8) * ldu));
+            const ColPk<TV, PB, SPLIT> cur = p[q];
+            if (l + q + 8 < ncol) p[q].load(col0, col0l, (int64_t)(l + q + 8) * ldu);
             const double cq = coef[l + q];
 #pragma unroll
-            for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(cur.v[r]);
+            for (int r = 0; r < V; ++r) a[r] -= cq * cur.val(r);
           }
         }
       }
     } else {
       for (; l + 8 <= ncol; l += 8) {
-        Pack16<TV, PB> p[8];
+        ColPk<TV, PB, SPLIT> p[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) p[q].raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)(l + q) * ldu));
+        for (int q = 0; q < 8; ++q) p[q].load(col0, col0l, (int64_t)(l + q) * ldu);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const double cq = coef[l + q];
 #pragma unroll
-          for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p[q].v[r]);
+          for (int r = 0; r < V; ++r) a[r] -= cq * p[q].val(r);
         }
       }
       for (; l < ncol; ++l) {
-        Pack16<TV, PB> p;
-        p.raw = __builtin_nontemporal_load((const Raw*)(col0 + (int64_t)l * ldu));
+        ColPk<TV, PB, SPLIT> p;
+        p.load(col0, col0l, (int64_t)l * ldu);
         const double cq = coef[l];
 #pragma unroll
-        for (int r = 0; r < V; ++r) a[r] -= cq * Conv<TV>::ld(p.v[r]);
+        for (int r = 0; r < V; ++r) a[r] -= cq * p.val(r);
       }
     }
-    Pack16<TV, PB> o;
+    ColPk<TV, PB, SPLIT> o;
 #pragma unroll
-    for (int r = 0; r < V; ++r) o.v[r] = Conv<TV>::st(a[r]);
-    __builtin_nontemporal_store(o.raw, (Raw*)(unew + i0));
+    for (int r = 0; r < V; ++r) o.set(r, a[r]);
+    __builtin_nontemporal_store(o.h.raw, (Raw*)(unew + i0));
+    if constexpr (SPLIT)
+      __builtin_nontemporal_store(o.l.raw, (typename ColPk<TV, PB, SPLIT>::RawL*)(unew_lo + i0));
+    if constexpr (SPLIT) {
+      typedef double d2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int c = 0; c < V / 2; ++c) *(d2v*)(xout + i0 + 2 * c) = (d2v){o.val(2 * c), o.val(2 * c + 1)};
+    }
 #pragma unroll
     for (int r = 0; r < V; ++r) {
+      const double v = o.val(r);
       if (i0 + r >= n) continue;
-      const double v = Conv<TV>::ld(o.v[r]);
       if (KIND == 2) nrm += v * v;
       else sketch_add<KIND>(wb, (uint64_t)(i0 + r), v, sp);
     }
@@ -944,7 +995,7 @@ __global__ __launch_bounds__(1024) void k_update(int64_t n, int64_t npk, int nco
 // latency-bound single workgroup, off the step's critical path.  LDS: the
 // coefficients (kMaxM + 2), then the least-squares scratch, reused afterwards
 // for the per-wave sketch bins.
-template <typename TV, typename TW, int KIND, bool PRE, int PB, bool ROLL>
+template <typename TV, typename TW, int KIND, bool PRE, int PB, bool ROLL, bool SPLIT>
 __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, const double* __restrict__ zraw,
                                                    const double* __restrict__ sraw, double* __restrict__ S,
                                                    double* __restrict__ B, int ldb, double* __restrict__ E,
@@ -952,7 +1003,9 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
                                                    double* __restrict__ scal, int* __restrict__ flags, double bd_rel,
                                                    int64_t n, int64_t npk, const TV* __restrict__ U, int64_t ldu,
                                                    const TW* __restrict__ w, TV* __restrict__ unew,
-                                                   double* __restrict__ spart, SketchP sp) {
+                                                   double* __restrict__ spart, SketchP sp,
+                                                   const bf16_t* __restrict__ Ulo, bf16_t* __restrict__ unew_lo,
+                                                   double* __restrict__ xout) {
   extern __shared__ double smem[];
   double* hc = smem;
   double* work = smem + kMaxM + 2;
@@ -964,7 +1017,7 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
   // for BF16, whose eight rows per packet leave no registers for it)
   typedef typename RawOf<PB>::type Raw;
   constexpr int V = PB / sizeof(TV);
-  constexpr int NP = PRE && sizeof(TV) >= 4 ? kLsPreU : 0;
+  constexpr int NP = PRE && sizeof(TV) >= 4 && !SPLIT ? kLsPreU : 0;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool use_pre = NP > 0 && g0 < npk && t + 1 >= NP;
   constexpr int WCH = (V * (int)sizeof(TW)) / PB;  // PB-byte chunks of w per packet
@@ -983,8 +1036,8 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
 #pragma unroll
     for (int c = 0; c < (PREW ? WCH : 0); ++c) pre[NP + c] = *(const Raw*)(w + gl * V + c * (PB / sizeof(TW)));
   });
-  update_body<TV, TW, KIND, NP, PREW, PB, ROLL && NP == 0>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp, work, pre,
-                                                     use_pre);
+  update_body<TV, TW, KIND, NP, PREW, PB, ROLL && NP == 0, SPLIT>(n, npk, t + 1, U, ldu, w, hc, unew, spart, sp,
+                                                              work, pre, use_pre, Ulo, unew_lo, xout);
 }
 
 // Sums over the wave of eight values per lane: lane L returns the total of
@@ -1092,10 +1145,13 @@ __global__ void k_ks_finalize(int t, const double* __restrict__ h, const double*
 // First column: u0 (device FP64) or a seeded N(0,1) vector (Philox counter
 // (i, c2, tag): tag 2 the start vector, tag 3 the replacement after a
 // breakdown), stored in TV when `store`; partials of Omega of the stored value.
-template <typename TV, int KIND>
+// SPLIT (TV = float): stored as the FP32 + BF16 pair (u, ulo), the stored
+// value also to xout in FP64.
+template <typename TV, int KIND, bool SPLIT = false>
 __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
                                               uint32_t s0, uint32_t s1, uint32_t c2, uint32_t tag,
-                                              double* __restrict__ spart, SketchP sp, int store) {
+                                              double* __restrict__ spart, SketchP sp, int store,
+                                              bf16_t* __restrict__ ulo = nullptr, double* __restrict__ xout = nullptr) {
   extern __shared__ double bins[];  // 8 waves x d (none for KIND 3)
   if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
@@ -1110,9 +1166,22 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
       double g1;
       gauss_pair((uint64_t)i, c2, tag, s0, s1, v, g1);
     }
-    const TV st = Conv<TV>::st(v);
-    if (store) u[i] = st;
-    const double vs = Conv<TV>::ld(st);
+    double vs;
+    if constexpr (SPLIT) {
+      float hi;
+      bf16_t lo;
+      split_pair(v, hi, lo);
+      vs = (double)hi + Conv<bf16_t>::ld(lo);
+      if (store) {
+        u[i] = hi;
+        ulo[i] = lo;
+        xout[i] = vs;
+      }
+    } else {
+      const TV st = Conv<TV>::st(v);
+      if (store) u[i] = st;
+      vs = Conv<TV>::ld(st);
+    }
     if (KIND == 2) nrm += vs * vs;
     else sketch_add<KIND>(wb, (uint64_t)i, vs, sp);
   }
@@ -1141,6 +1210,9 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
 // inputs); stores skip rows >= n.  The wave reads every input column of its
 // rows before it writes any output, so outputs may overlap inputs (in-place
 // restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
+// SPLIT: the input is the FP32 + BF16 pair basis (U, Ulo; TI = float), and
+// an FP32 output (TO = float) is stored as pairs too (O, Olo); the column
+// U(:, xdst) is then also written to xcur in FP64.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T, int R>
@@ -1148,13 +1220,16 @@ struct __attribute__((aligned(sizeof(T) * R))) RowPack {
   T v[R];
 };
 
-// Rows per lane of the rotation.  FP64 inputs: one (two rows per 16-byte
-// load measured no faster).  FP32 and BF16 inputs: the largest power of two
-// with at most 16 bytes per load and at most 6 accumulator tiles (R NT) per
-// lane; more tiles cost occupancy and measured slower.
+// Rows per lane of the rotation.  FP64 inputs: two (one 16-byte load) up to
+// 3 column tiles, else one (measured 5% faster on the 160^3 restart and 10%
+// on the 1000^2 one).  FP32 and BF16 inputs: the largest power of two with at
+// most 16 bytes per load and at most 6 accumulator tiles (R NT) per lane;
+// more tiles cost occupancy and measured slower (the pair basis, whose FP32
+// part sets R, included: 4 rows at 3 tiles measured 5% slower).
 template <typename TI>
 __host__ __device__ constexpr int rot_rows(int nt) {
   int r = 1;
+  if (sizeof(TI) == 8 && nt <= 3) return 2;
   if (sizeof(TI) < 8)
     while (2 * r * (int)sizeof(TI) <= 16 && 2 * r * nt <= 6) r *= 2;
   return r;
@@ -1162,13 +1237,22 @@ __host__ __device__ constexpr int rot_rows(int nt) {
 
 // YG: Y (minp x 16 NT FP64) does not fit in LDS (more than 160 KB: min and
 // kout both large); each lane then reads its Y entries from global memory
-// (Y is small and stays in L2).
-template <typename TI, typename TO, int NT, bool YG, int R>
-__global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
+// (Y is small and stays in L2).  Occupancy: asked for at least 3 waves per
+// SIMD, the compiler keeps the accumulators in VGPRs instead of AGPRs and
+// reaches 4 or 5 waves for up to 5 column tiles (2 without the request;
+// measured 5% faster for the FP64 basis and 30% for the pair basis on the
+// 160^3 restart); with Y from global memory (more address registers), and
+// for the pair basis with 7 or 8 tiles, it would spill, so those get no
+// request.
+template <typename TI, typename TO, int NT, bool YG, int R, bool SPLIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLIT && NT >= 7) ? 1 : 3))) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
                                                 int64_t ldo, int out0, int kout, const double* __restrict__ Y,
-                                                int xsrc, int xdst, double xscale) {
+                                                int xsrc, int xdst, double xscale, const bf16_t* Ulo, bf16_t* Olo,
+                                                double* __restrict__ xcur) {
   extern __shared__ double Ys[];  // minp x (16 NT), zero padded (unused when YG)
   constexpr int KC = 16 * NT;
+  constexpr bool SO = SPLIT && sizeof(TO) == 4;  // pair output
+  constexpr int RL = SPLIT ? R : 1;              // bfloat16 parts per lane
   const int minp = (min + 15) & ~15;
   if (!YG) {
     for (int idx = threadIdx.x; idx < minp * KC; idx += blockDim.x) {
@@ -1186,23 +1270,32 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
     const int64_t row = tile * 16 * R + (int64_t)R * lr;  // this lane's first row
     const bool full = row + R <= n;
     RowPack<TI, R> xe;
-    if (xsrc >= 0 && lk == 0) xe = *(const RowPack<TI, R>*)(U + row + (int64_t)xsrc * ldu);
+    RowPack<bf16_t, RL> xel;
+    if (xsrc >= 0 && lk == 0) {
+      xe = *(const RowPack<TI, R>*)(U + row + (int64_t)xsrc * ldu);
+      if constexpr (SPLIT) xel = *(const RowPack<bf16_t, R>*)(Ulo + row + (int64_t)xsrc * ldu);
+    }
     f64x4 acc[R][NT];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[r][t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     const TI* urow = U + row + (int64_t)in0 * ldu;
+    const bf16_t* urowl = SPLIT ? Ulo + row + (int64_t)in0 * ldu : nullptr;
     for (int k0 = 0; k0 < minp; k0 += 16) {
       RowPack<TI, R> a[4];
+      RowPack<bf16_t, RL> al[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int kk = k0 + 4 * s + lk;
         if (kk < min) {
           a[s] = *(const RowPack<TI, R>*)(urow + (int64_t)kk * ldu);
+          if constexpr (SPLIT) al[s] = *(const RowPack<bf16_t, R>*)(urowl + (int64_t)kk * ldu);
         } else {
 #pragma unroll
           for (int r = 0; r < R; ++r) a[s].v[r] = Conv<TI>::st(0.0);
+#pragma unroll
+          for (int r = 0; r < RL; ++r) al[s].v[r].b = 0;
         }
       }
 #pragma unroll
@@ -1217,8 +1310,11 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
             yv = Ys[(size_t)(k0 + 4 * s + lk) * KC + 16 * t + lr];
           }
 #pragma unroll
-          for (int r = 0; r < R; ++r)
-            acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, Conv<TI>::ld(a[s].v[r]), acc[r][t], 0, 0, 0);
+          for (int r = 0; r < R; ++r) {
+            double uv = Conv<TI>::ld(a[s].v[r]);
+            if constexpr (SPLIT) uv += Conv<bf16_t>::ld(al[s].v[r]);
+            acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, uv, acc[r][t], 0, 0, 0);
+          }
         }
       }
     }
@@ -1229,7 +1325,24 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
         const int oc = 16 * t + lk + 4 * i;
         if (oc >= kout) continue;
         TO* dst = O + row + (int64_t)(out0 + oc) * ldo;
-        if (full && vec_out) {
+        if constexpr (SO) {
+          bf16_t* dstl = Olo + row + (int64_t)(out0 + oc) * ldo;
+          RowPack<float, R> o;
+          RowPack<bf16_t, R> ol;
+#pragma unroll
+          for (int r = 0; r < R; ++r) split_pair(acc[r][t][i], o.v[r], ol.v[r]);
+          if (full && vec_out) {
+            *(RowPack<float, R>*)dst = o;
+            *(RowPack<bf16_t, R>*)dstl = ol;
+          } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              if (row + r < n) {
+                dst[r] = o.v[r];
+                dstl[r] = ol.v[r];
+              }
+          }
+        } else if (full && vec_out) {
           RowPack<TO, R> o;
 #pragma unroll
           for (int r = 0; r < R; ++r) o.v[r] = Conv<TO>::st(acc[r][t][i]);
@@ -1244,8 +1357,19 @@ __global__ __launch_bounds__(256) void k_rotate(int64_t n, const TI* U, int64_t 
     if (xsrc >= 0 && lk == 0) {
       TI* xd = (TI*)U + row + (int64_t)xdst * ldu;
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (row + r < n) xd[r] = Conv<TI>::st(Conv<TI>::ld(xe.v[r]) * xscale);
+      for (int r = 0; r < R; ++r) {
+        if (row + r >= n) continue;
+        if constexpr (SPLIT) {
+          float hi;
+          bf16_t lo;
+          split_pair(((double)xe.v[r] + Conv<bf16_t>::ld(xel.v[r])) * xscale, hi, lo);
+          xd[r] = hi;
+          ((bf16_t*)Ulo)[row + r + (int64_t)xdst * ldu] = lo;
+          xcur[row + r] = (double)hi + Conv<bf16_t>::ld(lo);
+        } else {
+          xd[r] = Conv<TI>::st(Conv<TI>::ld(xe.v[r]) * xscale);
+        }
+      }
     }
   }
 }
@@ -1447,7 +1571,8 @@ static int spmv_panel_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, d
 }
 
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
-  const int prec = prec_override >= 0 ? prec_override : e.prec;
+  int prec = prec_override >= 0 ? prec_override : e.prec;
+  if (prec == 3) prec = 0;  // the pair basis multiplies FP64 copies of its columns
   if (e.cb) {
     if (prec == 0) return spmv_panel_t<double, double, double>(e, e.val_pn, (const double*)x, (double*)w, zpart, do_sketch);
     if (prec == 1) return spmv_panel_t<float, float, float>(e, e.val32_pn, (const float*)x, (float*)w, zpart, do_sketch);
@@ -1528,15 +1653,18 @@ int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, cons
   return G;
 }
 
-template <typename TV, typename TW, bool PRE, int PB, bool ROLL>
+template <typename TV, typename TW, bool PRE, int PB, bool ROLL, bool SPLIT>
 static void ls_update_t(const LaunchEnv& e, dim3 grid, size_t lds, int t, int pending, const double* zraw,
                         const double* sraw, double* S, double* B, int ldb, double* E, double* cs, double* coef,
                         double* scal, int* flags, double bd_rel, int64_t npk, const void* U, int64_t ldu,
                         const void* w, void* unew, double* spart) {
-  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE, PB, ROLL>, lds);
-                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE, PB, ROLL>, grid, dim3(1024), lds, t,
-                             e.sp.d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n, npk,
-                             (const TV*)U, ldu, (const TW*)w, (TV*)unew, spart, e.sp));
+  const bf16_t* Ulo = SPLIT ? e.lo_of(U) : nullptr;
+  bf16_t* unew_lo = SPLIT ? e.lo_of(unew) : nullptr;
+  double* xout = SPLIT ? e.xcur : nullptr;
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE, PB, ROLL, SPLIT>, lds);
+                    launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE, PB, ROLL, SPLIT>, grid, dim3(1024),
+                             lds, t, e.sp.d, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal, flags, bd_rel, e.n,
+                             npk, (const TV*)U, ldu, (const TW*)w, (TV*)unew, spart, e.sp, Ulo, unew_lo, xout));
 }
 
 int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw, const double* sraw, double* S,
@@ -1562,24 +1690,28 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
   // rolling window of column loads (update_body) when each thread walks at
   // least 4 packets: measured faster there (FP64 and FP32 on the 160^3
   // operator), slower with 1 or 2 packets per thread
+  // (the pair basis takes no prefetch: its loads of two arrays leave no
+  // registers for it)
   const bool roll = !pre && passes >= 4;
-#define RKS_LSU_PB(TV, TW, PB)                                                                                        \
-  (pre ? ls_update_t<TV, TW, true, PB, false>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, scal,  \
-                                              flags, bd_rel, npk, U, ldu, w, unew, spart)                            \
-   : roll ? ls_update_t<TV, TW, false, PB, true>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef,    \
-                                                 scal, flags, bd_rel, npk, U, ldu, w, unew, spart)                   \
-          : ls_update_t<TV, TW, false, PB, false>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef,   \
-                                                  scal, flags, bd_rel, npk, U, ldu, w, unew, spart))
-#define RKS_LSU(TV, TW) (PBy == 8 ? RKS_LSU_PB(TV, TW, 8) : RKS_LSU_PB(TV, TW, 16))
-  if (e.prec == 0) RKS_LSU(double, double);
-  else if (e.prec == 1) RKS_LSU(float, float);
-  else RKS_LSU(bf16_t, float);
+#define RKS_LSU_PB(TV, TW, PB, SP)                                                                                    \
+  (pre && !SP ? ls_update_t<TV, TW, true, PB, false, SP>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs,   \
+                                                         coef, scal, flags, bd_rel, npk, U, ldu, w, unew, spart)     \
+   : roll ? ls_update_t<TV, TW, false, PB, true, SP>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs, coef, \
+                                                     scal, flags, bd_rel, npk, U, ldu, w, unew, spart)               \
+          : ls_update_t<TV, TW, false, PB, false, SP>(e, dim3(G), lds, t, pending, zraw, sraw, S, B, ldb, E, cs,      \
+                                                      coef, scal, flags, bd_rel, npk, U, ldu, w, unew, spart))
+#define RKS_LSU(TV, TW, SP) (PBy == 8 ? RKS_LSU_PB(TV, TW, 8, SP) : RKS_LSU_PB(TV, TW, 16, SP))
+  if (e.prec == 0) RKS_LSU(double, double, false);
+  else if (e.prec == 1) RKS_LSU(float, float, false);
+  else if (e.prec == 2) RKS_LSU(bf16_t, float, false);
+  else RKS_LSU(float, double, true);
 #undef RKS_LSU
 #undef RKS_LSU_PB
-  if (e.sp_kind == 0) {  // sketch of the stored value
+  if (e.sp_kind == 0) {  // sketch of the stored value (the pair basis: of its FP64 copy)
     if (e.prec == 0) return gauss_t<double>(e, (const double*)unew, spart);
     if (e.prec == 1) return gauss_t<float>(e, (const float*)unew, spart);
-    return gauss_t<bf16_t>(e, (const bf16_t*)unew, spart);
+    if (e.prec == 2) return gauss_t<bf16_t>(e, (const bf16_t*)unew, spart);
+    return gauss_t<double>(e, e.xcur, spart);
   }
   return G;
 }
@@ -1598,52 +1730,65 @@ int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<float, KIND>, lds);
                       k_init<float, KIND><<<grid, block, lds, e.stream>>>(e.n, (float*)u, u0, s0, s1, c2, tag, spart, e.sp,
                                                                         store));
-  } else {
+  } else if (prec == 2) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<bf16_t, KIND>, lds);
                       k_init<bf16_t, KIND><<<grid, block, lds, e.stream>>>(e.n, (bf16_t*)u, u0, s0, s1, c2, tag, spart, e.sp,
                                                                         store));
+  } else {
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_init<float, KIND, true>, lds);
+                      k_init<float, KIND, true><<<grid, block, lds, e.stream>>>(
+                          e.n, (float*)u, u0, s0, s1, c2, tag, spart, e.sp, store, store ? e.lo_of(u) : nullptr,
+                          e.xcur));
   }
   if (e.sp_kind == 0) {
     // sketch of the stored value; without a store, of u0 itself (FP64 only)
     if (!store) return u0 ? gauss_t<double>(e, u0, spart) : 0;
     if (prec == 0) return gauss_t<double>(e, (const double*)u, spart);
     if (prec == 1) return gauss_t<float>(e, (const float*)u, spart);
-    return gauss_t<bf16_t>(e, (const bf16_t*)u, spart);
+    if (prec == 2) return gauss_t<bf16_t>(e, (const bf16_t*)u, spart);
+    return gauss_t<double>(e, e.xcur, spart);
   }
   return G;
 }
 
-template <typename TI, typename TO, int NT>
+template <typename TI, typename TO, int NT, bool SPLIT>
 static void rotate_nt(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
                       int kout, const double* Y, int xsrc, int xdst, double xscale) {
   constexpr int R = rot_rows<TI>(NT);
   const int64_t ntile = (e.n + 16 * R - 1) / (16 * R);
   const int G = grid_for(ntile, 4, 2048);
   const size_t lds = (size_t)((min + 15) & ~15) * 16 * NT * 8;
+  // the pair basis: the bfloat16 parts of the input, of an FP32 output, and
+  // the FP64 copy of the column xdst
+  const bf16_t* Ulo = SPLIT ? e.lo_of(U) : nullptr;
+  bf16_t* Olo = SPLIT && sizeof(TO) == 4 ? e.lo_of(O) : nullptr;
+  double* xcur = SPLIT && xsrc >= 0 ? e.xcur : nullptr;
   if (lds > kRotLdsMax) {
-    launch_k(e, true, true, k_rotate<TI, TO, NT, true, R>, dim3(G), dim3(256), 0, e.n, U, ldu, in0, min, O, ldo,
-             out0, kout, Y, xsrc, xdst, xscale);
+    launch_k(e, true, true, k_rotate<TI, TO, NT, true, R, SPLIT>, dim3(G), dim3(256), 0, e.n, U, ldu, in0, min, O,
+             ldo, out0, kout, Y, xsrc, xdst, xscale, Ulo, Olo, xcur);
     return;
   }
-  lds_allow((const void*)k_rotate<TI, TO, NT, false, R>, lds);
-  launch_k(e, true, true, k_rotate<TI, TO, NT, false, R>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O, ldo,
-           out0, kout, Y, xsrc, xdst, xscale);
+  lds_allow((const void*)k_rotate<TI, TO, NT, false, R, SPLIT>, lds);
+  launch_k(e, true, true, k_rotate<TI, TO, NT, false, R, SPLIT>, dim3(G), dim3(256), lds, e.n, U, ldu, in0, min, O,
+           ldo, out0, kout, Y, xsrc, xdst, xscale, Ulo, Olo, xcur);
 }
 
-template <typename TI, typename TO>
+template <typename TI, typename TO, bool SPLIT = false>
 static void rotate_t(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int min, TO* O, int64_t ldo, int out0,
                      int kout, const double* Y, int xsrc, int xdst, double xscale) {
+#define RKS_ROT(NT) rotate_nt<TI, TO, NT, SPLIT>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale)
   switch ((kout + 15) / 16) {
     case 0:
-    case 1: rotate_nt<TI, TO, 1>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    case 2: rotate_nt<TI, TO, 2>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    case 3: rotate_nt<TI, TO, 3>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    case 4: rotate_nt<TI, TO, 4>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    case 5: rotate_nt<TI, TO, 5>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    case 6: rotate_nt<TI, TO, 6>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    case 7: rotate_nt<TI, TO, 7>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
-    default: rotate_nt<TI, TO, 8>(e, U, ldu, in0, min, O, ldo, out0, kout, Y, xsrc, xdst, xscale); break;
+    case 1: RKS_ROT(1); break;
+    case 2: RKS_ROT(2); break;
+    case 3: RKS_ROT(3); break;
+    case 4: RKS_ROT(4); break;
+    case 5: RKS_ROT(5); break;
+    case 6: RKS_ROT(6); break;
+    case 7: RKS_ROT(7); break;
+    default: RKS_ROT(8); break;
   }
+#undef RKS_ROT
 }
 
 void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int min, void* O, int64_t ldo, int out0,
@@ -1655,13 +1800,20 @@ void launch_rotate(const LaunchEnv& e, const void* U, int64_t ldu, int in0, int 
       rotate_t<float, double>(e, (const float*)U, ldu, in0, min, (double*)O, ldo, out0, kout, Y, xsrc, xdst, xscale);
     else
       rotate_t<float, float>(e, (const float*)U, ldu, in0, min, (float*)O, ldo, out0, kout, Y, xsrc, xdst, xscale);
-  } else {
+  } else if (e.prec == 2) {
     if (out_fp64)
       rotate_t<bf16_t, double>(e, (const bf16_t*)U, ldu, in0, min, (double*)O, ldo, out0, kout, Y, xsrc, xdst,
                                xscale);
     else
       rotate_t<bf16_t, bf16_t>(e, (const bf16_t*)U, ldu, in0, min, (bf16_t*)O, ldo, out0, kout, Y, xsrc, xdst,
                                xscale);
+  } else {
+    if (out_fp64)
+      rotate_t<float, double, true>(e, (const float*)U, ldu, in0, min, (double*)O, ldo, out0, kout, Y, xsrc, xdst,
+                                    xscale);
+    else
+      rotate_t<float, float, true>(e, (const float*)U, ldu, in0, min, (float*)O, ldo, out0, kout, Y, xsrc, xdst,
+                                   xscale);
   }
 }
 

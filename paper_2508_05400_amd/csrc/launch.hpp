@@ -11,7 +11,7 @@ namespace rks {
 struct LaunchEnv {
   hipStream_t stream;
   int64_t n;
-  int prec;            // 0 FP64 basis, 1 FP32 basis, 2 BF16 basis
+  int prec;            // 0 FP64 basis, 1 FP32 basis, 2 BF16 basis, 3 FP32 + BF16 pair basis
   const int* rp;       // CSR row pointers (device)
   const int* col;      // CSR columns (device)
   const double* val;   // FP64 values (device)
@@ -38,17 +38,29 @@ struct LaunchEnv {
   // dispatches' own timestamps (no marker packets between the kernels).
   hipEvent_t ev0 = nullptr;
   hipEvent_t ev1 = nullptr;
-  int vbytes() const { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+  // the pair basis (prec 3): the FP32 parts at pair_hi (the basis pointer the
+  // launchers get), the bfloat16 parts of the same elements at pair_lo, and
+  // xcur (ldu FP64 values, padding rows zero), the FP64 copy of the column
+  // written last, which the SpMV of the next step reads
+  const float* pair_hi = nullptr;
+  bf16_t* pair_lo = nullptr;
+  double* xcur = nullptr;
+  bf16_t* lo_of(const void* hi) const { return pair_lo + ((const float*)hi - pair_hi); }
+  // bytes between consecutive rows of a basis column (the pair basis: of its FP32 part)
+  int vbytes() const { return prec == 0 ? 8 : (prec == 2 ? 2 : 4); }
 };
 
 // w = A x, partials of Omega w (returns the number of partial rows: at most
-// kMaxPart for the row tiles, npanels for the column-blocked layout).
+// kMaxPart for the row tiles, npanels for the column-blocked layout).  For the
+// pair basis (prec 3) x and w are FP64.
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override);
 void launch_reduce(const LaunchEnv& e, const double* pa, int Ga, const double* pb, int Gb, double* oa, double* ob);
 // E = S^T S - I ((m+1) x (m+1), leading dimension ldb), kept current column by column.
 void launch_ls(const LaunchEnv& e, int t, int pending, int finalize_only, const double* zraw, const double* sraw,
                double* S, double* B, int ldb, double* E, double* cs, double* coef, double* scal, int* flags,
                double bd_rel);
+// (FP64, FP32 and BF16 bases: the deterministic Krylov-Schur step, which
+// takes no pair basis)
 int launch_update(const LaunchEnv& e, int ncol, const void* U, int64_t ldu, const void* w, const double* coef,
                   void* unew, double* spart);
 // Least squares (as launch_ls, not finalize-only) and update (as launch_update
@@ -58,7 +70,8 @@ int launch_ls_update(const LaunchEnv& e, int t, int pending, const double* zraw,
                      double bd_rel, const void* U, int64_t ldu, const void* w, void* unew, double* spart);
 // u = u0, or the seeded N(0,1) vector of Philox counter (i, c2, tag) (tag 2:
 // start vector, tag 3: breakdown replacement), stored in the basis type (or
-// prec_override's); partials of Omega of the stored value.
+// prec_override's); partials of Omega of the stored value.  The pair basis
+// (prec 3) also writes the stored value to xcur.
 int launch_init(const LaunchEnv& e, void* u, const double* u0, uint32_t s0, uint32_t s1, double* spart, int store,
                 int prec_override, uint32_t c2 = 0, uint32_t tag = 2);
 // O(:, out0 .. out0 + kout) = U(:, in0 .. in0 + min) Y.  ldu must be a multiple of

@@ -60,14 +60,18 @@ struct rks_ctx {
   rks_opts o{};
   double normA1 = 0.0;
   rks::LaunchEnv env{};
-  int vbytes = 8, wbytes = 8;
+  int vbytes = 8, wbytes = 8;  // bytes between rows of a basis column (the pair basis: its FP32 part), of w
+  int ebytes = 8;              // HBM bytes of one basis element (the pair basis: 4 + 2)
+  bool pair = false;           // FP32 + BF16 pair basis
   int64_t ldu = 0;
   // device buffers
   int *rp = nullptr, *col = nullptr, *tiles = nullptr, *flags = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
   void* U = nullptr;      // basis in use (U_lo or U64)
-  void* U_lo = nullptr;   // basis in the requested precision (allocated at create)
+  void* U_lo = nullptr;   // basis in the requested precision (allocated at create; the pair
+                          // basis: the FP32 parts, then the bfloat16 parts of the same elements)
+  double* xcur = nullptr; // pair basis: FP64 copy of the column written last (ldu values)
   void* U64 = nullptr;    // FP64 basis of the refinement phase (lazy)
   void* w = nullptr;
   double phase_tol = 0.0;
@@ -217,9 +221,15 @@ void flush_events(rks_ctx* c) {
 }
 
 double spmv_bytes(const rks_ctx* c) {
-  const double bval = (c->o.precision == RKS_PREC_FP64) ? 8.0 : 4.0;
-  return (bval + 4.0) * c->nnz + 4.0 * (c->n + 1) + (double)(c->vbytes + c->wbytes) * c->n;
+  // A's values in FP64 for an FP64 or pair basis (whose SpMV reads the FP64 copy of its column)
+  const bool f64 = c->env.prec == RKS_PREC_FP64 || c->pair;
+  const double bval = f64 ? 8.0 : 4.0, xb = c->pair ? 8.0 : c->ebytes;
+  return (bval + 4.0) * c->nnz + 4.0 * (c->n + 1) + (xb + c->wbytes) * c->n;
 }
+
+// The operand of the SpMV of column t: the column, or for the pair basis its FP64 copy.
+const void* spmv_x(rks_ctx* c, int t) { return c->pair ? (const void*)c->xcur : basis_col(c, t); }
+int spmv_prec(const rks_ctx* c) { return c->pair ? RKS_PREC_FP64 : -1; }
 
 // ---- one Arnoldi step (Algorithm 2 loop body) ------------------------------
 void account_step(rks_ctx* c, int t, bool timed, bool whole);
@@ -237,7 +247,7 @@ int arnoldi_step(rks_ctx* c, int t) {
   Prof pw(c, CAT_STEP, whole);
   {
     ProfK p(c, CAT_SPMV, timed, e);
-    c->G_z = rks::launch_spmv_sketch(p.env, basis_col(c, t), c->w, c->zpart, 1, -1);
+    c->G_z = rks::launch_spmv_sketch(p.env, spmv_x(c, t), c->w, c->zpart, 1, spmv_prec(c));
   }
   {
     ProfK p(c, CAT_REDUCE, timed, e);
@@ -260,7 +270,10 @@ int arnoldi_step(rks_ctx* c, int t) {
 // Launch and byte counts of one randomized Arnoldi step.
 void account_step(rks_ctx* c, int t, bool timed, bool whole) {
   if (!c->st) return;
-  const double bs = spmv_bytes(c), bu = (double)(t + 2) * c->n * c->vbytes + (double)c->wbytes * c->n;
+  // the update reads t + 1 columns and w, writes one column (the pair basis:
+  // and its FP64 copy)
+  const double bs = spmv_bytes(c),
+               bu = (double)(t + 2) * c->n * c->ebytes + (double)c->wbytes * c->n + (c->pair ? 8.0 * c->n : 0.0);
   c->st->n_spmv += 1;
   c->st->bytes_spmv += bs;
   c->st->n_update += 1;
@@ -457,7 +470,8 @@ int recover_breakdown(rks_ctx* c, int t) {
   c->breakdowns += 1;
   if (c->st) c->st->breakdowns += 1;
   const uint64_t s = c->o.start_seed;
-  const int wprec = c->env.prec == RKS_PREC_FP64 ? 0 : 1;  // w is FP64, or FP32 with a low-precision basis
+  // w is FP64 (FP64 and pair bases), or FP32 with an FP32 or BF16 basis
+  const int wprec = c->wbytes == 8 ? 0 : 1;
   const int G = rks::launch_init(e, c->w, nullptr, (uint32_t)s, (uint32_t)(s >> 32), c->zpart, 1, wprec,
                                  (uint32_t)c->breakdowns, 3u);
   rks::launch_reduce(e, c->zpart, G, nullptr, 0, c->z, nullptr);
@@ -743,7 +757,7 @@ int rotate_basis(rks_ctx* c, int in0, int min, int out0, int kout, double xscale
   }
   HIPCHK(c, hipGetLastError());
   if (c->st) {
-    const double br = (double)(min + 1 + kout + 1) * c->n * c->vbytes;
+    const double br = (double)(min + 1 + kout + 1) * c->n * c->ebytes + (c->pair ? 8.0 * c->n : 0.0);
     c->st->n_rotate += 1;
     c->st->bytes_rotate += br;
     if (c->o.profile > 0) {
@@ -887,8 +901,10 @@ int verified_max_resid(rks_ctx* c, double* out) {
 // Switch the basis in use between the requested precision and FP64.
 int set_basis(rks_ctx* c, int prec) {
   c->env.prec = prec;
-  c->vbytes = (prec == RKS_PREC_FP64) ? 8 : (prec == RKS_PREC_V32 ? 4 : 2);
-  c->wbytes = (prec == RKS_PREC_FP64) ? 8 : 4;
+  c->pair = prec == RKS_PREC_V32_BF16;
+  c->vbytes = (prec == RKS_PREC_FP64) ? 8 : (prec == RKS_PREC_VBF16 ? 2 : 4);
+  c->ebytes = c->pair ? 6 : c->vbytes;
+  c->wbytes = (prec == RKS_PREC_FP64 || c->pair) ? 8 : 4;
   if (prec == c->o.precision) {
     c->U = c->U_lo;
   } else {
@@ -1031,7 +1047,7 @@ bool valid_csr(const int32_t* rp, const int32_t* col, int64_t n, int64_t nnz, st
 }
 
 void free_all(rks_ctx* c) {
-  void* dev[] = {c->rp, c->col, c->tiles, c->dstate, c->val, c->val32, c->U_lo, c->U64, c->w,
+  void* dev[] = {c->rp, c->col, c->tiles, c->dstate, c->val, c->val32, c->U_lo, c->U64, c->w, c->xcur,
                  c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->kpart,
                  c->col_pn, c->tiles_pn, c->toff_pn, c->ptile, c->off_pn, c->val_pn, c->val32_pn,
                  c->Xr, c->ax1, c->ax2, c->rpart};
@@ -1094,7 +1110,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "sketch_kind");
   if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
-  if (o.precision < 0 || o.precision > 2 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
+  if (o.precision < 0 || o.precision > 3 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
       !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
       o.method > 1 || o.graphs < 0 || o.graphs > 1 || o.stall_restarts < 0)
     return fail(nullptr, RKS_EINVAL,
@@ -1194,9 +1210,14 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     delete c;
     return fail(nullptr, RKS_EINVAL, why);
   }
-  c->vbytes = (o.precision == RKS_PREC_FP64) ? 8 : (o.precision == RKS_PREC_V32 ? 4 : 2);
-  c->wbytes = (o.precision == RKS_PREC_FP64) ? 8 : 4;
+  const bool pair = o.precision == RKS_PREC_V32_BF16;
+  const bool low = o.precision == RKS_PREC_V32 || o.precision == RKS_PREC_VBF16;  // FP32 copies of A's values
+  const int ebytes = o.precision == RKS_PREC_FP64 ? 8 : (pair ? 6 : (o.precision == RKS_PREC_V32 ? 4 : 2));
   c->ldu = (n + 127) / 128 * 128;
+  c->pair = pair;
+  c->vbytes = o.precision == RKS_PREC_FP64 ? 8 : (o.precision == RKS_PREC_VBF16 ? 2 : 4);
+  c->ebytes = ebytes;
+  c->wbytes = (o.precision == RKS_PREC_FP64 || pair) ? 8 : 4;
   bool ok = true;
   std::string what;
   auto dm = [&](void** p, size_t bytes) {
@@ -1219,20 +1240,21 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   const int64_t nzp = nnz + rks::kCsrPad;  // padded: the SpMV reads nonzeros in aligned pairs
   dm((void**)&c->col, nzp * 4);
   dm((void**)&c->val, nzp * 8);
-  if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32, nzp * 4);
+  if (low) dm((void**)&c->val32, nzp * 4);
   dm((void**)&c->tiles, tdesc.size() * 4);
   if (use_cb) {
     dm((void**)&c->col_pn, (size_t)nzp * 4);
     dm((void**)&c->val_pn, (size_t)nzp * 8);
-    if (o.precision != RKS_PREC_FP64) dm((void**)&c->val32_pn, (size_t)nzp * 4);
+    if (low) dm((void**)&c->val32_pn, (size_t)nzp * 4);
     dm((void**)&c->tiles_pn, pl.tiles.size() * 4);
     dm((void**)&c->toff_pn, pl.toff.size() * 4);
     dm((void**)&c->off_pn, pl.off.size() * 2);
     dm((void**)&c->ptile, pl.ptile.size() * 4);
   }
-  dm(&c->U_lo, (size_t)c->ldu * (m + 1) * c->vbytes);
+  dm(&c->U_lo, (size_t)c->ldu * (m + 1) * ebytes);
   c->U = c->U_lo;
   dm(&c->w, (size_t)c->ldu * 8);
+  if (pair) dm((void**)&c->xcur, (size_t)c->ldu * 8);
   // state block: E ((m+1)^2) | B ((m+1) m) | S (d (m+1)) | cs (m+1) | flags (4 int32), FP64 offsets
   const size_t oE = 0, oB = oE + (size_t)(m + 1) * (m + 1), oS = oB + (size_t)(m + 1) * m,
                oC = oS + (size_t)d * (m + 1), oF = oC + (size_t)(m + 1), state_bytes = (oF + 2) * 8;
@@ -1295,9 +1317,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   zero_pad(c->col_pn, 4);
   zero_pad(c->val_pn, 8);
   zero_pad(c->val32_pn, 4);
-  if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * c->vbytes) != hipSuccess) rc = RKS_EHIP;
-  // padding rows of U and w stay zero for the whole life of the context
+  if (rc == RKS_OK && hipMemset(c->U_lo, 0, (size_t)c->ldu * (m + 1) * ebytes) != hipSuccess) rc = RKS_EHIP;
+  // padding rows of U, w and xcur stay zero for the whole life of the context
   if (rc == RKS_OK && hipMemset(c->w, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
+  if (rc == RKS_OK && pair && hipMemset(c->xcur, 0, (size_t)c->ldu * 8) != hipSuccess) rc = RKS_EHIP;
   if (rc == RKS_OK && hipMemset(c->E, 0, (size_t)(m + 1) * (m + 1) * 8) != hipSuccess) rc = RKS_EHIP;
   if (rc != RKS_OK) {
     free_all(c);
@@ -1308,6 +1331,11 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.stream = stm;
   e.n = n;
   e.prec = o.precision;
+  if (pair) {
+    e.pair_hi = (const float*)c->U_lo;
+    e.pair_lo = (rks::bf16_t*)((char*)c->U_lo + (size_t)c->ldu * (m + 1) * 4);
+    e.xcur = c->xcur;
+  }
   e.rp = c->rp;
   e.col = c->col;
   e.val = c->val;
@@ -1360,7 +1388,9 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   c->st = st;
   const auto t0 = std::chrono::steady_clock::now();
   set_basis(c, c->o.precision);
-  const bool mixed = c->o.precision != RKS_PREC_FP64;
+  // (the pair basis runs one phase: its stored values carry 32 bits of
+  // significand, which the verified FP64 residual does not need refined)
+  const bool mixed = c->o.precision == RKS_PREC_V32 || c->o.precision == RKS_PREC_VBF16;
   const bool refine = mixed && c->o.refine;
   PhaseOut p1{};
   int rc;
@@ -1522,6 +1552,13 @@ int rks_get_state(rks_ctx* c, int32_t* ncols, double* B, double* S, double* U) {
   if (U) {
     const size_t colb = (size_t)c->ldu * c->vbytes;
     std::vector<unsigned char> buf(colb);
+    std::vector<uint16_t> lo(c->pair ? c->ldu : 0);
+    auto bf16 = [](uint16_t h) {
+      const uint32_t u = (uint32_t)h << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      return (double)f;
+    };
     for (int l = 0; l <= c->m; ++l) {
       double* dst = U + (size_t)l * c->n;
       if (l >= nc) {
@@ -1529,6 +1566,8 @@ int rks_get_state(rks_ctx* c, int32_t* ncols, double* B, double* S, double* U) {
         continue;
       }
       HIPCHK(c, hipMemcpy(buf.data(), basis_col(c, l), colb, hipMemcpyDeviceToHost));
+      if (c->pair)
+        HIPCHK(c, hipMemcpy(lo.data(), c->env.lo_of(basis_col(c, l)), (size_t)c->ldu * 2, hipMemcpyDeviceToHost));
       const double s = c->hcs[l];
       for (int64_t i = 0; i < c->n; ++i) {
         double v;
@@ -1538,13 +1577,11 @@ int rks_get_state(rks_ctx* c, int32_t* ncols, double* B, double* S, double* U) {
           float f;
           std::memcpy(&f, &buf[i * 4], 4);
           v = f;
+          if (c->pair) v += bf16(lo[i]);  // the stored value hi + lo
         } else {
           uint16_t h;
           std::memcpy(&h, &buf[i * 2], 2);
-          uint32_t u = (uint32_t)h << 16;
-          float f;
-          std::memcpy(&f, &u, 4);
-          v = f;
+          v = bf16(h);
         }
         dst[i] = v * s;
       }
