@@ -34,15 +34,15 @@ def _extension(A, k, m, d, which, kind="sparse", seed=3):
     return B, S, U
 
 
-def _identities(A, B, S, U, m, d, kind, seed):
+def _identities(A, B, S, U, m, d, kind, seed, rel_bar=None, orth_bar=1e-12):
     Sp = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
     nA = abs(Sp).sum(axis=0).max()
     rel = np.linalg.norm(Sp @ U[:, :m] - U @ B) / (nA * np.linalg.norm(U[:, :m]))
-    assert rel < 16 * m * U64, rel
+    assert rel < (16 * m * U64 if rel_bar is None else rel_bar), rel
     om = sketch_matrix(A.n, d, kind, seed)
     OU = np.asarray(om @ U)
     assert np.linalg.norm(OU - S) < 1e-12
-    assert np.linalg.norm(OU.T @ OU - np.eye(m + 1)) < 1e-12
+    assert np.linalg.norm(OU.T @ OU - np.eye(m + 1)) < orth_bar
     return nA
 
 
@@ -99,16 +99,24 @@ def _invariant_case():
     return _diag_csr(diag), diag, u0
 
 
-def test_exact_invariant_subspace_is_continued_past(lib, cuda):
+@pytest.mark.parametrize("prec", ["fp64", "fp32+bf16"])
+def test_exact_invariant_subspace_is_continued_past(lib, cuda, prec):
     """The extension meets the vanishing remainder at column 3, replaces it
     with the seeded tag-3 vector sketch-orthogonalised against U_3 and sets
     B(3, 2) = 0, as the oracle does: the whole decomposition equals the
     oracle's (entrywise 1e-9 ||A||_1) and satisfies the exact identities, and
-    its Rayleigh quotient holds the three exact eigenvalues to 1e-12."""
+    its Rayleigh quotient holds the three exact eigenvalues to 1e-12.  The
+    pair basis meets the breakdown too (its first columns keep the start's
+    three-coordinate support, so they span the invariant subspace exactly)
+    and continues through the FP64 replacement vector like FP64 storage; its
+    columns carry the pair rounding (relation to 64 * 2^-32; off the diagonal
+    the sketch Gram matrix sees each stored column's rounding error against
+    the others, about u (m+1) / sqrt(3 d) in norm with u = 2^-32, bar 4 times
+    that) and agree with the oracle's pair storage to the same bars."""
     A, diag, u0 = _invariant_case()
     k, m, d = 5, 12, 40
     ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
-                       P.rks_opts_default(sketch_kind="sparse", sketch_seed=3, start_seed=1))
+                       P.rks_opts_default(sketch_kind="sparse", sketch_seed=3, start_seed=1, precision=prec))
     try:
         P.rks_arnoldi(ctx, u0)
         B = np.zeros((m + 1, m), order="F")
@@ -117,12 +125,16 @@ def test_exact_invariant_subspace_is_continued_past(lib, cuda):
         assert P.rks_get_state(ctx, B, S, U) == m + 1
     finally:
         P.rks_destroy(ctx)
-    o = RKSOracle(A, k, m, d, "LM", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1)
+    o = RKSOracle(A, k, m, d, "LM", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1, store=prec)
     o.start(u0)
     o.extend()
     assert o.breakdowns == 1 and o.B[3, 2] == 0.0
     assert B[3, 2] == 0.0
-    nA = _identities(A, B, S, U, m, d, "sparse", 3)
+    if prec == "fp64":
+        nA = _identities(A, B, S, U, m, d, "sparse", 3)
+    else:
+        u = 2.0**-32
+        nA = _identities(A, B, S, U, m, d, "sparse", 3, 64 * u, 4 * u * (m + 1) / np.sqrt(3 * d))
     assert np.abs(B - o.B).max() <= 1e-9 * nA, np.abs(B - o.B).max() / nA
     assert np.abs(U - o.U).max() <= 1e-9 * np.abs(o.U).max()
     ev = np.linalg.eigvals(B[:m, :m])

@@ -361,6 +361,11 @@ def test_error_paths(lib, cuda):
         assert ei.value.code == -4  # RKS_ENAN
     finally:
         s.close()
+    # the deterministic Krylov-Schur step takes FP64 bases only; precision codes end at 3
+    for kw in (dict(precision="fp32+bf16", method="ks_cgs2"), dict(precision=4)):
+        with pytest.raises(P.RksError) as ei:
+            P.Solver.from_csr(A, k=4, m=12, d=30, which="LR", tol=1e-10, **kw)
+        assert ei.value.code == -1  # RKS_EINVAL
 
 
 def test_stagnation_stop(lib, cuda):
