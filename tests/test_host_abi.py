@@ -167,6 +167,47 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
         assert got == int(val), (cname, field, got, val)
 
 
+def test_binding_enum_names_match_the_header(tmp_path):
+    """The binding's string names for which, sketch kind, basis precision,
+    SpMV layout and method map to the header's enum values (the precision
+    names include the pair basis, "fp32+bf16")."""
+    import shutil
+    import subprocess
+    from paper_2508_05400_amd import _binding as B
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    expect = {
+        ("which", "LM"): "RKS_LM", ("which", "SM"): "RKS_SM", ("which", "LR"): "RKS_LR", ("which", "SR"): "RKS_SR",
+        ("sketch", "gauss"): "RKS_SKETCH_GAUSS", ("sketch", "sparse"): "RKS_SKETCH_SPARSE",
+        ("precision", "fp64"): "RKS_PREC_FP64", ("precision", "fp32"): "RKS_PREC_V32",
+        ("precision", "bf16"): "RKS_PREC_VBF16", ("precision", "fp32+bf16"): "RKS_PREC_V32_BF16",
+        ("layout", "auto"): "RKS_SPMV_AUTO", ("layout", "rows"): "RKS_SPMV_ROWS",
+        ("layout", "column_blocks"): "RKS_SPMV_COLUMN_BLOCKS",
+        ("method", "rks"): "RKS_METHOD_RKS", ("method", "ks_cgs2"): "RKS_METHOD_KS_CGS2",
+    }
+    tables = {"which": B.WHICH, "sketch": B.SKETCH, "precision": B.PRECISION, "layout": B.SPMV_LAYOUT,
+              "method": B.METHOD}
+    lines = ['#include <stdio.h>', '#include "rks.h"', "int main(void) {"]
+    for (t, name), cname in expect.items():
+        lines.append(f'  printf("{t} {name} %d\\n", (int){cname});')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "enums.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "enums"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        t, name, val = line.split()
+        assert tables[t][name] == int(val), (t, name, tables[t][name], val)
+        seen += 1
+    assert seen == len(expect)
+    # aliases map to values the header defines too
+    for t, table in tables.items():
+        assert set(table.values()) <= {tables[t][n] for (tt, n) in expect if tt == t}, t
+
+
 def test_bench_refuses_more_than_one_gpu():
     """bench.py measures one GPU; asked for more it exits with a message before
     touching any device."""
