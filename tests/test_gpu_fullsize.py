@@ -46,7 +46,7 @@ U64 = 2.0**-53
 ULOW = {"fp64": U64, "fp32": 2.0**-24, "bf16": 2.0**-8, "fp32+bf16": 2.0**-32}
 
 FULL = [("cd2d-1000", "fp64"), ("cd3d-160", "fp64"), ("cd3d-160", "fp32"), ("cd3d-160", "bf16"),
-        ("cd3d-160", "fp32+bf16"), ("powerlaw-2m", "fp64")]
+        ("cd3d-160", "fp32+bf16"), ("powerlaw-2m", "fp64"), ("powerlaw-2m", "fp32+bf16")]
 
 
 @functools.lru_cache(maxsize=4)
