@@ -349,9 +349,12 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_panel(
 // Deterministic sum of G partial rows: block (x, y) sums kRedBins bins of
 // array y.  Each of the kRedSl row slices adds every kRedSl-th row with two
 // chains; a fixed tree over the slices finishes the sum (same order every
-// call).  A wave reads 8 rows x 64 contiguous bytes per load.
+// call).  A wave reads 8 rows x 64 contiguous bytes per load.  128 slices
+// (10 rows each for the SpMV's 1,280 partial rows) took the launch from 4.8
+// to 4.0 us against 64 slices; 4 bins per block or 4 chains per slice did
+// not help further.
 constexpr int kRedBins = 8;
-constexpr int kRedSl = 64;
+constexpr int kRedSl = 128;
 
 __global__ __launch_bounds__(kRedBins * kRedSl) void k_reduce(const double* __restrict__ pa,
                                                              const double* __restrict__ pb, int Ga, int Gb, int d,

@@ -374,7 +374,10 @@ def test_stagnation_stop(lib, cuda):
     with Algorithm 1's truncation, which stalls (the oracle pin
     test_algorithm1_truncation_stalls_on_the_small_2d_workload), the solve
     stops well before the cap, with the estimate history showing no halving
-    over its last S restarts; with S = 0 it runs to the cap."""
+    over its last S restarts.  With S = 0 the same solve never stops for
+    stagnation and runs past that point: to the cap, or (the stalled phase
+    ends or not depending on the rounding order of the kernels' sums) to
+    the verified residual."""
     A = convdiff2d(100, (20.0, 10.0))
     kw = dict(k=10, m=40, d=80, which="LR", tol=1e-10, sketch_kind="gauss", sketch_seed=0, start_seed=1,
               resid_tol=1e-8, max_restarts=300)
@@ -389,8 +392,13 @@ def test_stagnation_stop(lib, cuda):
     h = np.array(st["hist_est"][:r + 1])
     assert h[r - S:].min() >= 0.5 * h[:r - S + 1].min() * (1 - 1e-12)
     with P.Solver.from_csr(A, **kw) as s2:
-        assert s2.solve() == 1
-        assert s2.stats.stop_reason == 0 and s2.stats.restarts == 300
+        code = s2.solve()
+        st2 = s2.stats.as_dict()
+    assert st2["restarts"] > r
+    if code == 1:
+        assert st2["stop_reason"] == 0 and st2["restarts"] == 300
+    else:
+        assert code == 0 and st2["stop_reason"] == 2 and st2["max_resid"] <= 1e-8
 
 
 def test_verified_residual_stop(lib, cuda):
