@@ -67,13 +67,22 @@ def round_storage(x, store):
     one is taken, and a tie goes to the one whose last significand bit is 0.
     'fp32+bf16' stores a pair: hi, the binary32 rounding, and lo, the bfloat16
     rounding (as above) of the remainder x - hi, which FP64 holds exactly; the
-    stored value is hi + lo, within 2^-32 |x| of x."""
+    stored value is hi + lo, within 2^-32 |x| of x.
+    'fp32+fx16' stores hi and a 16-bit signed integer q: the remainder x - hi
+    measured in units of 2^-15 ulp(hi) and rounded to the nearest integer
+    (ties to even), where ulp(hi) = 2^(max(e, 1) - 150) for the biased
+    binary32 exponent e of hi (the spacing of binary32 values at hi).  Since
+    |x - hi| <= ulp(hi) / 2, |q| <= 2^14; the stored value hi + q 2^-15 ulp(hi)
+    is within 2^-16 ulp(hi) <= 2^-39 |hi| of x."""
     x = np.asarray(x, dtype=np.float64)
     if store == "fp64":
         return x.copy()
     if store == "fp32+bf16":
         hi = round_storage(x, "fp32")
         return hi + round_storage(x - hi, "bf16")
+    if store == "fp32+fx16":
+        hi, q, step = fx16_pair(x)
+        return hi + q * step
     x32 = x.astype(np.float32)
     if store == "fp32":
         return x32.astype(np.float64)
@@ -88,6 +97,18 @@ def round_storage(x, store):
     down_even = ((bits >> np.uint32(16)) & np.uint32(1)) == 0
     take_up = (du < dd) | ((du == dd) & ~down_even & (dd > 0))
     return np.where(take_up, up, down)
+
+
+def fx16_pair(x):
+    """The parts of the 'fp32+fx16' storage of x (see round_storage): hi (as
+    FP64), the integer q (as FP64) and the unit step = 2^-15 ulp(hi)."""
+    x = np.asarray(x, dtype=np.float64)
+    hi32 = x.astype(np.float32)
+    hi = hi32.astype(np.float64)
+    e = ((hi32.view(np.uint32) >> np.uint32(23)) & np.uint32(0xFF)).astype(np.int64)
+    step = np.ldexp(1.0, np.maximum(e, 1) - 150 - 15)
+    q = np.rint((x - hi) / step)    # exact quotient (a power of two); rint ties to even
+    return hi, q, step
 
 
 def which_key(lam: complex, which: str):
@@ -190,8 +211,8 @@ class RKSOracle:
         # copies of A's values and its result is rounded to binary32; the
         # stored column is the unnormalised remainder rounded to the format,
         # its scale 1/beta is kept in FP64, and the sketch is taken of the
-        # stored value); 'fp32+bf16' stores the remainder as such a pair and
-        # forms the product with A in FP64 from the stored value
+        # stored value); 'fp32+bf16' and 'fp32+fx16' store the remainder as
+        # such a pair and form the product with A in FP64 from the stored value
         self.store = store
         if store != "fp64":
             self.A_low = sp.csr_matrix((round_storage(self.A.data, "fp32"), self.A.indices, self.A.indptr),
@@ -248,10 +269,11 @@ class RKSOracle:
         """A u_j.  With a low-precision basis, u_j = c_j v_j is a stored
         vector v_j times its FP64 scale c_j: the product A v_j is formed from
         binary32 copies of A's values and rounded to binary32, then scaled
-        ('fp32+bf16': in FP64 from A's values and the stored value)."""
+        (the pairs 'fp32+bf16' and 'fp32+fx16': in FP64 from A's values and
+        the stored value)."""
         if self.store == "fp64":
             return self.A @ self.U[:, j]
-        if self.store == "fp32+bf16":
+        if self.store in ("fp32+bf16", "fp32+fx16"):
             return self.cs[j] * (self.A @ self.stored[:, j])
         w = round_storage(self.A_low @ self.stored[:, j], "fp32")
         return self.cs[j] * w

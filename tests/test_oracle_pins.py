@@ -683,6 +683,72 @@ def test_fp32_bf16_storage_reaches_below_1e9():
     assert np.abs(rpr.lam - r64.lam).max() <= 1e-8 * np.abs(r64.lam).max()
 
 
+def test_round_storage_fp32_fx16_brute_force():
+    """The FP32 + 16-bit fixed-point pair: hi is the binary32 rounding of x
+    (numpy's conversion), and the stored value is the point of the grid
+    hi + k delta (k an integer, delta = 2^-15 times the spacing of binary32
+    values at hi, taken from numpy's spacing) nearest to x, a tie going to the
+    even k, found by comparing the two grid points around x.  |k| <= 2^14, the
+    error is at most delta / 2 <= 2^-39 |hi|, and binary32 values (zero
+    included) store exactly."""
+    from oracle.rks import round_storage
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(30000) * 10.0 ** rng.uniform(-30, 30, 30000)
+    one32 = float(np.spacing(np.float32(1.0)))                   # 2^-23
+    extra = [1.0 + 0.5 * one32,                                   # remainder exactly half a binary32 step
+             1.0 + one32 * 2.0**-15 * 2.5,                        # remainder at a grid midpoint: rounds to even (2)
+             1.0 + one32 * 2.0**-15 * 3.5,                        # midpoint: rounds to even (4)
+             3.0, 0.0, -1.5, 1e-42, -2.0**-140 * 1.2345]          # binary32 values, a subnormal range value
+    x = np.concatenate([x, extra])
+    hi = x.astype(np.float32).astype(np.float64)
+    delta = np.abs(np.spacing(x.astype(np.float32)).astype(np.float64)) * 2.0**-15
+    r = x - hi
+    k0 = np.floor(r / delta)
+    a, b = hi + k0 * delta, hi + (k0 + 1) * delta
+    da, db = np.abs(x - a), np.abs(x - b)
+    pick_b = (db < da) | ((db == da) & (k0 % 2 != 0))
+    want = np.where(pick_b, b, a)
+    got = round_storage(x, "fp32+fx16")
+    assert np.array_equal(got, want)
+    k = np.where(pick_b, k0 + 1, k0)
+    assert np.abs(k).max() <= 2**14
+    assert np.all(np.abs(got - x) <= delta / 2)
+    assert np.all(np.abs(got - x) <= 2.0**-39 * np.abs(hi) + 2.0**-165)
+    n = len(extra)
+    assert got[-n + 1] == 1.0 + one32 * 2.0**-15 * 2 and got[-n + 2] == 1.0 + one32 * 2.0**-15 * 4
+    assert got[-n + 3] == 3.0 and got[-n + 4] == 0.0 and got[-n + 5] == -1.5
+
+
+def test_fp32_fx16_storage_converges_like_fp64():
+    """The FP32 + fixed-point basis keeps 39 significant bits: on the small 2D
+    workload it reaches residual below 1e-11, in FP64's number of restarts
+    (+-1) and with FP64's eigenvalues to 1e-10, where the FP32 + BF16 pair
+    (2^-32) floors near 1e-10.  Its extension's Krylov relation misses only
+    the fixed-point rounding of each stored remainder (2^-39 of the
+    remainder) and FP64 noise."""
+    A = convdiff2d(30, (2.0, 1.0))
+    kw = dict(sketch="sparse", sketch_seed=3, start_seed=1, max_restarts=60)
+    r64 = rks(A, 4, 20, 50, "LR", 1e-13, **kw)
+    rfx = rks(A, 4, 20, 50, "LR", 1e-13, store="fp32+fx16", **kw)
+    assert rfx.converged and rfx.resid.max() < 1e-11
+    assert abs(rfx.restarts - r64.restarts) <= 1
+    assert np.abs(rfx.lam - r64.lam).max() <= 1e-10 * np.abs(r64.lam).max()
+    A = convdiff2d(30, (20.0, 10.0))
+    k, m, d = 5, 16, 48
+    u = 2.0**-39
+    o = RKSOracle(A, k, m, d, "LR", 1e-10, sketch="sparse", sketch_seed=3, start_seed=1, store="fp32+fx16")
+    o.start()
+    o.extend()
+    Ad = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    Aabs = abs(Ad)
+    for j in range(m):
+        res = Ad @ o.U[:, j] - o.U[:, :j + 2] @ o.B[:j + 2, j]
+        r = o.U[:, :j + 2] @ o.B[:j + 2, j]
+        bound = (u * np.abs(r) + np.abs(o.U[:, :j + 1]) @ np.abs(o.B[:j + 1, j]) * u
+                 + 1e-14 * (Aabs @ np.abs(o.U[:, j])))
+        assert np.all(np.abs(res) <= bound), (j, np.max(np.abs(res) / bound))
+
+
 def test_store_fp64_is_the_plain_oracle():
     A = convdiff2d(20, (6.0, 3.0))
     a = rks(A, 4, 16, 40, "LR", 1e-10, sketch="sparse", sketch_seed=1, store="fp64")
