@@ -9,8 +9,8 @@ One step = one complete rks_solve (start vector -> converged or restart cap)
 with the matrix already resident in HBM, followed by nothing else; the
 eigenpair residual check runs after the timed region.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16|fp32+bf16]
-                  [--keep auto|N] [--compare fp32,bf16,fp32+bf16,alg1,eta,ks_cgs2,aggr] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16|fp32+fx16]
+                  [--keep auto|N] [--compare fp32,bf16,fp32+fx16,alg1,eta,ks_cgs2,aggr] [--no-cpu-baseline]
 
 Stop rules: the main run stops when every FP64 residual
 ||A x - lambda x|| / (||A||_1 ||x||) is verified on the device to be <= 1e-8
@@ -24,7 +24,7 @@ The solver keeps the restart size --keep Schur vectors at each contraction
 Section 3.1).  The default line times the FP64 solver and, after it, these
 variants on the same workload, reported under "variants" with their own
 time-to-k, loop bandwidth and error against the main run: the FP32- and
-BF16-basis solvers (with FP64 refinement), the FP32 + BF16 pair-basis
+BF16-basis solvers (with FP64 refinement), the pair-basis (binary32 + 16-bit remainder)
 solver (6 bytes per basis element, FP64 arithmetic, one phase), "alg1"
 (FP64, keep = k, the truncation of Algorithm 1 as printed) and "eta" (FP64,
 estimate stop only).  Also available: "ks_cgs2" (deterministic Krylov-Schur)
@@ -246,8 +246,8 @@ def main():
                     "0 = none (the run stops at its own verified residual --resid-tol)")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay repeated extensions as HIP graphs (used only "
                     "when the per-kernel events are off, --no-profile); 0: launch every kernel")
-    ap.add_argument("--compare", default="fp32,bf16,fp32+bf16,alg1,eta", help="comma list of extra runs on the same "
-                    "workload after the main run: basis precisions (fp32, bf16, fp32+bf16), alg1 (FP64, keep = k), eta (FP64, the paper's "
+    ap.add_argument("--compare", default="fp32,bf16,fp32+fx16,alg1,eta", help="comma list of extra runs on the same "
+                    "workload after the main run: basis precisions (fp32, bf16, fp32+fx16), alg1 (FP64, keep = k), eta (FP64, the paper's "
                     "estimate stop only), aggr (lock = 2) and/or ks_cgs2 (deterministic Krylov-Schur); reported under "
                     "'variants'")
     ap.add_argument("--compare-steps", type=int, default=2, help="timed solves per variant (after one untimed solve); "
@@ -332,7 +332,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32-basis/f64", "bf16": "bf16-basis/f64",
-                  "fp32+bf16": "f32+bf16-basis/f64"}[cfg["precision"]],
+                  "fp32+fx16": "f32+fx16-basis/f64"}[cfg["precision"]],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload).format(**cfg),
                    "n": A.n, "nnz": A.nnz, "k": cfg["k"], "m": cfg["m"], "d": cfg["d"],
@@ -373,7 +373,7 @@ def main():
     extra = {}
     for prec in [p for p in args.compare.split(",") if p]:
         # a precision (fp32, bf16: mixed precision with FP64 refinement;
-        # fp32+bf16: the pair basis in one phase), ks_cgs2:
+        # fp32+fx16: the pair basis in one phase), ks_cgs2:
         # deterministic Krylov-Schur with an FP64 basis (the paper's comparison),
         # alg1: FP64 with the restart size of Algorithm 1 (keep = k), or aggr:
         # FP64 with aggressive deflation (converged wanted blocks moved to the
@@ -415,7 +415,7 @@ def main():
                            "vs_main_run": _error_vs(lam, X64, lam2, X2)}
     if extra:
         out["variants"] = extra
-        mixed = {p: extra[p]["time_to_k_s"] / t_mean for p in ("fp32", "bf16", "fp32+bf16") if p in extra}
+        mixed = {p: extra[p]["time_to_k_s"] / t_mean for p in ("fp32", "bf16", "fp32+fx16") if p in extra}
         if mixed:
             out["mixed_vs_fp64_time_ratio"] = mixed
     if not args.no_cpu_baseline:

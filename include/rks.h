@@ -56,12 +56,14 @@ typedef enum { RKS_SKETCH_GAUSS = 0, RKS_SKETCH_SPARSE = 1 } rks_sketch_kind;
  * paper's future-work direction of Section 6; sketch-space quantities, the
  * Rayleigh quotient and all small dense steps stay FP64).  V32 and VBF16
  * store binary32 or bfloat16 columns and multiply them with binary32 copies
- * of A's values.  V32_BF16 stores each element as a pair, 6 bytes: hi, its
- * binary32 rounding, and lo, the bfloat16 rounding of the remainder (both to
- * nearest even), with value hi + lo within 2^-32 of the element relative to
- * it; arithmetic stays FP64, the products with A read an FP64 copy of the
- * column last written (n doubles more device memory). */
-typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2, RKS_PREC_V32_BF16 = 3 } rks_precision;
+ * of A's values.  V32_FX16 stores each element x as a pair, 6 bytes: hi, its
+ * binary32 rounding, and lo, a 16-bit signed integer, the remainder x - hi in
+ * units of 2^-15 ulp(hi) rounded to nearest even (ulp(hi) = 2^(max(e,1) - 150)
+ * for the biased binary32 exponent e of hi); the value hi + lo 2^-15 ulp(hi)
+ * is within 2^-39 of x relative to it.  Arithmetic stays FP64, the products
+ * with A read an FP64 copy of the column last written (n doubles more device
+ * memory). */
+typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2, RKS_PREC_V32_FX16 = 3 } rks_precision;
 
 /* SpMV layout.  ROWS: wave tiles of consecutive rows.  COLUMN_BLOCKS: for
  * rows that gather x from everywhere, with x larger than an XCD's L2: the

@@ -818,17 +818,28 @@ union Pack16 {
   T v[PB / sizeof(T)];
 };
 
-// The FP32 + BF16 pair of x: hi = x rounded to binary32, lo = the remainder
-// x - hi (exact in FP64) rounded to bfloat16 through binary32, both to
-// nearest even; the stored value hi + lo is within 2^-32 |x| of x.
-__device__ __forceinline__ void split_pair(double x, float& hi, bf16_t& lo) {
+// The pair basis stores x as hi, its binary32 rounding, and lo, a 16-bit
+// signed integer: the remainder x - hi (exact in FP64) in units of
+// delta = 2^-15 ulp(hi), rounded to nearest even, where ulp(hi) =
+// 2^(max(e, 1) - 150) for the biased binary32 exponent e of hi.  |x - hi| <=
+// ulp(hi) / 2, so |lo| <= 2^14; the stored value hi + lo delta (exact in
+// FP64) is within delta / 2 <= 2^-39 |hi| of x.
+// pair_unit(hi, s) = 2^(s (max(e, 1) - 165)) as a double: delta for s = 1,
+// 1 / delta for s = -1 (built from its exponent bits; always a normal double).
+__device__ __forceinline__ double pair_unit(float hi, int s) {
+  const int e = (int)((__float_as_uint(hi) >> 23) & 0xFFu);
+  const int k = s * ((e > 1 ? e : 1) - 165);
+  return __longlong_as_double((long long)((unsigned long long)(k + 1023) << 52));
+}
+__device__ __forceinline__ double pair_val(float hi, int16_t lo) { return (double)hi + (double)lo * pair_unit(hi, 1); }
+__device__ __forceinline__ void split_pair(double x, float& hi, int16_t& lo) {
   hi = (float)x;
-  lo = Conv<bf16_t>::st(x - (double)hi);
+  lo = (int16_t)__builtin_rint((x - (double)hi) * pair_unit(hi, -1));
 }
 
-// One packet of a basis column: PB bytes of TV values and, for the FP32 + BF16
-// pair basis (SPLIT, TV = float), the bfloat16 remainders of the same rows
-// from the second array (PB / 2 bytes); the value of a row is hi + lo.
+// One packet of a basis column: PB bytes of TV values and, for the pair basis
+// (SPLIT, TV = float), the 16-bit remainders of the same rows from the second
+// array (PB / 2 bytes); the value of a row is pair_val(hi, lo).
 template <typename TV, int PB, bool SPLIT>
 struct ColPk {
   typedef typename RawOf<PB>::type Raw;
@@ -836,14 +847,14 @@ struct ColPk {
   Pack16<TV, PB> h;
   union {
     RawL raw;
-    bf16_t v[SPLIT ? PB / 4 : 2];
+    int16_t v[SPLIT ? PB / 4 : 2];
   } l;
-  __device__ __forceinline__ void load(const TV* hi, const bf16_t* lo, int64_t off) {
+  __device__ __forceinline__ void load(const TV* hi, const int16_t* lo, int64_t off) {
     h.raw = __builtin_nontemporal_load((const Raw*)(hi + off));
     if constexpr (SPLIT) l.raw = __builtin_nontemporal_load((const RawL*)(lo + off));
   }
   __device__ __forceinline__ double val(int r) const {
-    if constexpr (SPLIT) return (double)h.v[r] + Conv<bf16_t>::ld(l.v[r]);
+    if constexpr (SPLIT) return pair_val(h.v[r], l.v[r]);
     else return Conv<TV>::ld(h.v[r]);
   }
   // stores a (rounded to the basis format) as row r of the packet
@@ -855,7 +866,7 @@ struct ColPk {
 
 // u~ = coef[ncol] * w - sum_{l < ncol} coef[l] U(:, l), stored (rounded to the
 // basis precision) as the new column; partials of Omega of the stored value.
-// SPLIT: the basis is the FP32 + BF16 pair (U, Ulo; the new column to unew,
+// SPLIT: the basis is the pair basis (U, Ulo; the new column to unew,
 // unew_lo), and the stored value of the new column also goes to xout in FP64
 // (the next product with A reads it there).
 // Each thread owns V consecutive rows and streams every basis column once
@@ -876,8 +887,8 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
                                             const TW* __restrict__ w, const double* __restrict__ coef,
                                             TV* __restrict__ unew, double* __restrict__ spart, SketchP sp,
                                             double* bins, const typename RawOf<PB>::type* pre = nullptr,
-                                            bool use_pre = false, const bf16_t* __restrict__ Ulo = nullptr,
-                                            bf16_t* __restrict__ unew_lo = nullptr, double* __restrict__ xout = nullptr) {
+                                            bool use_pre = false, const int16_t* __restrict__ Ulo = nullptr,
+                                            int16_t* __restrict__ unew_lo = nullptr, double* __restrict__ xout = nullptr) {
   // pre: NPRE leading basis columns, then (PREW) the w chunks, of the first packet
   typedef typename RawOf<PB>::type Raw;
   constexpr int V = PB / sizeof(TV);
@@ -903,7 +914,7 @@ __device__ __forceinline__ void update_body(int64_t n, int64_t npk, int ncol, co
         for (int r = 0; r < WV; ++r) a[c * WV + r] = ws * (double)wp[c].v[r];
     }
     const TV* col0 = U + i0;
-    const bf16_t* col0l = SPLIT ? Ulo + i0 : nullptr;
+    const int16_t* col0l = SPLIT ? Ulo + i0 : nullptr;
     int l = 0;
     if (NPRE > 0 && use_pre) {  // the first packet's leading columns, loaded before the least squares
 #pragma unroll
@@ -1007,7 +1018,7 @@ __global__ __launch_bounds__(1024) void k_ls_update(int t, int d, int pending, c
                                                    int64_t n, int64_t npk, const TV* __restrict__ U, int64_t ldu,
                                                    const TW* __restrict__ w, TV* __restrict__ unew,
                                                    double* __restrict__ spart, SketchP sp,
-                                                   const bf16_t* __restrict__ Ulo, bf16_t* __restrict__ unew_lo,
+                                                   const int16_t* __restrict__ Ulo, int16_t* __restrict__ unew_lo,
                                                    double* __restrict__ xout) {
   extern __shared__ double smem[];
   double* hc = smem;
@@ -1148,13 +1159,13 @@ __global__ void k_ks_finalize(int t, const double* __restrict__ h, const double*
 // First column: u0 (device FP64) or a seeded N(0,1) vector (Philox counter
 // (i, c2, tag): tag 2 the start vector, tag 3 the replacement after a
 // breakdown), stored in TV when `store`; partials of Omega of the stored value.
-// SPLIT (TV = float): stored as the FP32 + BF16 pair (u, ulo), the stored
+// SPLIT (TV = float): stored as the pair (u, ulo; see split_pair), the stored
 // value also to xout in FP64.
 template <typename TV, int KIND, bool SPLIT = false>
 __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, const double* __restrict__ u0,
                                               uint32_t s0, uint32_t s1, uint32_t c2, uint32_t tag,
                                               double* __restrict__ spart, SketchP sp, int store,
-                                              bf16_t* __restrict__ ulo = nullptr, double* __restrict__ xout = nullptr) {
+                                              int16_t* __restrict__ ulo = nullptr, double* __restrict__ xout = nullptr) {
   extern __shared__ double bins[];  // 8 waves x d (none for KIND 3)
   if (KIND != 3) bins_zero(bins, sp.d);
   __syncthreads();
@@ -1172,9 +1183,9 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
     double vs;
     if constexpr (SPLIT) {
       float hi;
-      bf16_t lo;
+      int16_t lo;
       split_pair(v, hi, lo);
-      vs = (double)hi + Conv<bf16_t>::ld(lo);
+      vs = pair_val(hi, lo);
       if (store) {
         u[i] = hi;
         ulo[i] = lo;
@@ -1213,8 +1224,8 @@ __global__ __launch_bounds__(512) void k_init(int64_t n, TV* __restrict__ u, con
 // inputs); stores skip rows >= n.  The wave reads every input column of its
 // rows before it writes any output, so outputs may overlap inputs (in-place
 // restart); optionally U(:, xdst) = xscale * U(:, xsrc) as well.
-// SPLIT: the input is the FP32 + BF16 pair basis (U, Ulo; TI = float), and
-// an FP32 output (TO = float) is stored as pairs too (O, Olo); the column
+// SPLIT: the input is the pair basis (U, Ulo; TI = float; see split_pair),
+// and an FP32 output (TO = float) is stored as pairs too (O, Olo); the column
 // U(:, xdst) is then also written to xcur in FP64.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -1250,12 +1261,12 @@ __host__ __device__ constexpr int rot_rows(int nt) {
 template <typename TI, typename TO, int NT, bool YG, int R, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLIT && NT >= 7) ? 1 : 3))) void k_rotate(int64_t n, const TI* U, int64_t ldu, int in0, int min, TO* O,
                                                 int64_t ldo, int out0, int kout, const double* __restrict__ Y,
-                                                int xsrc, int xdst, double xscale, const bf16_t* Ulo, bf16_t* Olo,
+                                                int xsrc, int xdst, double xscale, const int16_t* Ulo, int16_t* Olo,
                                                 double* __restrict__ xcur) {
   extern __shared__ double Ys[];  // minp x (16 NT), zero padded (unused when YG)
   constexpr int KC = 16 * NT;
   constexpr bool SO = SPLIT && sizeof(TO) == 4;  // pair output
-  constexpr int RL = SPLIT ? R : 1;              // bfloat16 parts per lane
+  constexpr int RL = SPLIT ? R : 1;              // 16-bit parts per lane
   const int minp = (min + 15) & ~15;
   if (!YG) {
     for (int idx = threadIdx.x; idx < minp * KC; idx += blockDim.x) {
@@ -1273,10 +1284,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLI
     const int64_t row = tile * 16 * R + (int64_t)R * lr;  // this lane's first row
     const bool full = row + R <= n;
     RowPack<TI, R> xe;
-    RowPack<bf16_t, RL> xel;
+    RowPack<int16_t, RL> xel;
     if (xsrc >= 0 && lk == 0) {
       xe = *(const RowPack<TI, R>*)(U + row + (int64_t)xsrc * ldu);
-      if constexpr (SPLIT) xel = *(const RowPack<bf16_t, R>*)(Ulo + row + (int64_t)xsrc * ldu);
+      if constexpr (SPLIT) xel = *(const RowPack<int16_t, R>*)(Ulo + row + (int64_t)xsrc * ldu);
     }
     f64x4 acc[R][NT];
 #pragma unroll
@@ -1284,21 +1295,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLI
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[r][t] = (f64x4){0.0, 0.0, 0.0, 0.0};
     const TI* urow = U + row + (int64_t)in0 * ldu;
-    const bf16_t* urowl = SPLIT ? Ulo + row + (int64_t)in0 * ldu : nullptr;
+    const int16_t* urowl = SPLIT ? Ulo + row + (int64_t)in0 * ldu : nullptr;
     for (int k0 = 0; k0 < minp; k0 += 16) {
       RowPack<TI, R> a[4];
-      RowPack<bf16_t, RL> al[4];
+      RowPack<int16_t, RL> al[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int kk = k0 + 4 * s + lk;
         if (kk < min) {
           a[s] = *(const RowPack<TI, R>*)(urow + (int64_t)kk * ldu);
-          if constexpr (SPLIT) al[s] = *(const RowPack<bf16_t, R>*)(urowl + (int64_t)kk * ldu);
+          if constexpr (SPLIT) al[s] = *(const RowPack<int16_t, R>*)(urowl + (int64_t)kk * ldu);
         } else {
 #pragma unroll
           for (int r = 0; r < R; ++r) a[s].v[r] = Conv<TI>::st(0.0);
 #pragma unroll
-          for (int r = 0; r < RL; ++r) al[s].v[r].b = 0;
+          for (int r = 0; r < RL; ++r) al[s].v[r] = 0;
         }
       }
 #pragma unroll
@@ -1314,8 +1325,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLI
           }
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            double uv = Conv<TI>::ld(a[s].v[r]);
-            if constexpr (SPLIT) uv += Conv<bf16_t>::ld(al[s].v[r]);
+            double uv;
+            if constexpr (SPLIT) uv = pair_val(a[s].v[r], al[s].v[r]);
+            else uv = Conv<TI>::ld(a[s].v[r]);
             acc[r][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv, uv, acc[r][t], 0, 0, 0);
           }
         }
@@ -1329,14 +1341,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLI
         if (oc >= kout) continue;
         TO* dst = O + row + (int64_t)(out0 + oc) * ldo;
         if constexpr (SO) {
-          bf16_t* dstl = Olo + row + (int64_t)(out0 + oc) * ldo;
+          int16_t* dstl = Olo + row + (int64_t)(out0 + oc) * ldo;
           RowPack<float, R> o;
-          RowPack<bf16_t, R> ol;
+          RowPack<int16_t, R> ol;
 #pragma unroll
           for (int r = 0; r < R; ++r) split_pair(acc[r][t][i], o.v[r], ol.v[r]);
           if (full && vec_out) {
             *(RowPack<float, R>*)dst = o;
-            *(RowPack<bf16_t, R>*)dstl = ol;
+            *(RowPack<int16_t, R>*)dstl = ol;
           } else {
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -1364,11 +1376,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(YG || (SPLI
         if (row + r >= n) continue;
         if constexpr (SPLIT) {
           float hi;
-          bf16_t lo;
-          split_pair(((double)xe.v[r] + Conv<bf16_t>::ld(xel.v[r])) * xscale, hi, lo);
+          int16_t lo;
+          split_pair(pair_val(xe.v[r], xel.v[r]) * xscale, hi, lo);
           xd[r] = hi;
-          ((bf16_t*)Ulo)[row + r + (int64_t)xdst * ldu] = lo;
-          xcur[row + r] = (double)hi + Conv<bf16_t>::ld(lo);
+          ((int16_t*)Ulo)[row + r + (int64_t)xdst * ldu] = lo;
+          xcur[row + r] = pair_val(hi, lo);
         } else {
           xd[r] = Conv<TI>::st(Conv<TI>::ld(xe.v[r]) * xscale);
         }
@@ -1661,8 +1673,8 @@ static void ls_update_t(const LaunchEnv& e, dim3 grid, size_t lds, int t, int pe
                         const double* sraw, double* S, double* B, int ldb, double* E, double* cs, double* coef,
                         double* scal, int* flags, double bd_rel, int64_t npk, const void* U, int64_t ldu,
                         const void* w, void* unew, double* spart) {
-  const bf16_t* Ulo = SPLIT ? e.lo_of(U) : nullptr;
-  bf16_t* unew_lo = SPLIT ? e.lo_of(unew) : nullptr;
+  const int16_t* Ulo = SPLIT ? e.lo_of(U) : nullptr;
+  int16_t* unew_lo = SPLIT ? e.lo_of(unew) : nullptr;
   double* xout = SPLIT ? e.xcur : nullptr;
   RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_ls_update<TV, TW, KIND, PRE, PB, ROLL, SPLIT>, lds);
                     launch_k(e, true, e.sp_kind != 0, k_ls_update<TV, TW, KIND, PRE, PB, ROLL, SPLIT>, grid, dim3(1024),
@@ -1763,8 +1775,8 @@ static void rotate_nt(const LaunchEnv& e, const TI* U, int64_t ldu, int in0, int
   const size_t lds = (size_t)((min + 15) & ~15) * 16 * NT * 8;
   // the pair basis: the bfloat16 parts of the input, of an FP32 output, and
   // the FP64 copy of the column xdst
-  const bf16_t* Ulo = SPLIT ? e.lo_of(U) : nullptr;
-  bf16_t* Olo = SPLIT && sizeof(TO) == 4 ? e.lo_of(O) : nullptr;
+  const int16_t* Ulo = SPLIT ? e.lo_of(U) : nullptr;
+  int16_t* Olo = SPLIT && sizeof(TO) == 4 ? e.lo_of(O) : nullptr;
   double* xcur = SPLIT && xsrc >= 0 ? e.xcur : nullptr;
   if (lds > kRotLdsMax) {
     launch_k(e, true, true, k_rotate<TI, TO, NT, true, R, SPLIT>, dim3(G), dim3(256), 0, e.n, U, ldu, in0, min, O,

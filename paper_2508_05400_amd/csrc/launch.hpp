@@ -11,7 +11,7 @@ namespace rks {
 struct LaunchEnv {
   hipStream_t stream;
   int64_t n;
-  int prec;            // 0 FP64 basis, 1 FP32 basis, 2 BF16 basis, 3 FP32 + BF16 pair basis
+  int prec;            // 0 FP64 basis, 1 FP32 basis, 2 BF16 basis, 3 pair basis (FP32 + 16-bit remainder)
   const int* rp;       // CSR row pointers (device)
   const int* col;      // CSR columns (device)
   const double* val;   // FP64 values (device)
@@ -39,13 +39,13 @@ struct LaunchEnv {
   hipEvent_t ev0 = nullptr;
   hipEvent_t ev1 = nullptr;
   // the pair basis (prec 3): the FP32 parts at pair_hi (the basis pointer the
-  // launchers get), the bfloat16 parts of the same elements at pair_lo, and
+  // launchers get), the 16-bit remainders of the same elements at pair_lo, and
   // xcur (ldu FP64 values, padding rows zero), the FP64 copy of the column
   // written last, which the SpMV of the next step reads
   const float* pair_hi = nullptr;
-  bf16_t* pair_lo = nullptr;
+  int16_t* pair_lo = nullptr;
   double* xcur = nullptr;
-  bf16_t* lo_of(const void* hi) const { return pair_lo + ((const float*)hi - pair_hi); }
+  int16_t* lo_of(const void* hi) const { return pair_lo + ((const float*)hi - pair_hi); }
   // bytes between consecutive rows of a basis column (the pair basis: of its FP32 part)
   int vbytes() const { return prec == 0 ? 8 : (prec == 2 ? 2 : 4); }
 };

@@ -62,7 +62,7 @@ struct rks_ctx {
   rks::LaunchEnv env{};
   int vbytes = 8, wbytes = 8;  // bytes between rows of a basis column (the pair basis: its FP32 part), of w
   int ebytes = 8;              // HBM bytes of one basis element (the pair basis: 4 + 2)
-  bool pair = false;           // FP32 + BF16 pair basis
+  bool pair = false;           // pair basis (FP32 + 16-bit remainder)
   int64_t ldu = 0;
   // device buffers
   int *rp = nullptr, *col = nullptr, *tiles = nullptr, *flags = nullptr;
@@ -70,7 +70,7 @@ struct rks_ctx {
   float* val32 = nullptr;
   void* U = nullptr;      // basis in use (U_lo or U64)
   void* U_lo = nullptr;   // basis in the requested precision (allocated at create; the pair
-                          // basis: the FP32 parts, then the bfloat16 parts of the same elements)
+                          // basis: the FP32 parts, then the 16-bit remainders of the same elements)
   double* xcur = nullptr; // pair basis: FP64 copy of the column written last (ldu values)
   void* U64 = nullptr;    // FP64 basis of the refinement phase (lazy)
   void* w = nullptr;
@@ -901,7 +901,7 @@ int verified_max_resid(rks_ctx* c, double* out) {
 // Switch the basis in use between the requested precision and FP64.
 int set_basis(rks_ctx* c, int prec) {
   c->env.prec = prec;
-  c->pair = prec == RKS_PREC_V32_BF16;
+  c->pair = prec == RKS_PREC_V32_FX16;
   c->vbytes = (prec == RKS_PREC_FP64) ? 8 : (prec == RKS_PREC_VBF16 ? 2 : 4);
   c->ebytes = c->pair ? 6 : c->vbytes;
   c->wbytes = (prec == RKS_PREC_FP64 || c->pair) ? 8 : 4;
@@ -1210,7 +1210,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     delete c;
     return fail(nullptr, RKS_EINVAL, why);
   }
-  const bool pair = o.precision == RKS_PREC_V32_BF16;
+  const bool pair = o.precision == RKS_PREC_V32_FX16;
   const bool low = o.precision == RKS_PREC_V32 || o.precision == RKS_PREC_VBF16;  // FP32 copies of A's values
   const int ebytes = o.precision == RKS_PREC_FP64 ? 8 : (pair ? 6 : (o.precision == RKS_PREC_V32 ? 4 : 2));
   c->ldu = (n + 127) / 128 * 128;
@@ -1333,7 +1333,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.prec = o.precision;
   if (pair) {
     e.pair_hi = (const float*)c->U_lo;
-    e.pair_lo = (rks::bf16_t*)((char*)c->U_lo + (size_t)c->ldu * (m + 1) * 4);
+    e.pair_lo = (int16_t*)((char*)c->U_lo + (size_t)c->ldu * (m + 1) * 4);
     e.xcur = c->xcur;
   }
   e.rp = c->rp;
@@ -1388,7 +1388,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   c->st = st;
   const auto t0 = std::chrono::steady_clock::now();
   set_basis(c, c->o.precision);
-  // (the pair basis runs one phase: its stored values carry 32 bits of
+  // (the pair basis runs one phase: its stored values carry 39 bits of
   // significand, which the verified FP64 residual does not need refined)
   const bool mixed = c->o.precision == RKS_PREC_V32 || c->o.precision == RKS_PREC_VBF16;
   const bool refine = mixed && c->o.refine;
@@ -1552,7 +1552,7 @@ int rks_get_state(rks_ctx* c, int32_t* ncols, double* B, double* S, double* U) {
   if (U) {
     const size_t colb = (size_t)c->ldu * c->vbytes;
     std::vector<unsigned char> buf(colb);
-    std::vector<uint16_t> lo(c->pair ? c->ldu : 0);
+    std::vector<int16_t> lo(c->pair ? c->ldu : 0);
     auto bf16 = [](uint16_t h) {
       const uint32_t u = (uint32_t)h << 16;
       float f;
@@ -1577,7 +1577,12 @@ int rks_get_state(rks_ctx* c, int32_t* ncols, double* B, double* S, double* U) {
           float f;
           std::memcpy(&f, &buf[i * 4], 4);
           v = f;
-          if (c->pair) v += bf16(lo[i]);  // the stored value hi + lo
+          if (c->pair) {  // the stored value hi + lo 2^-15 ulp(hi)
+            uint32_t hb;
+            std::memcpy(&hb, &f, 4);
+            const int ex = (int)((hb >> 23) & 0xFFu);
+            v += std::ldexp((double)lo[i], std::max(ex, 1) - 165);
+          }
         } else {
           uint16_t h;
           std::memcpy(&h, &buf[i * 2], 2);

@@ -170,7 +170,7 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
 def test_binding_enum_names_match_the_header(tmp_path):
     """The binding's string names for which, sketch kind, basis precision,
     SpMV layout and method map to the header's enum values (the precision
-    names include the pair basis, "fp32+bf16")."""
+    names include the pair basis, "fp32+fx16")."""
     import shutil
     import subprocess
     from paper_2508_05400_amd import _binding as B
@@ -180,7 +180,7 @@ def test_binding_enum_names_match_the_header(tmp_path):
         ("which", "LM"): "RKS_LM", ("which", "SM"): "RKS_SM", ("which", "LR"): "RKS_LR", ("which", "SR"): "RKS_SR",
         ("sketch", "gauss"): "RKS_SKETCH_GAUSS", ("sketch", "sparse"): "RKS_SKETCH_SPARSE",
         ("precision", "fp64"): "RKS_PREC_FP64", ("precision", "fp32"): "RKS_PREC_V32",
-        ("precision", "bf16"): "RKS_PREC_VBF16", ("precision", "fp32+bf16"): "RKS_PREC_V32_BF16",
+        ("precision", "bf16"): "RKS_PREC_VBF16", ("precision", "fp32+fx16"): "RKS_PREC_V32_FX16",
         ("layout", "auto"): "RKS_SPMV_AUTO", ("layout", "rows"): "RKS_SPMV_ROWS",
         ("layout", "column_blocks"): "RKS_SPMV_COLUMN_BLOCKS",
         ("method", "rks"): "RKS_METHOD_RKS", ("method", "ks_cgs2"): "RKS_METHOD_KS_CGS2",
