@@ -242,6 +242,9 @@ def main():
                     help="time the kernels of every P-th Arnoldi step with HIP events (the events "
                          "around whole steps cost a few microseconds each, so the sample is sparse)")
     ap.add_argument("--keep", default="auto", help="restart size: auto (k + (m-k)/4), or a number in [k, m-2]")
+    ap.add_argument("--a-values", default="auto", choices=["auto", "fp64"],
+                    help="storage of A's values for the FP64 product: auto (one-byte indices into the table of "
+                         "distinct values when there are at most 256; bit-identical products) or fp64")
     ap.add_argument("--refine", type=int, default=1, help="low-precision main run: 1 = FP64 refinement phase, "
                     "0 = none (the run stops at its own verified residual --resid-tol)")
     ap.add_argument("--graphs", type=int, default=0, help="1: replay repeated extensions as HIP graphs (used only "
@@ -286,7 +289,7 @@ def main():
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else args.profile_every,
                                resid_tol=args.resid_tol, keep=keep, graphs=args.graphs, refine=args.refine,
-                               stream=stream)
+                               a_values=args.a_values, stream=stream)
     for _ in range(args.warmup):
         solver.solve()
     torch.cuda.synchronize()
@@ -355,6 +358,8 @@ def main():
         "max_est": st["max_est"],
         "loop_gbs": loop_gbs,
         "spmv_layout": {1: "rows", 2: "column_blocks"}.get(st["spmv_layout"], "?"),
+        "a_values": (f"value-indexed: {st['a_distinct']} distinct values, a 1-byte index per nonzero"
+                     if st["a_distinct"] else "fp64"),
         "kernel_avg_us": _kernel_avg_us(st),
         "step_avg_us": st["t_step"] / max(st["n_timed_whole"], 1) * 1e6,
         "timed_sample": (f"HIP events on every {args.profile_every}th Arnoldi step inside the timed solves, "
@@ -387,7 +392,7 @@ def main():
                                start_seed=cfg["start_seed"], precision=vprec, keep=0 if prec == "alg1" else keep,
                                method=method, lock=vlock,
                                max_restarts=cfg.get("max_restarts", 300),
-                               resid_tol=0.0 if prec == "eta" else args.resid_tol,
+                               resid_tol=0.0 if prec == "eta" else args.resid_tol, a_values=args.a_values,
                                profile=0 if args.no_profile else args.profile_every, stream=stream) as s2:
             if not slow:
                 s2.solve()

@@ -84,6 +84,19 @@ typedef enum { RKS_SPMV_AUTO = 0, RKS_SPMV_ROWS = 1, RKS_SPMV_COLUMN_BLOCKS = 2 
  * options are ignored. */
 typedef enum { RKS_METHOD_RKS = 0, RKS_METHOD_KS_CGS2 = 1 } rks_method;
 
+/* Storage of A's values for the FP64 product (FP64 and pair bases, and the
+ * FP64 residual checks) in the row-tile layout.  AUTO: when A has at most
+ * 256 distinct values (compared bit for bit), each nonzero stores a one-byte
+ * index into the table of those values instead of the 8-byte value (a
+ * value-indexed CSR, as in Kourtis, Goumas and Koziris, "Optimizing sparse
+ * matrix-vector multiplication using index and value compression", 2008);
+ * the SpMV looks the values up in a copy of the table in LDS and forms the
+ * same FP64 products, so results are identical to the bit.  Constant-
+ * coefficient stencils have a handful of values; matrices with more than 256
+ * keep FP64 values.  FP64: always 8-byte values.  The FP32 and BF16 bases'
+ * binary32 product and the column-blocked layout always store values. */
+typedef enum { RKS_AVALUES_AUTO = 0, RKS_AVALUES_FP64 = 1 } rks_a_values;
+
 /* rks_opts.keep: restart size chosen from k and m (see the field). */
 #define RKS_KEEP_AUTO (-1)
 
@@ -155,6 +168,9 @@ typedef struct {
                             estimate |b^T y| / |lambda| has not fallen below half of its
                             level S restarts earlier (stagnation, as on operators whose
                             wanted eigenvalues are packed together); 0 = off (default) */
+  int32_t a_values;      /* rks_a_values: storage of A's values for the FP64 product,
+                            default AUTO (value-indexed when A has at most 256
+                            distinct values) */
 } rks_opts;
 
 /* Fills *o with the defaults listed above. */
@@ -195,6 +211,9 @@ typedef struct {
   int32_t spmv_layout;       /* rks_spmv_layout in use (ROWS or COLUMN_BLOCKS) */
   int32_t keep;              /* restart size in use */
   double hist_est[512];  /* max estimate after contraction r (r < 512) */
+  int32_t a_distinct;    /* distinct values of A in the value table of the FP64
+                            product (value-indexed storage), 0 when it reads
+                            FP64 values */
 } rks_stats;
 
 /* Create a solver for k eigenpairs of A with Krylov dimension m and sketch

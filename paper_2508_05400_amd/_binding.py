@@ -19,6 +19,7 @@ SKETCH = {"gauss": 0, "sparse": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "v32": 1, "bf16": 2, "vbf16": 2, "fp32+fx16": 3, "v32_fx16": 3}
 SPMV_LAYOUT = {"auto": 0, "rows": 1, "column_blocks": 2}
 METHOD = {"rks": 0, "ks_cgs2": 1}
+A_VALUES = {"auto": 0, "fp64": 1}
 
 
 class RksCsr(ctypes.Structure):
@@ -35,7 +36,7 @@ class RksOpts(ctypes.Structure):
                 ("resid_tol", ctypes.c_double), ("refine", ctypes.c_int32),
                 ("refine_tol", ctypes.c_double), ("spmv_layout", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("keep", ctypes.c_int32), ("graphs", ctypes.c_int32),
-                ("stall_restarts", ctypes.c_int32)]
+                ("stall_restarts", ctypes.c_int32), ("a_values", ctypes.c_int32)]
 
 
 class RksStats(ctypes.Structure):
@@ -56,7 +57,7 @@ class RksStats(ctypes.Structure):
                 ("bytes_timed_update", ctypes.c_double), ("bytes_timed_rotate", ctypes.c_double),
                 ("n_timed_whole", ctypes.c_int64), ("t_step", ctypes.c_double),
                 ("bytes_timed_whole", ctypes.c_double), ("spmv_layout", ctypes.c_int32),
-                ("keep", ctypes.c_int32), ("hist_est", ctypes.c_double * 512)]
+                ("keep", ctypes.c_int32), ("hist_est", ctypes.c_double * 512), ("a_distinct", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         out = {f: getattr(self, f) for f, _ in self._fields_ if f != "hist_est"}
@@ -168,6 +169,8 @@ def rks_opts_default(**kw) -> RksOpts:
             v = SPMV_LAYOUT[v]
         if k == "method" and isinstance(v, str):
             v = METHOD[v]
+        if k == "a_values" and isinstance(v, str):
+            v = A_VALUES[v]
         if k == "stream" and v is not None and not isinstance(v, int):
             v = int(v.cuda_stream)
         setattr(o, k, v)

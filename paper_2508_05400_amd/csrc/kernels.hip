@@ -88,11 +88,20 @@ __device__ __forceinline__ double* wave_bins(double* bins, int d) {
 // row longer than kTileFill nonzeros is reduced by the whole wave.  The row sum ends
 // in the lane with sub == 0 of row rr (< nr).  after_loads(rr, sub) runs while
 // the loads are in flight (independent work can hide under them).
-template <typename TV, typename TA, typename F>
+// TS: the stored values (TA itself), or one-byte indices into the table vt
+// of the matrix's distinct values (the FP64 product's value-indexed
+// storage; vt in LDS, 256 entries).
+template <typename TA, typename TS>
+__device__ __forceinline__ TA a_value(TS v, const double* vt) {
+  if constexpr (sizeof(TS) == 1) return (TA)vt[v];
+  else return (TA)v;
+}
+
+template <typename TV, typename TA, typename TS, typename F>
 __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* __restrict__ col,
-                                        const TA* __restrict__ val, const TV* __restrict__ x, int4 dsc, TA* pw,
-                                        int lane, int& rr, int& sub, F&& after_loads) {
-  typedef TA TA2 __attribute__((ext_vector_type(2)));
+                                        const TS* __restrict__ val, const double* vt, const TV* __restrict__ x,
+                                        int4 dsc, TA* pw, int lane, int& rr, int& sub, F&& after_loads) {
+  typedef TS TS2 __attribute__((ext_vector_type(2)));
   constexpr int NP = kTileNnz / 128;  // pairs per lane
   const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
   TA s = 0;
@@ -109,13 +118,13 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
     // pair p covers tile entries 2p - sh and 2p + 1 - sh (ne + sh <= 2 NP 64)
     const int e0a = e0 & ~1, sh = e0 - e0a, nea = ne + sh;
     int2 ci[NP];
-    TA2 vv[NP];
+    TS2 vv[NP];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int p2 = 2 * (lane + 64 * u);
       if (p2 < nea) {
         ci[u] = *(const int2*)(col + e0a + p2);
-        vv[u] = *(const TA2*)(val + e0a + p2);
+        vv[u] = *(const TS2*)(val + e0a + p2);
       }
     }
     after_loads(rr, sub);
@@ -132,8 +141,8 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
     for (int u = 0; u < NP; ++u) {
       const int p2 = 2 * (lane + 64 * u);
       if (p2 < nea) {
-        if (p2 >= sh) pw[p2 - sh] = vv[u].x * xa[u];
-        if (p2 + 1 < nea) pw[p2 + 1 - sh] = vv[u].y * xb[u];
+        if (p2 >= sh) pw[p2 - sh] = a_value<TA>(vv[u].x, vt) * xa[u];
+        if (p2 + 1 < nea) pw[p2 + 1 - sh] = a_value<TA>(vv[u].y, vt) * xb[u];
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -144,7 +153,7 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
   } else {
     rr = 0;
     sub = lane;
-    for (int e = lane; e < ne; e += 64) s += val[e0 + e] * (TA)Conv<TV>::ld(x[col[e0 + e]]);
+    for (int e = lane; e < ne; e += 64) s += a_value<TA>(val[e0 + e], vt) * (TA)Conv<TV>::ld(x[col[e0 + e]]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   }
   return s;
@@ -158,17 +167,23 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
 // (nonzeros, then the gathered x), so it wants many resident waves: small
 // workgroups (kSpmvWaves waves, each with its LDS slice and d sketch bins)
 // let five of them share a CU, where two 8-wave workgroups fit before.
-template <typename TV, typename TW, typename TA, int KIND>
+// TS = uint8_t: A's values as one-byte indices into vtab (256 FP64 entries,
+// copied to LDS first); otherwise vtab is unused.
+template <typename TV, typename TW, typename TA, int KIND, typename TS = TA>
 __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
-                                                     const TA* __restrict__ val, const int4* __restrict__ tdesc,
-                                                     int ntiles, const TV* __restrict__ x, TW* __restrict__ w,
+                                                     const TS* __restrict__ val, const double* __restrict__ vtab,
+                                                     const int4* __restrict__ tdesc, int ntiles,
+                                                     const TV* __restrict__ x, TW* __restrict__ w,
                                                      double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
   extern __shared__ double bins[];  // kSpmvWaves waves x d
   __shared__ TA prod[kSpmvWaves][kTileNnz];
+  __shared__ double vt[sizeof(TS) == 1 ? 256 : 1];
   const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (do_sketch) bins_zero(bins, sp.d);
+  if constexpr (sizeof(TS) == 1)
+    for (int i = tid; i < 256; i += 64 * kSpmvWaves) vt[i] = vtab[i];
   __syncthreads();
   TA* pw = prod[wv];
   double* wb = wave_bins(bins, sp.d);
@@ -193,7 +208,7 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
     int have = 0;
     // the row's sketch column does not depend on the data: hash it while the
     // tile's loads are in flight
-    const TA s = tile_rows<TV, TA>(rp, col, val, x, dsc, pw, lane, rr, sub, [&](int r_, int s_) {
+    const TA s = tile_rows<TV, TA, TS>(rp, col, val, vt, x, dsc, pw, lane, rr, sub, [&](int r_, int s_) {
       if (KIND == 1 && do_sketch && r_ < dsc.y && s_ == 0) {
         sparse_column((uint64_t)(dsc.x + r_), sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
         have = 1;
@@ -1597,21 +1612,26 @@ int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart
   if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the tile mapping)
   dim3 grid(G), block(64 * kSpmvWaves);
   const size_t lds = bins_lds(e, kSpmvWaves, do_sketch && e.sp_kind == 1);
-  if (prec == 0) {
+  if (prec == 0 && e.vidx) {  // value-indexed FP64 product
+    RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<double, double, double, KIND, uint8_t>, lds);
+                      launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<double, double, double, KIND, uint8_t>,
+                               grid, block, lds, e.rp, e.col, e.vidx, e.vtab, (const int4*)e.tiles, e.ntiles,
+                               (const double*)x, (double*)w, zpart, e.sp, do_sketch));
+  } else if (prec == 0) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<double, double, double, KIND>, lds);
                       launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<double, double, double, KIND>, grid, block, lds,
-                               e.rp, e.col, e.val, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w, zpart,
-                               e.sp, do_sketch));
+                               e.rp, e.col, e.val, nullptr, (const int4*)e.tiles, e.ntiles, (const double*)x, (double*)w,
+                               zpart, e.sp, do_sketch));
   } else if (prec == 1) {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<float, float, float, KIND>, lds);
                       launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<float, float, float, KIND>, grid, block, lds,
-                               e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w, zpart,
-                               e.sp, do_sketch));
+                               e.rp, e.col, e.val32, nullptr, (const int4*)e.tiles, e.ntiles, (const float*)x, (float*)w,
+                               zpart, e.sp, do_sketch));
   } else {
     RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sketch<bf16_t, float, float, KIND>, lds);
                       launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sketch<bf16_t, float, float, KIND>, grid, block, lds,
-                               e.rp, e.col, e.val32, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w, zpart,
-                               e.sp, do_sketch));
+                               e.rp, e.col, e.val32, nullptr, (const int4*)e.tiles, e.ntiles, (const bf16_t*)x, (float*)w,
+                               zpart, e.sp, do_sketch));
   }
   if (do_sketch && e.sp_kind == 0)
     return prec == 0 ? gauss_t<double>(e, (const double*)w, zpart) : gauss_t<float>(e, (const float*)w, zpart);

@@ -16,6 +16,11 @@ struct LaunchEnv {
   const int* col;      // CSR columns (device)
   const double* val;   // FP64 values (device)
   const float* val32;  // FP32 values (device, mixed precision only)
+  // value-indexed storage of A for the FP64 product (row tiles; null when
+  // unused): one byte per nonzero indexing vtab, the matrix's distinct FP64
+  // values (256 entries, unused ones zero)
+  const uint8_t* vidx = nullptr;
+  const double* vtab = nullptr;
   const int* tiles;    // SpMV wave tiles: {first row, rows, first nonzero, nonzeros} per tile
   int ntiles;
   int64_t ldu;         // basis leading dimension (n rounded up to 128; padding rows are zero)

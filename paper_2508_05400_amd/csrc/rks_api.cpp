@@ -68,6 +68,9 @@ struct rks_ctx {
   int *rp = nullptr, *col = nullptr, *tiles = nullptr, *flags = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
+  uint8_t* vidx = nullptr;  // value-indexed A (FP64 product): one byte per nonzero
+  double* vtab = nullptr;   // its table of distinct values (256 entries)
+  int a_distinct = 0;       // distinct values in vtab (0: FP64 values)
   void* U = nullptr;      // basis in use (U_lo or U64)
   void* U_lo = nullptr;   // basis in the requested precision (allocated at create; the pair
                           // basis: the FP32 parts, then the 16-bit remainders of the same elements)
@@ -221,9 +224,10 @@ void flush_events(rks_ctx* c) {
 }
 
 double spmv_bytes(const rks_ctx* c) {
-  // A's values in FP64 for an FP64 or pair basis (whose SpMV reads the FP64 copy of its column)
+  // A's values in FP64 for an FP64 or pair basis (whose SpMV reads the FP64 copy of its column),
+  // or their one-byte indices (value-indexed storage)
   const bool f64 = c->env.prec == RKS_PREC_FP64 || c->pair;
-  const double bval = f64 ? 8.0 : 4.0, xb = c->pair ? 8.0 : c->ebytes;
+  const double bval = f64 ? (c->env.vidx ? 1.0 : 8.0) : 4.0, xb = c->pair ? 8.0 : c->ebytes;
   return (bval + 4.0) * c->nnz + 4.0 * (c->n + 1) + (xb + c->wbytes) * c->n;
 }
 
@@ -1050,7 +1054,7 @@ void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->dstate, c->val, c->val32, c->U_lo, c->U64, c->w, c->xcur,
                  c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->kpart,
                  c->col_pn, c->tiles_pn, c->toff_pn, c->ptile, c->off_pn, c->val_pn, c->val32_pn,
-                 c->Xr, c->ax1, c->ax2, c->rpart};
+                 c->Xr, c->ax1, c->ax2, c->rpart, c->vidx, c->vtab};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {c->hstate, c->hY};
@@ -1112,10 +1116,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 3 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
       !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
-      o.method > 1 || o.graphs < 0 || o.graphs > 1 || o.stall_restarts < 0)
+      o.method > 1 || o.graphs < 0 || o.graphs > 1 || o.stall_restarts < 0 || o.a_values < 0 || o.a_values > 1)
     return fail(nullptr, RKS_EINVAL,
-                "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout, method, graphs or "
-                "stall_restarts");
+                "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout, method, graphs, "
+                "stall_restarts or a_values");
   int keep = o.keep == 0 ? k : o.keep;
   if (o.keep == RKS_KEEP_AUTO)
     keep = std::max(k, std::min({k + (m - k) / 4, m - 2, rks::kRotMax - 1}));
@@ -1212,6 +1216,30 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   }
   const bool pair = o.precision == RKS_PREC_V32_FX16;
   const bool low = o.precision == RKS_PREC_V32 || o.precision == RKS_PREC_VBF16;  // FP32 copies of A's values
+  // value-indexed storage for the FP64 product (row tiles): the table of
+  // distinct values (bit patterns, at most 256, kept sorted) and each
+  // nonzero's index into it
+  std::vector<uint64_t> vkeys;
+  std::vector<uint8_t> vind;
+  if (o.a_values == RKS_AVALUES_AUTO && !use_cb && nnz > 0) {
+    for (int64_t e = 0; e < nnz && vkeys.size() <= 256; ++e) {
+      uint64_t key;
+      std::memcpy(&key, &val[e], 8);
+      auto it = std::lower_bound(vkeys.begin(), vkeys.end(), key);
+      if (it == vkeys.end() || *it != key) vkeys.insert(it, key);
+    }
+    if (vkeys.size() <= 256) {
+      vind.resize(nnz);
+      for (int64_t e = 0; e < nnz; ++e) {
+        uint64_t key;
+        std::memcpy(&key, &val[e], 8);
+        vind[e] = (uint8_t)(std::lower_bound(vkeys.begin(), vkeys.end(), key) - vkeys.begin());
+      }
+    } else {
+      vkeys.clear();
+    }
+  }
+  const bool indexed = !vkeys.empty();
   const int ebytes = o.precision == RKS_PREC_FP64 ? 8 : (pair ? 6 : (o.precision == RKS_PREC_V32 ? 4 : 2));
   c->ldu = (n + 127) / 128 * 128;
   c->pair = pair;
@@ -1241,6 +1269,10 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   dm((void**)&c->col, nzp * 4);
   dm((void**)&c->val, nzp * 8);
   if (low) dm((void**)&c->val32, nzp * 4);
+  if (indexed) {
+    dm((void**)&c->vidx, nzp);
+    dm((void**)&c->vtab, 256 * 8);
+  }
   dm((void**)&c->tiles, tdesc.size() * 4);
   if (use_cb) {
     dm((void**)&c->col_pn, (size_t)nzp * 4);
@@ -1294,6 +1326,13 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     std::vector<float> v32(val.begin(), val.end());
     cp(c->val32, v32.data(), nnz * 4);
   }
+  if (indexed) {
+    std::vector<double> tab(256, 0.0);
+    for (size_t i = 0; i < vkeys.size(); ++i) std::memcpy(&tab[i], &vkeys[i], 8);
+    cp(c->vidx, vind.data(), nnz);
+    cp(c->vtab, tab.data(), 256 * 8);
+    c->a_distinct = (int)vkeys.size();
+  }
   cp(c->tiles, tdesc.data(), tdesc.size() * 4);
   if (use_cb) {
     cp(c->col_pn, pl.col.data(), (size_t)nnz * 4);
@@ -1314,6 +1353,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   zero_pad(c->col, 4);
   zero_pad(c->val, 8);
   zero_pad(c->val32, 4);
+  zero_pad(c->vidx, 1);
   zero_pad(c->col_pn, 4);
   zero_pad(c->val_pn, 8);
   zero_pad(c->val32_pn, 4);
@@ -1340,6 +1380,8 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.col = c->col;
   e.val = c->val;
   e.val32 = c->val32;
+  e.vidx = c->vidx;
+  e.vtab = c->vtab;
   e.tiles = c->tiles;
   e.ntiles = ntiles;
   if (use_cb) {
@@ -1439,6 +1481,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   st->locked = c->q;
   st->keff = c->kr;
   st->spmv_layout = c->env.cb ? RKS_SPMV_COLUMN_BLOCKS : RKS_SPMV_ROWS;
+  st->a_distinct = c->a_distinct;
   st->keep = c->keep;
   st->max_est = p1.maxest;
   st->t_host = p1.thost;

@@ -116,6 +116,74 @@ def test_spmv_sketch_parity(lib, cuda, case, layout):
         P.rks_destroy(ctx)
 
 
+def table_valued(A, nvals, seed):
+    """A's pattern with values drawn from nvals distinct random doubles, each
+    of them used (-0.0 and 0.0 among them: distinct bit patterns)."""
+    rng = np.random.default_rng(seed)
+    tab = rng.standard_normal(nvals)
+    tab[:2] = [0.0, -0.0]
+    idx = rng.integers(0, nvals, len(A.val))
+    idx[rng.permutation(len(A.val))[:nvals]] = np.arange(nvals)
+    return CSR(A.n, A.row_ptr, A.col, tab[idx], dict(A.meta, values=nvals))
+
+
+VIDX = {
+    # constant-coefficient stencil: 5 distinct values
+    "cd2d-37": (lambda: convdiff2d(37, (20.0, 10.0)), 5),
+    # the widest table (256 values, index 255 used), with empty rows and rows
+    # of 510, 511 and 700 nonzeros (the long-row path)
+    "longrows-256": (lambda: table_valued(long_rows(9001, 7), 256, 3), 256),
+    # one value too many: FP64 values
+    "longrows-257": (lambda: table_valued(long_rows(9001, 7), 257, 3), 0),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32+fx16"])
+@pytest.mark.parametrize("case", sorted(VIDX))
+def test_value_indexed_storage_is_bitwise_fp64(lib, cuda, case, prec):
+    """A matrix with at most 256 distinct values is stored value-indexed by
+    default (a one-byte index per nonzero into the table of its values); the
+    SpMV looks each value up and forms the same FP64 product, so the fused
+    SpMV + sketch (w, z), a whole extension (B, S, U) and a short solve
+    (Ritz values, residuals, restart and product counts) equal those with
+    a_values = 'fp64' to the last bit, on both bases whose product is FP64.
+    The statistics report the table size, 0 beyond 256 values."""
+    mk, nd = VIDX[case]
+    A = mk()
+    assert len(np.unique(A.val.view(np.uint64))) == (nd or 257)
+    k, m, d = 6, 24, 60
+    outs = {}
+    for av in ("auto", "fp64"):
+        ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
+                           P.rks_opts_default(sketch_seed=5, start_seed=1, precision=prec, a_values=av,
+                                              spmv_layout="rows"))
+        try:
+            x = start_vector_normal(A.n, 9)
+            w = cuda.zeros(A.n, dtype=cuda.float64, device="cuda")
+            z = cuda.zeros(d, dtype=cuda.float64, device="cuda")
+            P.rks_spmv_sketch(ctx, dev(cuda, x), w, z)
+            P.rks_arnoldi(ctx, None)
+            B = np.zeros((m + 1, m), order="F")
+            S = np.zeros((d, m + 1), order="F")
+            U = np.zeros((A.n, m + 1), order="F")
+            P.rks_get_state(ctx, B, S, U)
+        finally:
+            P.rks_destroy(ctx)
+        with P.Solver.from_csr(A, k=k, m=m, d=d, which="LM", tol=1e-10, sketch_seed=5, start_seed=1,
+                               precision=prec, a_values=av, spmv_layout="rows", max_restarts=4) as s:
+            assert s.solve() in (0, 1), P.rks_last_error(s.ctx)
+            st = (s.stats.restarts, s.stats.matvecs, s.stats.a_distinct)
+            lam, X, res = s.eigpairs()
+        outs[av] = (w.cpu().numpy(), z.cpu().numpy(), B, S, U, lam, X, res, st)
+    a, f = outs["auto"], outs["fp64"]
+    assert a[8][2] == nd and f[8][2] == 0
+    assert a[8][:2] == f[8][:2]
+    for ga, gf in zip(a[:8], f[:8]):
+        assert np.array_equal(ga, gf)
+    np.testing.assert_allclose(a[0], sp_of(A) @ start_vector_normal(A.n, 9), rtol=0,
+                               atol=64 * U64 * float((abs(sp_of(A)) @ np.abs(start_vector_normal(A.n, 9))).max()))
+
+
 ARN = {
     "cd2d-37-gauss": (lambda: convdiff2d(37, (20.0, 10.0)), "gauss", 8, 30, 62),
     "cd2d-37-sparse": (lambda: convdiff2d(37, (20.0, 10.0)), "sparse", 8, 30, 96),

@@ -169,7 +169,7 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
 
 def test_binding_enum_names_match_the_header(tmp_path):
     """The binding's string names for which, sketch kind, basis precision,
-    SpMV layout and method map to the header's enum values (the precision
+    SpMV layout, method and value storage map to the header's enum values (the precision
     names include the pair basis, "fp32+fx16")."""
     import shutil
     import subprocess
@@ -184,9 +184,10 @@ def test_binding_enum_names_match_the_header(tmp_path):
         ("layout", "auto"): "RKS_SPMV_AUTO", ("layout", "rows"): "RKS_SPMV_ROWS",
         ("layout", "column_blocks"): "RKS_SPMV_COLUMN_BLOCKS",
         ("method", "rks"): "RKS_METHOD_RKS", ("method", "ks_cgs2"): "RKS_METHOD_KS_CGS2",
+        ("a_values", "auto"): "RKS_AVALUES_AUTO", ("a_values", "fp64"): "RKS_AVALUES_FP64",
     }
     tables = {"which": B.WHICH, "sketch": B.SKETCH, "precision": B.PRECISION, "layout": B.SPMV_LAYOUT,
-              "method": B.METHOD}
+              "method": B.METHOD, "a_values": B.A_VALUES}
     lines = ['#include <stdio.h>', '#include "rks.h"', "int main(void) {"]
     for (t, name), cname in expect.items():
         lines.append(f'  printf("{t} {name} %d\\n", (int){cname});')
