@@ -4,6 +4,7 @@
 
 #include <hip/hip_ext.h>
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 namespace rks {
@@ -87,7 +88,8 @@ __device__ __forceinline__ double* wave_bins(double* bins, int d) {
 // order, so the wave needs no block-level barrier.  A tile that is a single
 // row longer than kTileFill nonzeros is reduced by the whole wave.  The row sum ends
 // in the lane with sub == 0 of row rr (< nr).  after_loads(rr, sub) runs while
-// the loads are in flight (independent work can hide under them).
+// the loads are in flight (independent work can hide under them), then
+// prepare_values(), which a long tile runs before its loop.
 // TS: the stored values (TA itself), or one-byte indices into the table vt
 // of the matrix's distinct values (the FP64 product's value-indexed
 // storage; vt in LDS, 256 entries).
@@ -97,11 +99,31 @@ __device__ __forceinline__ TA a_value(TS v, const double* vt) {
   else return (TA)v;
 }
 
-template <typename TV, typename TA, typename TS, typename F>
+// A pair of stored values as loaded, and value h (0 or 1) of it.  A pair of
+// one-byte indices is one 16-bit load kept whole in a 32-bit register and
+// unpacked only where the values are used: packed into shared registers,
+// the loads of a lane's pairs would each wait for the one before.
+template <typename TS>
+struct APair {
+  typedef TS TS2 __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<sizeof(TS) == 1, uint32_t, TS2>::type type;
+  __device__ static type load(const TS* p) {
+    if constexpr (sizeof(TS) == 1) return (uint32_t)*(const uint16_t*)p;
+    else return *(const TS2*)p;
+  }
+};
+template <typename TA, typename TS>
+__device__ __forceinline__ TA a_value2(typename APair<TS>::type p, int h, const double* vt) {
+  if constexpr (sizeof(TS) == 1) return (TA)vt[(p >> (8 * h)) & 0xFF];
+  else return (TA)(h ? p.y : p.x);
+}
+
+template <typename TV, typename TA, typename TS, typename F, typename G>
 __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* __restrict__ col,
                                         const TS* __restrict__ val, const double* vt, const TV* __restrict__ x,
-                                        int4 dsc, TA* pw, int lane, int& rr, int& sub, F&& after_loads) {
-  typedef TS TS2 __attribute__((ext_vector_type(2)));
+                                        int4 dsc, TA* pw, int lane, int& rr, int& sub, F&& after_loads,
+                                        G&& prepare_values) {
+  typedef typename APair<TS>::type VP;
   constexpr int NP = kTileNnz / 128;  // pairs per lane
   const int r0 = dsc.x, nr = dsc.y, e0 = dsc.z, ne = dsc.w;
   TA s = 0;
@@ -118,16 +140,20 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
     // pair p covers tile entries 2p - sh and 2p + 1 - sh (ne + sh <= 2 NP 64)
     const int e0a = e0 & ~1, sh = e0 - e0a, nea = ne + sh;
     int2 ci[NP];
-    TS2 vv[NP];
+    VP vv[NP];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int p2 = 2 * (lane + 64 * u);
+      // index pairs: loaded by every lane (pairs past the tile reload its
+      // first, in bounds), since a load under the branch is merged there
+      if constexpr (sizeof(TS) == 1) vv[u] = APair<TS>::load(val + e0a + (p2 < nea ? p2 : 0));
       if (p2 < nea) {
         ci[u] = *(const int2*)(col + e0a + p2);
-        vv[u] = *(const TS2*)(val + e0a + p2);
+        if constexpr (sizeof(TS) != 1) vv[u] = APair<TS>::load(val + e0a + p2);
       }
     }
     after_loads(rr, sub);
+    prepare_values();
     TA xa[NP], xb[NP];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
@@ -141,8 +167,8 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
     for (int u = 0; u < NP; ++u) {
       const int p2 = 2 * (lane + 64 * u);
       if (p2 < nea) {
-        if (p2 >= sh) pw[p2 - sh] = a_value<TA>(vv[u].x, vt) * xa[u];
-        if (p2 + 1 < nea) pw[p2 + 1 - sh] = a_value<TA>(vv[u].y, vt) * xb[u];
+        if (p2 >= sh) pw[p2 - sh] = a_value2<TA, TS>(vv[u], 0, vt) * xa[u];
+        if (p2 + 1 < nea) pw[p2 + 1 - sh] = a_value2<TA, TS>(vv[u], 1, vt) * xb[u];
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -153,6 +179,7 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
   } else {
     rr = 0;
     sub = lane;
+    prepare_values();
     for (int e = lane; e < ne; e += 64) s += a_value<TA>(val[e0 + e], vt) * (TA)Conv<TV>::ld(x[col[e0 + e]]);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   }
@@ -168,7 +195,11 @@ __device__ __forceinline__ TA tile_rows(const int* __restrict__ rp, const int* _
 // workgroups (kSpmvWaves waves, each with its LDS slice and d sketch bins)
 // let five of them share a CU, where two 8-wave workgroups fit before.
 // TS = uint8_t: A's values as one-byte indices into vtab (256 FP64 entries,
-// copied to LDS first); otherwise vtab is unused.
+// copied to LDS; otherwise vtab is unused).  Every wave copies the whole
+// table in its first tile, once that tile's nonzero loads are in flight, so
+// the copy's latency hides under theirs and no barrier waits for it: the
+// waves write the same values, and a wave's own LDS writes complete before
+// its later LDS reads.
 template <typename TV, typename TW, typename TA, int KIND, typename TS = TA>
 __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __restrict__ rp, const int* __restrict__ col,
                                                      const TS* __restrict__ val, const double* __restrict__ vtab,
@@ -181,9 +212,8 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
   const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  bool tab = sizeof(TS) != 1;
   if (do_sketch) bins_zero(bins, sp.d);
-  if constexpr (sizeof(TS) == 1)
-    for (int i = tid; i < 256; i += 64 * kSpmvWaves) vt[i] = vtab[i];
   __syncthreads();
   TA* pw = prod[wv];
   double* wb = wave_bins(bins, sp.d);
@@ -208,12 +238,26 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
     int have = 0;
     // the row's sketch column does not depend on the data: hash it while the
     // tile's loads are in flight
-    const TA s = tile_rows<TV, TA, TS>(rp, col, val, vt, x, dsc, pw, lane, rr, sub, [&](int r_, int s_) {
-      if (KIND == 1 && do_sketch && r_ < dsc.y && s_ == 0) {
-        sparse_column((uint64_t)(dsc.x + r_), sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
-        have = 1;
-      }
-    });
+    const TA s = tile_rows<TV, TA, TS>(
+        rp, col, val, vt, x, dsc, pw, lane, rr, sub,
+        [&](int r_, int s_) {
+          if (KIND == 1 && do_sketch && r_ < dsc.y && s_ == 0) {
+            sparse_column((uint64_t)(dsc.x + r_), sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
+            have = 1;
+          }
+        },
+        [&] {
+          if constexpr (sizeof(TS) == 1) {
+            if (!tab) {
+              double tv[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) tv[q] = vtab[64 * q + lane];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) vt[64 * q + lane] = tv[q];
+              tab = true;
+            }
+          }
+        });
     if (rr < dsc.y && sub == 0) {
       const int r = dsc.x + rr;
       const TW ws = (TW)s;
