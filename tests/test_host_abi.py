@@ -107,6 +107,10 @@ def test_create_rejects_bad_arguments(lib):
         with pytest.raises(P.RksError) as ei:
             P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 1e-10, P.rks_opts_default(lock=lock))
         assert ei.value.code == -1
+    for av in (-1, 2):  # 0 value-indexed when possible, 1 FP64 values
+        with pytest.raises(P.RksError) as ei:
+            P.rks_create(A.row_ptr, A.col, A.val, A.n, 3, 10, 20, "LM", 1e-10, P.rks_opts_default(a_values=av))
+        assert ei.value.code == -1 and "a_values" in P.rks_last_error(None)
     # malformed CSR: decreasing row pointer, column out of range, unsorted row
     rp = A.row_ptr.copy(); rp[5] = rp[4] - 1
     with pytest.raises(P.RksError):
