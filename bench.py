@@ -242,6 +242,9 @@ def main():
                     help="time the kernels of every P-th Arnoldi step with HIP events (the events "
                          "around whole steps cost a few microseconds each, so the sample is sparse)")
     ap.add_argument("--keep", default="auto", help="restart size: auto (k + (m-k)/4), or a number in [k, m-2]")
+    ap.add_argument("--spmv-layout", default="auto", choices=["auto", "rows", "column_blocks", "sliced"],
+                    help="SpMV layout (auto: column blocks for rows that gather from everywhere, else sliced "
+                         "when its padding is small, else row tiles)")
     ap.add_argument("--a-values", default="auto", choices=["auto", "fp64"],
                     help="storage of A's values for the FP64 product: auto (one-byte indices into the table of "
                          "distinct values when there are at most 256; bit-identical products) or fp64")
@@ -289,7 +292,7 @@ def main():
                                start_seed=cfg["start_seed"], precision=cfg["precision"], lock=int(cfg["lock"]),
                                max_restarts=cfg.get("max_restarts", 300), profile=0 if args.no_profile else args.profile_every,
                                resid_tol=args.resid_tol, keep=keep, graphs=args.graphs, refine=args.refine,
-                               a_values=args.a_values, stream=stream)
+                               a_values=args.a_values, spmv_layout=args.spmv_layout, stream=stream)
     for _ in range(args.warmup):
         solver.solve()
     torch.cuda.synchronize()
@@ -357,7 +360,7 @@ def main():
         "max_resid": float(np.max(res)),
         "max_est": st["max_est"],
         "loop_gbs": loop_gbs,
-        "spmv_layout": {1: "rows", 2: "column_blocks"}.get(st["spmv_layout"], "?"),
+        "spmv_layout": {1: "rows", 2: "column_blocks", 3: "sliced"}.get(st["spmv_layout"], "?"),
         "a_values": (f"value-indexed: {st['a_distinct']} distinct values, a 1-byte index per nonzero"
                      if st["a_distinct"] else "fp64"),
         "kernel_avg_us": _kernel_avg_us(st),
@@ -393,6 +396,7 @@ def main():
                                method=method, lock=vlock,
                                max_restarts=cfg.get("max_restarts", 300),
                                resid_tol=0.0 if prec == "eta" else args.resid_tol, a_values=args.a_values,
+                               spmv_layout=args.spmv_layout,
                                profile=0 if args.no_profile else args.profile_every, stream=stream) as s2:
             if not slow:
                 s2.solve()

@@ -72,9 +72,20 @@ typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2, RKS_PREC
  * workgroups on the same block at about the same time, so the gathered part
  * of x stays in L2) and keeps the row sums in LDS until w is written (it
  * stores a second copy of A, reordered by panel and block, with 16-bit row
- * offsets).  AUTO picks COLUMN_BLOCKS when n >= 2^20 and the median column
- * span of a row tile exceeds n/4. */
-typedef enum { RKS_SPMV_AUTO = 0, RKS_SPMV_ROWS = 1, RKS_SPMV_COLUMN_BLOCKS = 2 } rks_spmv_layout;
+ * offsets).  SLICED: slices of 64 consecutive rows, one row per lane of a
+ * wave, each slice's nonzeros stored k-th of every row together (a sliced
+ * ELLPACK layout, rows padded to the longest row of their slice): a wave's
+ * loads of the k-th nonzeros are contiguous, and on a banded matrix so are
+ * its gathers of x; a lane adds its row's products in order in a register.
+ * It stores a second copy of A in that order.  AUTO picks COLUMN_BLOCKS when
+ * n >= 2^20 and the median column span of a row tile exceeds n/4, else
+ * SLICED when the padding adds at most 1/8 to the nonzeros, else ROWS. */
+typedef enum {
+  RKS_SPMV_AUTO = 0,
+  RKS_SPMV_ROWS = 1,
+  RKS_SPMV_COLUMN_BLOCKS = 2,
+  RKS_SPMV_SLICED = 3
+} rks_spmv_layout;
 
 /* RKS: randomized Krylov-Schur (Algorithm 1 with Algorithm 2).  KS_CGS2:
  * deterministic Krylov-Schur, the paper's point of comparison (Section 5):

@@ -17,7 +17,7 @@ RKS_EINVAL, RKS_ENOMEM, RKS_EHIP, RKS_ENAN, RKS_ESTATE, RKS_EBREAKDOWN, RKS_EDEN
 WHICH = {"LM": 0, "SM": 1, "LR": 2, "SR": 3}
 SKETCH = {"gauss": 0, "sparse": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "v32": 1, "bf16": 2, "vbf16": 2, "fp32+fx16": 3, "v32_fx16": 3}
-SPMV_LAYOUT = {"auto": 0, "rows": 1, "column_blocks": 2}
+SPMV_LAYOUT = {"auto": 0, "rows": 1, "column_blocks": 2, "sliced": 3}
 METHOD = {"rks": 0, "ks_cgs2": 1}
 A_VALUES = {"auto": 0, "fp64": 1}
 

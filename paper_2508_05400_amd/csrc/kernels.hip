@@ -277,6 +277,102 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
   if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
 }
 
+// w = A x and partials of Omega w in the sliced layout (see LaunchEnv): one
+// wave per slice of kSliceRows rows, lane l owning row kSliceRows s + l and
+// adding its products in order (k = 0, 1, ...) in a register, so no LDS
+// staging and no cross-lane reduction.  A wave's loads of the k-th nonzeros
+// are contiguous (256 bytes of columns, 64 of value indices), and on a banded
+// matrix so are its gathers of x.  Loads go in groups of 8 k, every one issued
+// before the first use and none under a branch (k past the slice's longest
+// row is clamped to its last: in bounds, not added); padding (k >= the row's
+// length) is loaded but not added.  The row's sketch column is hashed while
+// the first group is in flight.  Slices are dealt to the XCDs in contiguous
+// eighths, as the row tiles are.  TS as in k_spmv_sketch.
+template <typename TV, typename TW, typename TA, int KIND, typename TS>
+__global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sell(const int* __restrict__ rp,
+                                                   const int64_t* __restrict__ sl_off, int nsl,
+                                                   const int* __restrict__ col, const TS* __restrict__ val,
+                                                   const double* __restrict__ vtab, int64_t n,
+                                                   const TV* __restrict__ x, TW* __restrict__ w,
+                                                   double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
+  extern __shared__ double bins[];  // kSpmvWaves waves x d
+  __shared__ double vt[sizeof(TS) == 1 ? 256 : 1];
+  typedef typename std::conditional<sizeof(TS) == 1, uint32_t, TS>::type VL;
+  const int do_sketch = KIND == 1 ? do_sketch_arg : 0;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  bool tab = sizeof(TS) != 1;
+  if (do_sketch) bins_zero(bins, sp.d);
+  __syncthreads();
+  double* wb = wave_bins(bins, sp.d);
+  const int Gx = gridDim.x >> 3;
+  int s0, send, sstep;
+  if (Gx > 0 && (gridDim.x & 7) == 0) {
+    const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
+    const int chunk = (nsl + 7) >> 3;
+    s0 = xcd * chunk + lb * kSpmvWaves + wv;
+    send = min(nsl, (xcd + 1) * chunk);
+    sstep = Gx * kSpmvWaves;
+  } else {
+    s0 = blockIdx.x * kSpmvWaves + wv;
+    send = nsl;
+    sstep = gridDim.x * kSpmvWaves;
+  }
+  for (int s = s0; s < send; s += sstep) {
+    const int64_t b0 = sl_off[s];  // wave-uniform
+    const int slen = (int)((sl_off[s + 1] - b0) / kSliceRows);
+    const int64_t r = (int64_t)s * kSliceRows + lane;
+    const int len = r < n ? rp[r + 1] - rp[r] : 0;
+    TA acc = 0;
+    int hrows[8];
+    float hsg[8];
+    for (int k0 = 0; k0 < slen; k0 += 8) {
+      int cc[8];
+      VL vv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t e = b0 + (int64_t)kSliceRows * (k0 + q < slen ? k0 + q : slen - 1) + lane;
+        cc[q] = col[e];
+        vv[q] = (VL)val[e];
+      }
+      if (k0 == 0) {
+        if (KIND == 1 && do_sketch && r < n) sparse_column((uint64_t)r, sp.d, sp.zeta, sp.k0, sp.k1, hrows, hsg);
+        if constexpr (sizeof(TS) == 1) {
+          if (!tab) {
+            double tv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tv[q] = vtab[64 * q + lane];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vt[64 * q + lane] = tv[q];
+            tab = true;
+          }
+        }
+      }
+      TA xv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[q] = (TA)Conv<TV>::ld(x[cc[q]]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        TA a;
+        if constexpr (sizeof(TS) == 1) a = (TA)vt[vv[q]];
+        else a = (TA)vv[q];
+        if (k0 + q < len) acc += a * xv[q];
+      }
+    }
+    if (r < n) {
+      const TW ws = (TW)acc;
+      w[r] = ws;
+      if (KIND == 1 && do_sketch) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (q < sp.zeta) atomicAdd(&wb[hrows[q]], (double)hsg[q] * (double)ws);
+      }
+    }
+  }
+  __syncthreads();
+  if (do_sketch) bins_store(bins, zpart, sp.d, sp.scale);
+}
+
 // Row sums of one panel tile {first row r0 (within the panel), rows nr, first
 // nonzero e0, nonzeros ne} of the column-blocked layout, added to the panel's
 // row sums acc (LDS).  As in tile_rows, a lane loads up to 4 pairs of
@@ -1644,9 +1740,29 @@ static int spmv_panel_t(const LaunchEnv& e, const TA* val, const TV* x, TW* w, d
   return e.npanels;
 }
 
+template <typename TV, typename TW, typename TA, typename TS>
+static int spmv_sell_t(const LaunchEnv& e, const TS* val, const TV* x, TW* w, double* zpart, int do_sketch) {
+  int G = grid_for(e.nsl, kSpmvWaves, kSellMaxG);
+  if (G >= 8) G &= ~7;  // a multiple of the XCD count (see the slice mapping)
+  const size_t lds = bins_lds(e, kSpmvWaves, do_sketch && e.sp_kind == 1);
+  RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sell<TV, TW, TA, KIND, TS>, lds);
+                    launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sell<TV, TW, TA, KIND, TS>, dim3(G),
+                             dim3(64 * kSpmvWaves), lds, e.rp, e.sl_off, e.nsl, e.col_sl, val, e.vtab, e.n, x, w,
+                             zpart, e.sp, do_sketch));
+  if (do_sketch && e.sp_kind == 0) return gauss_t<TW>(e, w, zpart);
+  return G;
+}
+
 int launch_spmv_sketch(const LaunchEnv& e, const void* x, void* w, double* zpart, int do_sketch, int prec_override) {
   int prec = prec_override >= 0 ? prec_override : e.prec;
   if (prec == 3) prec = 0;  // the pair basis multiplies FP64 copies of its columns
+  if (e.sl) {
+    if (prec == 0 && e.vidx_sl)
+      return spmv_sell_t<double, double, double, uint8_t>(e, e.vidx_sl, (const double*)x, (double*)w, zpart, do_sketch);
+    if (prec == 0) return spmv_sell_t<double, double, double, double>(e, e.val_sl, (const double*)x, (double*)w, zpart, do_sketch);
+    if (prec == 1) return spmv_sell_t<float, float, float, float>(e, e.val32_sl, (const float*)x, (float*)w, zpart, do_sketch);
+    return spmv_sell_t<bf16_t, float, float, float>(e, e.val32_sl, (const bf16_t*)x, (float*)w, zpart, do_sketch);
+  }
   if (e.cb) {
     if (prec == 0) return spmv_panel_t<double, double, double>(e, e.val_pn, (const double*)x, (double*)w, zpart, do_sketch);
     if (prec == 1) return spmv_panel_t<float, float, float>(e, e.val32_pn, (const float*)x, (float*)w, zpart, do_sketch);

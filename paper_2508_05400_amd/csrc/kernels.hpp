@@ -23,7 +23,8 @@ namespace rks {
 constexpr int kMaxD = 1024;      // largest sketch size (LDS bins)
 constexpr int kMaxM = 255;       // largest Krylov dimension
 constexpr int kMaxG = 512;       // largest number of partial-sum rows (producer blocks)
-constexpr int kMaxPart = kSpmvMaxG > kMaxG ? kSpmvMaxG : kMaxG;  // partial rows of the row-tile SpMV's sketch
+constexpr int kMaxPart0 = kSpmvMaxG > kMaxG ? kSpmvMaxG : kMaxG;
+constexpr int kMaxPart = kSellMaxG > kMaxPart0 ? kSellMaxG : kMaxPart0;  // partial rows of the row-tile or sliced SpMV's sketch
 constexpr int kRotMax = 128;     // output columns per rotation pass (8 MFMA column tiles)
 constexpr size_t kRotLdsMax = 160 * 1024;  // Y in LDS up to this size, else read from global memory
 constexpr size_t kLsLdsMax = 150 * 1024;  // LDS budget of the least-squares kernel

@@ -38,6 +38,18 @@ struct LaunchEnv {
   const int* toff_pn = nullptr;     // per tile: first row offset, -1 for a long tile
   const uint16_t* off_pn = nullptr; // row offsets of the tiles
   const int* ptile = nullptr;       // (kCb + 1) per panel: first tile of each column block, then the end
+  // sliced layout (used when sl = 1): nsl slices of kSliceRows rows; slice s
+  // holds entries sl_off[s] .. sl_off[s+1] - 1, entry (k, lane) at
+  // sl_off[s] + kSliceRows k + lane (the k-th nonzero of row kSliceRows s +
+  // lane; rows shorter than the slice's longest are padded with column =
+  // the row, never added)
+  int sl = 0;
+  int nsl = 0;
+  const int64_t* sl_off = nullptr;
+  const int* col_sl = nullptr;
+  const double* val_sl = nullptr;    // FP64 values (unless value-indexed)
+  const uint8_t* vidx_sl = nullptr;  // value indices (value-indexed storage)
+  const float* val32_sl = nullptr;   // mixed precision only
   // Timing (null when off): a launcher that runs with these set records ev0 at
   // the start of its first kernel and ev1 at the end of its last one, from the
   // dispatches' own timestamps (no marker packets between the kernels).

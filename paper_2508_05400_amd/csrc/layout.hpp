@@ -14,6 +14,13 @@ constexpr int kCsrPad = 2;       // readable padding entries after col[] and val
 constexpr int kSpmvWaves = 4;    // waves per SpMV workgroup
 constexpr int kSpmvMaxG = 1280;  // SpMV workgroups at most (5 per CU: LDS-bound for FP64 with d <= 360)
 
+// Sliced layout: slices of kSliceRows consecutive rows (one per lane of a
+// wave), each stored k-th nonzero of every row together; at most
+// kSellMaxG workgroups of kSpmvWaves waves (6 per CU; no product staging in
+// LDS, only the sketch bins).
+constexpr int kSliceRows = 64;
+constexpr int kSellMaxG = 1536;
+
 // Column-blocked layout (operators whose rows gather x from everywhere):
 // kCb column blocks (n / kCb values of x, which fit in an XCD's L2); row
 // panels of consecutive rows, one workgroup each; panel tiles of up to

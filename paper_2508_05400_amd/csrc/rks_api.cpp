@@ -71,6 +71,12 @@ struct rks_ctx {
   uint8_t* vidx = nullptr;  // value-indexed A (FP64 product): one byte per nonzero
   double* vtab = nullptr;   // its table of distinct values (256 entries)
   int a_distinct = 0;       // distinct values in vtab (0: FP64 values)
+  // sliced layout (when chosen): slice offsets, columns and values in slice order
+  int64_t* sl_off = nullptr;
+  int* col_sl = nullptr;
+  double* val_sl = nullptr;
+  uint8_t* vidx_sl = nullptr;
+  float* val32_sl = nullptr;
   void* U = nullptr;      // basis in use (U_lo or U64)
   void* U_lo = nullptr;   // basis in the requested precision (allocated at create; the pair
                           // basis: the FP32 parts, then the 16-bit remainders of the same elements)
@@ -1054,7 +1060,8 @@ void free_all(rks_ctx* c) {
   void* dev[] = {c->rp, c->col, c->tiles, c->dstate, c->val, c->val32, c->U_lo, c->U64, c->w, c->xcur,
                  c->coef, c->z, c->sr, c->zpart, c->spart, c->scal, c->Yd, c->u0tmp, c->kpart,
                  c->col_pn, c->tiles_pn, c->toff_pn, c->ptile, c->off_pn, c->val_pn, c->val32_pn,
-                 c->Xr, c->ax1, c->ax2, c->rpart, c->vidx, c->vtab};
+                 c->Xr, c->ax1, c->ax2, c->rpart, c->vidx, c->vtab, c->sl_off, c->col_sl, c->val_sl,
+                 c->vidx_sl, c->val32_sl};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {c->hstate, c->hY};
@@ -1115,7 +1122,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (o.sketch_kind == RKS_SKETCH_SPARSE && (o.zeta < 1 || o.zeta > 8 || o.zeta > d))
     return fail(nullptr, RKS_EINVAL, "need 1 <= zeta <= min(8, d)");
   if (o.precision < 0 || o.precision > 3 || o.max_restarts < 0 || !(o.whiten_tol >= 0.0) ||
-      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 2 || o.method < 0 ||
+      !(o.resid_tol >= 0.0) || !(o.refine_tol >= 0.0) || o.spmv_layout < 0 || o.spmv_layout > 3 || o.method < 0 ||
       o.method > 1 || o.graphs < 0 || o.graphs > 1 || o.stall_restarts < 0 || o.a_values < 0 || o.a_values > 1)
     return fail(nullptr, RKS_EINVAL,
                 "precision, max_restarts, whiten_tol, resid_tol, refine_tol, spmv_layout, method, graphs, "
@@ -1240,6 +1247,26 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     }
   }
   const bool indexed = !vkeys.empty();
+  // sliced layout: slices of kSliceRows rows, each padded to its longest row
+  const int64_t nsl = (n + rks::kSliceRows - 1) / rks::kSliceRows;
+  std::vector<int64_t> sloff;
+  bool use_sl = false;
+  if (!use_cb && (o.spmv_layout == RKS_SPMV_SLICED || o.spmv_layout == RKS_SPMV_AUTO)) {
+    sloff.assign(nsl + 1, 0);
+    for (int64_t sb = 0; sb < nsl; ++sb) {
+      int ml = 0;
+      for (int64_t r = sb * rks::kSliceRows; r < std::min<int64_t>(n, (sb + 1) * rks::kSliceRows); ++r)
+        ml = std::max(ml, rp[r + 1] - rp[r]);
+      sloff[sb + 1] = sloff[sb] + (int64_t)rks::kSliceRows * ml;
+    }
+    const int64_t P = sloff[nsl];
+    use_sl = (o.spmv_layout == RKS_SPMV_SLICED || P <= nnz + nnz / 8) && P > 0 && P < ((int64_t)1 << 31);
+    if (o.spmv_layout == RKS_SPMV_SLICED && !use_sl) {
+      delete c;
+      return fail(nullptr, RKS_EINVAL, "sliced layout: no nonzeros, or 2^31 padded entries or more");
+    }
+  }
+  const int64_t sl_entries = use_sl ? sloff[nsl] : 0;
   const int ebytes = o.precision == RKS_PREC_FP64 ? 8 : (pair ? 6 : (o.precision == RKS_PREC_V32 ? 4 : 2));
   c->ldu = (n + 127) / 128 * 128;
   c->pair = pair;
@@ -1272,6 +1299,13 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   if (indexed) {
     dm((void**)&c->vidx, nzp);
     dm((void**)&c->vtab, 256 * 8);
+  }
+  if (use_sl) {
+    dm((void**)&c->sl_off, (size_t)(nsl + 1) * 8);
+    dm((void**)&c->col_sl, (size_t)sl_entries * 4);
+    if (indexed) dm((void**)&c->vidx_sl, (size_t)sl_entries);
+    else dm((void**)&c->val_sl, (size_t)sl_entries * 8);
+    if (low) dm((void**)&c->val32_sl, (size_t)sl_entries * 4);
   }
   dm((void**)&c->tiles, tdesc.size() * 4);
   if (use_cb) {
@@ -1333,6 +1367,35 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     cp(c->vtab, tab.data(), 256 * 8);
     c->a_distinct = (int)vkeys.size();
   }
+  if (use_sl && rc == RKS_OK) {
+    // entry (k, lane) of slice sb: the k-th nonzero of row kSliceRows sb + lane,
+    // or padding (column = the row, or 0 past n; value 0, never added)
+    std::vector<int32_t> scol((size_t)sl_entries);
+    std::vector<uint8_t> sidx(indexed ? (size_t)sl_entries : 0);
+    std::vector<double> sval(indexed ? 0 : (size_t)sl_entries);
+    std::vector<float> sval32(low ? (size_t)sl_entries : 0);
+    for (int64_t sb = 0; sb < nsl; ++sb) {
+      const int64_t b0 = sloff[sb], slen = (sloff[sb + 1] - b0) / rks::kSliceRows;
+      for (int lane = 0; lane < rks::kSliceRows; ++lane) {
+        const int64_t r = sb * rks::kSliceRows + lane;
+        const int64_t len = r < n ? rp[r + 1] - rp[r] : 0;
+        for (int64_t k = 0; k < slen; ++k) {
+          const size_t e = (size_t)(b0 + k * rks::kSliceRows + lane);
+          const bool real = k < len;
+          const int64_t j = real ? rp[r] + k : 0;
+          scol[e] = real ? col[j] : (int32_t)(r < n ? r : 0);
+          if (indexed) sidx[e] = real ? vind[j] : 0;
+          else sval[e] = real ? val[j] : 0.0;
+          if (low) sval32[e] = real ? (float)val[j] : 0.0f;
+        }
+      }
+    }
+    cp(c->sl_off, sloff.data(), (size_t)(nsl + 1) * 8);
+    cp(c->col_sl, scol.data(), (size_t)sl_entries * 4);
+    if (indexed) cp(c->vidx_sl, sidx.data(), (size_t)sl_entries);
+    else cp(c->val_sl, sval.data(), (size_t)sl_entries * 8);
+    if (low) cp(c->val32_sl, sval32.data(), (size_t)sl_entries * 4);
+  }
   cp(c->tiles, tdesc.data(), tdesc.size() * 4);
   if (use_cb) {
     cp(c->col_pn, pl.col.data(), (size_t)nnz * 4);
@@ -1382,6 +1445,15 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   e.val32 = c->val32;
   e.vidx = c->vidx;
   e.vtab = c->vtab;
+  if (use_sl) {
+    e.sl = 1;
+    e.nsl = (int)nsl;
+    e.sl_off = c->sl_off;
+    e.col_sl = c->col_sl;
+    e.val_sl = c->val_sl;
+    e.vidx_sl = c->vidx_sl;
+    e.val32_sl = c->val32_sl;
+  }
   e.tiles = c->tiles;
   e.ntiles = ntiles;
   if (use_cb) {
@@ -1480,7 +1552,7 @@ int rks_solve(rks_ctx* c, const double* u0, int32_t u0_on_device, rks_stats* st)
   st->restarts = p1.restarts;
   st->locked = c->q;
   st->keff = c->kr;
-  st->spmv_layout = c->env.cb ? RKS_SPMV_COLUMN_BLOCKS : RKS_SPMV_ROWS;
+  st->spmv_layout = c->env.cb ? RKS_SPMV_COLUMN_BLOCKS : (c->env.sl ? RKS_SPMV_SLICED : RKS_SPMV_ROWS);
   st->a_distinct = c->a_distinct;
   st->keep = c->keep;
   st->max_est = p1.maxest;

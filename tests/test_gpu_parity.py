@@ -92,7 +92,7 @@ def test_sketch_parity(lib, cuda, case):
         P.rks_destroy(ctx)
 
 
-@pytest.mark.parametrize("layout", ["rows", "column_blocks"])
+@pytest.mark.parametrize("layout", ["rows", "column_blocks", "sliced"])
 @pytest.mark.parametrize("case", sorted(SMALL))
 def test_spmv_sketch_parity(lib, cuda, case, layout):
     mk, kind, d = SMALL[case]
@@ -138,16 +138,18 @@ VIDX = {
 }
 
 
+@pytest.mark.parametrize("layout", ["rows", "sliced"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32+fx16"])
 @pytest.mark.parametrize("case", sorted(VIDX))
-def test_value_indexed_storage_is_bitwise_fp64(lib, cuda, case, prec):
+def test_value_indexed_storage_is_bitwise_fp64(lib, cuda, case, prec, layout):
     """A matrix with at most 256 distinct values is stored value-indexed by
     default (a one-byte index per nonzero into the table of its values); the
     SpMV looks each value up and forms the same FP64 product, so the fused
     SpMV + sketch (w, z), a whole extension (B, S, U) and a short solve
     (Ritz values, residuals, restart and product counts) equal those with
-    a_values = 'fp64' to the last bit, on both bases whose product is FP64.
-    The statistics report the table size, 0 beyond 256 values."""
+    a_values = 'fp64' to the last bit, on both bases whose product is FP64,
+    in the row-tile and the sliced layouts.  The statistics report the table
+    size, 0 beyond 256 values, and the layout."""
     mk, nd = VIDX[case]
     A = mk()
     assert len(np.unique(A.val.view(np.uint64))) == (nd or 257)
@@ -156,7 +158,7 @@ def test_value_indexed_storage_is_bitwise_fp64(lib, cuda, case, prec):
     for av in ("auto", "fp64"):
         ctx = P.rks_create(A.row_ptr, A.col, A.val, A.n, k, m, d, "LM", 1e-10,
                            P.rks_opts_default(sketch_seed=5, start_seed=1, precision=prec, a_values=av,
-                                              spmv_layout="rows"))
+                                              spmv_layout=layout))
         try:
             x = start_vector_normal(A.n, 9)
             w = cuda.zeros(A.n, dtype=cuda.float64, device="cuda")
@@ -170,9 +172,10 @@ def test_value_indexed_storage_is_bitwise_fp64(lib, cuda, case, prec):
         finally:
             P.rks_destroy(ctx)
         with P.Solver.from_csr(A, k=k, m=m, d=d, which="LM", tol=1e-10, sketch_seed=5, start_seed=1,
-                               precision=prec, a_values=av, spmv_layout="rows", max_restarts=4) as s:
+                               precision=prec, a_values=av, spmv_layout=layout, max_restarts=4) as s:
             assert s.solve() in (0, 1), P.rks_last_error(s.ctx)
             st = (s.stats.restarts, s.stats.matvecs, s.stats.a_distinct)
+            assert s.stats.spmv_layout == {"rows": 1, "sliced": 3}[layout]
             lam, X, res = s.eigpairs()
         outs[av] = (w.cpu().numpy(), z.cpu().numpy(), B, S, U, lam, X, res, st)
     a, f = outs["auto"], outs["fp64"]
@@ -191,7 +194,9 @@ ARN = {
 }
 
 
-@pytest.mark.parametrize("case,layout", [(c, "rows") for c in sorted(ARN)] + [("powerlaw-5003", "column_blocks")])
+@pytest.mark.parametrize("case,layout", [(c, "rows") for c in sorted(ARN)] + [("powerlaw-5003", "column_blocks"),
+                                           ("cd2d-37-sparse", "sliced"), ("cd2d-37-gauss", "sliced"),
+                                           ("powerlaw-5003", "sliced")])
 def test_arnoldi_parity(lib, cuda, case, layout):
     """First extension (Algorithm 2 from one column) vs the oracle: B, S, U."""
     mk, kind, k, m, d = ARN[case]

@@ -186,7 +186,7 @@ def test_binding_enum_names_match_the_header(tmp_path):
         ("precision", "fp64"): "RKS_PREC_FP64", ("precision", "fp32"): "RKS_PREC_V32",
         ("precision", "bf16"): "RKS_PREC_VBF16", ("precision", "fp32+fx16"): "RKS_PREC_V32_FX16",
         ("layout", "auto"): "RKS_SPMV_AUTO", ("layout", "rows"): "RKS_SPMV_ROWS",
-        ("layout", "column_blocks"): "RKS_SPMV_COLUMN_BLOCKS",
+        ("layout", "column_blocks"): "RKS_SPMV_COLUMN_BLOCKS", ("layout", "sliced"): "RKS_SPMV_SLICED",
         ("method", "rks"): "RKS_METHOD_RKS", ("method", "ks_cgs2"): "RKS_METHOD_KS_CGS2",
         ("a_values", "auto"): "RKS_AVALUES_AUTO", ("a_values", "fp64"): "RKS_AVALUES_FP64",
     }
