@@ -96,7 +96,7 @@ typedef enum {
 typedef enum { RKS_METHOD_RKS = 0, RKS_METHOD_KS_CGS2 = 1 } rks_method;
 
 /* Storage of A's values for the FP64 product (FP64 and pair bases, and the
- * FP64 residual checks) in the row-tile layout.  AUTO: when A has at most
+ * FP64 residual checks) in the row-tile and sliced layouts.  AUTO: when A has at most
  * 256 distinct values (compared bit for bit), each nonzero stores a one-byte
  * index into the table of those values instead of the 8-byte value (a
  * value-indexed CSR, as in Kourtis, Goumas and Koziris, "Optimizing sparse
