@@ -284,8 +284,10 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
 // are contiguous (256 bytes of columns, 64 of value indices), and on a banded
 // matrix so are its gathers of x.  Loads go in groups of 8 k, every one issued
 // before the first use and none under a branch (k past the slice's longest
-// row is clamped to its last: in bounds, not added); padding (k >= the row's
-// length) is loaded but not added.  The row's sketch column is hashed while
+// row is clamped to its last: in bounds, not added).  Padding (k >= the row's
+// length) holds +0.0 when pad0, and is then added like the nonzeros (exactly
+// 0 for finite x, and no row lengths are read); otherwise it is loaded but not
+// added.  The row's sketch column is hashed while
 // the first group is in flight.  Slices are dealt to the XCDs in contiguous
 // eighths, as the row tiles are.  TS as in k_spmv_sketch.
 template <typename TV, typename TW, typename TA, int KIND, typename TS>
@@ -294,7 +296,8 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sell(const int* __rest
                                                    const int* __restrict__ col, const TS* __restrict__ val,
                                                    const double* __restrict__ vtab, int64_t n,
                                                    const TV* __restrict__ x, TW* __restrict__ w,
-                                                   double* __restrict__ zpart, SketchP sp, int do_sketch_arg) {
+                                                   double* __restrict__ zpart, SketchP sp, int do_sketch_arg,
+                                                   int pad0) {
   extern __shared__ double bins[];  // kSpmvWaves waves x d
   __shared__ double vt[sizeof(TS) == 1 ? 256 : 1];
   typedef typename std::conditional<sizeof(TS) == 1, uint32_t, TS>::type VL;
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sell(const int* __rest
     const int64_t b0 = sl_off[s];  // wave-uniform
     const int slen = (int)((sl_off[s + 1] - b0) / kSliceRows);
     const int64_t r = (int64_t)s * kSliceRows + lane;
-    const int len = r < n ? rp[r + 1] - rp[r] : 0;
+    const int len = pad0 ? slen : (r < n ? rp[r + 1] - rp[r] : 0);
     TA acc = 0;
     int hrows[8];
     float hsg[8];
@@ -1748,7 +1751,7 @@ static int spmv_sell_t(const LaunchEnv& e, const TS* val, const TV* x, TW* w, do
   RKS_SKETCH_SWITCH(e.sp_kind, lds_allow((const void*)k_spmv_sell<TV, TW, TA, KIND, TS>, lds);
                     launch_k(e, true, !(do_sketch && e.sp_kind == 0), k_spmv_sell<TV, TW, TA, KIND, TS>, dim3(G),
                              dim3(64 * kSpmvWaves), lds, e.rp, e.sl_off, e.nsl, e.col_sl, val, e.vtab, e.n, x, w,
-                             zpart, e.sp, do_sketch));
+                             zpart, e.sp, do_sketch, e.sl_pad0));
   if (do_sketch && e.sp_kind == 0) return gauss_t<TW>(e, w, zpart);
   return G;
 }

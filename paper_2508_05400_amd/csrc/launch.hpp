@@ -41,8 +41,7 @@ struct LaunchEnv {
   // sliced layout (used when sl = 1): nsl slices of kSliceRows rows; slice s
   // holds entries sl_off[s] .. sl_off[s+1] - 1, entry (k, lane) at
   // sl_off[s] + kSliceRows k + lane (the k-th nonzero of row kSliceRows s +
-  // lane; rows shorter than the slice's longest are padded with column =
-  // the row, never added)
+  // lane; rows shorter than the slice's longest are padded, see sl_pad0)
   int sl = 0;
   int nsl = 0;
   const int64_t* sl_off = nullptr;
@@ -50,6 +49,7 @@ struct LaunchEnv {
   const double* val_sl = nullptr;    // FP64 values (unless value-indexed)
   const uint8_t* vidx_sl = nullptr;  // value indices (value-indexed storage)
   const float* val32_sl = nullptr;   // mixed precision only
+  int sl_pad0 = 0;                   // padding holds +0.0 (added like the nonzeros; no row lengths read)
   // Timing (null when off): a launcher that runs with these set records ev0 at
   // the start of its first kernel and ev1 at the end of its last one, from the
   // dispatches' own timestamps (no marker packets between the kernels).

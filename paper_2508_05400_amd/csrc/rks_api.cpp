@@ -1228,6 +1228,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   // nonzero's index into it
   std::vector<uint64_t> vkeys;
   std::vector<uint8_t> vind;
+  int a_nd = 0;  // distinct values of A (the table may hold +0.0 besides)
   if (o.a_values == RKS_AVALUES_AUTO && !use_cb && nnz > 0) {
     for (int64_t e = 0; e < nnz && vkeys.size() <= 256; ++e) {
       uint64_t key;
@@ -1236,6 +1237,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
       if (it == vkeys.end() || *it != key) vkeys.insert(it, key);
     }
     if (vkeys.size() <= 256) {
+      a_nd = (int)vkeys.size();
+      // +0.0 in the table (if there is room) pads the sliced layout
+      if (vkeys.front() != 0 && vkeys.size() < 256) vkeys.insert(vkeys.begin(), (uint64_t)0);
       vind.resize(nnz);
       for (int64_t e = 0; e < nnz; ++e) {
         uint64_t key;
@@ -1267,6 +1271,9 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     }
   }
   const int64_t sl_entries = use_sl ? sloff[nsl] : 0;
+  // padding carries the value +0.0, so the kernel may add it (no row lengths
+  // needed), unless the value table is full without +0.0
+  const bool pad0 = !indexed || vkeys.front() == 0;
   const int ebytes = o.precision == RKS_PREC_FP64 ? 8 : (pair ? 6 : (o.precision == RKS_PREC_V32 ? 4 : 2));
   c->ldu = (n + 127) / 128 * 128;
   c->pair = pair;
@@ -1365,11 +1372,13 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     for (size_t i = 0; i < vkeys.size(); ++i) std::memcpy(&tab[i], &vkeys[i], 8);
     cp(c->vidx, vind.data(), nnz);
     cp(c->vtab, tab.data(), 256 * 8);
-    c->a_distinct = (int)vkeys.size();
+    c->a_distinct = a_nd;
   }
   if (use_sl && rc == RKS_OK) {
     // entry (k, lane) of slice sb: the k-th nonzero of row kSliceRows sb + lane,
-    // or padding (column = the row, or 0 past n; value 0, never added)
+    // or padding: value +0.0 (table index 0 when value-indexed and pad0) and
+    // the row's first column (the row itself if it is empty, 0 past n), so
+    // the padding adds exactly 0 for finite x
     std::vector<int32_t> scol((size_t)sl_entries);
     std::vector<uint8_t> sidx(indexed ? (size_t)sl_entries : 0);
     std::vector<double> sval(indexed ? 0 : (size_t)sl_entries);
@@ -1383,7 +1392,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
           const size_t e = (size_t)(b0 + k * rks::kSliceRows + lane);
           const bool real = k < len;
           const int64_t j = real ? rp[r] + k : 0;
-          scol[e] = real ? col[j] : (int32_t)(r < n ? r : 0);
+          scol[e] = real ? col[j] : (len > 0 ? col[rp[r]] : (int32_t)(r < n ? r : 0));
           if (indexed) sidx[e] = real ? vind[j] : 0;
           else sval[e] = real ? val[j] : 0.0;
           if (low) sval32[e] = real ? (float)val[j] : 0.0f;
@@ -1453,6 +1462,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     e.val_sl = c->val_sl;
     e.vidx_sl = c->vidx_sl;
     e.val32_sl = c->val32_sl;
+    e.sl_pad0 = pad0 ? 1 : 0;
   }
   e.tiles = c->tiles;
   e.ntiles = ntiles;

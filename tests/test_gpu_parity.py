@@ -116,12 +116,13 @@ def test_spmv_sketch_parity(lib, cuda, case, layout):
         P.rks_destroy(ctx)
 
 
-def table_valued(A, nvals, seed):
+def table_valued(A, nvals, seed, zeros=True):
     """A's pattern with values drawn from nvals distinct random doubles, each
-    of them used (-0.0 and 0.0 among them: distinct bit patterns)."""
+    of them used (with zeros, -0.0 and 0.0 among them: distinct bit patterns)."""
     rng = np.random.default_rng(seed)
     tab = rng.standard_normal(nvals)
-    tab[:2] = [0.0, -0.0]
+    if zeros:
+        tab[:2] = [0.0, -0.0]
     idx = rng.integers(0, nvals, len(A.val))
     idx[rng.permutation(len(A.val))[:nvals]] = np.arange(nvals)
     return CSR(A.n, A.row_ptr, A.col, tab[idx], dict(A.meta, values=nvals))
@@ -133,6 +134,9 @@ VIDX = {
     # the widest table (256 values, index 255 used), with empty rows and rows
     # of 510, 511 and 700 nonzeros (the long-row path)
     "longrows-256": (lambda: table_valued(long_rows(9001, 7), 256, 3), 256),
+    # a full table without +0.0: the sliced layout cannot pad with a zero value
+    # and reads the row lengths instead
+    "longrows-256-nozero": (lambda: table_valued(long_rows(9001, 7), 256, 4, zeros=False), 256),
     # one value too many: FP64 values
     "longrows-257": (lambda: table_valued(long_rows(9001, 7), 257, 3), 0),
 }
