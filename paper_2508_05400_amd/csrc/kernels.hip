@@ -365,7 +365,8 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sell(const int* __rest
     if (r < n) {
       const TW ws = (TW)acc;
       w[r] = ws;
-      if (KIND == 1 && do_sketch) {
+      // (a slice of empty rows hashes nothing and adds nothing: its sums are 0)
+      if (KIND == 1 && do_sketch && slen > 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           if (q < sp.zeta) atomicAdd(&wb[hrows[q]], (double)hsg[q] * (double)ws);

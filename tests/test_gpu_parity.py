@@ -42,7 +42,28 @@ SMALL = {
     "powerlaw-5003-d700": (lambda: powerlaw_random(5003, 4), "sparse", 700),
     # empty rows and rows longer than a tile, some inside a single column block
     "longrows-9001": (lambda: long_rows(9001, 7), "sparse", 120),
+    # rows 64..191 empty: two whole slices of the sliced layout without nonzeros
+    "gaprows-1000": (lambda: gap_rows(1000, 11), "sparse", 60),
 }
+
+
+def gap_rows(n, seed):
+    """Random rows of 1..12 nonzeros, except rows 64..191, which are empty."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for r in range(n):
+        if 64 <= r < 192:
+            continue
+        c = np.sort(rng.choice(n, int(rng.integers(1, 13)), replace=False))
+        rows.append(np.full(len(c), r))
+        cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    A = CSR(n, np.cumsum(rp).astype(np.int32), cols.astype(np.int32), rng.standard_normal(len(rows)),
+            {"kind": "gap_rows", "n": n})
+    A.check()
+    return A
 
 
 def long_rows(n, seed):
