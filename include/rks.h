@@ -74,7 +74,8 @@ typedef enum { RKS_PREC_FP64 = 0, RKS_PREC_V32 = 1, RKS_PREC_VBF16 = 2, RKS_PREC
  * stores a second copy of A, reordered by panel and block, with 16-bit row
  * offsets).  SLICED: slices of 64 consecutive rows, one row per lane of a
  * wave, each slice's nonzeros stored k-th of every row together (a sliced
- * ELLPACK layout, rows padded to the longest row of their slice): a wave's
+ * ELLPACK layout, SELL-C with C = 64 as in Kreutzer et al., SIAM J. Sci.
+ * Comput. 2014, rows padded to the longest row of their slice): a wave's
  * loads of the k-th nonzeros are contiguous, and on a banded matrix so are
  * its gathers of x; a lane adds its row's products in order in a register.
  * It stores a second copy of A in that order.  AUTO picks COLUMN_BLOCKS when
