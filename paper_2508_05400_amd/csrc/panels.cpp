@@ -1,4 +1,4 @@
-// Column-blocked SpMV layout (see panels.hpp).
+// Host-side SpMV layouts: column blocks and slices (see panels.hpp).
 #include "panels.hpp"
 
 #include <algorithm>
@@ -86,6 +86,41 @@ bool build_panels(int64_t n, const int32_t* rp, const int32_t* col, const double
     }
   }
   return true;
+}
+
+void slice_offsets(int64_t n, const int32_t* rp, std::vector<int64_t>& off) {
+  const int64_t ns = (n + kSliceRows - 1) / kSliceRows;
+  off.assign(ns + 1, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int32_t ml = 0;
+    for (int64_t r = s * kSliceRows; r < std::min<int64_t>(n, (s + 1) * kSliceRows); ++r)
+      ml = std::max(ml, rp[r + 1] - rp[r]);
+    off[s + 1] = off[s] + (int64_t)kSliceRows * ml;
+  }
+}
+
+void build_slices(int64_t n, const int32_t* rp, const int32_t* col, const std::vector<int64_t>& off,
+                  std::vector<int32_t>& scol, std::vector<int32_t>& src) {
+  const int64_t ns = (int64_t)off.size() - 1, P = off[ns];
+  scol.assign((size_t)P, 0);
+  src.assign((size_t)P, -1);
+  for (int64_t s = 0; s < ns; ++s) {
+    const int64_t b0 = off[s], slen = (off[s + 1] - b0) / kSliceRows;
+    for (int lane = 0; lane < kSliceRows; ++lane) {
+      const int64_t r = s * kSliceRows + lane;
+      const int64_t len = r < n ? rp[r + 1] - rp[r] : 0;
+      const int32_t pad = len > 0 ? col[rp[r]] : (int32_t)(r < n ? r : 0);
+      for (int64_t k = 0; k < slen; ++k) {
+        const size_t e = (size_t)(b0 + k * kSliceRows + lane);
+        if (k < len) {
+          scol[e] = col[rp[r] + k];
+          src[e] = (int32_t)(rp[r] + k);
+        } else {
+          scol[e] = pad;
+        }
+      }
+    }
+  }
 }
 
 }  // namespace rks

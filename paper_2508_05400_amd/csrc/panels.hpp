@@ -1,4 +1,4 @@
-// Column-blocked SpMV layout (host side): row panels x column blocks.
+// Host-side SpMV layouts: column-blocked (row panels x column blocks) and sliced.
 //
 // The columns are split into kCb contiguous blocks of ceil(n / kCb) columns
 // and the rows into panels of rows_pp consecutive rows (the last panel may be
@@ -41,5 +41,17 @@ int64_t panel_rows(int64_t n);
 // reason if an index of the layout would overflow 32 bits.
 bool build_panels(int64_t n, const int32_t* rp, const int32_t* col, const double* val, PanelLayout& L,
                   std::string& why);
+
+// Sliced layout (host side): slices of kSliceRows consecutive rows, each
+// padded to its longest row; slice s holds entries off[s] .. off[s+1] - 1,
+// entry (k, lane) at off[s] + kSliceRows k + lane being the k-th nonzero of
+// row kSliceRows s + lane, or padding.  slice_offsets fills off (nslices + 1
+// values; off[nslices] = padded entries).  build_slices fills, per entry, its
+// column and src, the index of its nonzero in the CSR arrays, or -1 for
+// padding, whose column is the row's first (the row itself if the row is
+// empty, 0 past n), so that every entry's column is a valid index of x.
+void slice_offsets(int64_t n, const int32_t* rp, std::vector<int64_t>& off);
+void build_slices(int64_t n, const int32_t* rp, const int32_t* col, const std::vector<int64_t>& off,
+                  std::vector<int32_t>& scol, std::vector<int32_t>& src);
 
 }  // namespace rks

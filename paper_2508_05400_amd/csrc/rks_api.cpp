@@ -1256,13 +1256,7 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
   std::vector<int64_t> sloff;
   bool use_sl = false;
   if (!use_cb && (o.spmv_layout == RKS_SPMV_SLICED || o.spmv_layout == RKS_SPMV_AUTO)) {
-    sloff.assign(nsl + 1, 0);
-    for (int64_t sb = 0; sb < nsl; ++sb) {
-      int ml = 0;
-      for (int64_t r = sb * rks::kSliceRows; r < std::min<int64_t>(n, (sb + 1) * rks::kSliceRows); ++r)
-        ml = std::max(ml, rp[r + 1] - rp[r]);
-      sloff[sb + 1] = sloff[sb] + (int64_t)rks::kSliceRows * ml;
-    }
+    rks::slice_offsets(n, rp.data(), sloff);
     const int64_t P = sloff[nsl];
     use_sl = (o.spmv_layout == RKS_SPMV_SLICED || P <= nnz + nnz / 8) && P > 0 && P < ((int64_t)1 << 31);
     if (o.spmv_layout == RKS_SPMV_SLICED && !use_sl) {
@@ -1375,29 +1369,18 @@ int rks_create(const rks_csr* A, int32_t k, int32_t m, int32_t d, int32_t which,
     c->a_distinct = a_nd;
   }
   if (use_sl && rc == RKS_OK) {
-    // entry (k, lane) of slice sb: the k-th nonzero of row kSliceRows sb + lane,
-    // or padding: value +0.0 (table index 0 when value-indexed and pad0) and
-    // the row's first column (the row itself if it is empty, 0 past n), so
-    // the padding adds exactly 0 for finite x
-    std::vector<int32_t> scol((size_t)sl_entries);
+    // columns of the entries, and their values: padding carries +0.0 (table
+    // index 0 when value-indexed and pad0), so it adds exactly 0 for finite x
+    std::vector<int32_t> scol, src;
+    rks::build_slices(n, rp.data(), col.data(), sloff, scol, src);
     std::vector<uint8_t> sidx(indexed ? (size_t)sl_entries : 0);
     std::vector<double> sval(indexed ? 0 : (size_t)sl_entries);
     std::vector<float> sval32(low ? (size_t)sl_entries : 0);
-    for (int64_t sb = 0; sb < nsl; ++sb) {
-      const int64_t b0 = sloff[sb], slen = (sloff[sb + 1] - b0) / rks::kSliceRows;
-      for (int lane = 0; lane < rks::kSliceRows; ++lane) {
-        const int64_t r = sb * rks::kSliceRows + lane;
-        const int64_t len = r < n ? rp[r + 1] - rp[r] : 0;
-        for (int64_t k = 0; k < slen; ++k) {
-          const size_t e = (size_t)(b0 + k * rks::kSliceRows + lane);
-          const bool real = k < len;
-          const int64_t j = real ? rp[r] + k : 0;
-          scol[e] = real ? col[j] : (len > 0 ? col[rp[r]] : (int32_t)(r < n ? r : 0));
-          if (indexed) sidx[e] = real ? vind[j] : 0;
-          else sval[e] = real ? val[j] : 0.0;
-          if (low) sval32[e] = real ? (float)val[j] : 0.0f;
-        }
-      }
+    for (size_t e = 0; e < (size_t)sl_entries; ++e) {
+      const int32_t j = src[e];
+      if (indexed) sidx[e] = j >= 0 ? vind[j] : 0;
+      else sval[e] = j >= 0 ? val[j] : 0.0;
+      if (low) sval32[e] = j >= 0 ? (float)val[j] : 0.0f;
     }
     cp(c->sl_off, sloff.data(), (size_t)(nsl + 1) * 8);
     cp(c->col_sl, scol.data(), (size_t)sl_entries * 4);

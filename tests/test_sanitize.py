@@ -49,3 +49,24 @@ def test_panel_layout_under_asan_and_ubsan(tmp_path):
     assert run.returncode == 0, run.stdout[-4000:] + run.stderr[-4000:]
     assert "ERROR: AddressSanitizer" not in run.stderr and "runtime error" not in run.stderr
     assert run.stdout.strip().endswith("ok: 0 failures")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_slice_layout_under_asan_and_ubsan(tmp_path):
+    """The sliced SpMV layout (slice_offsets, build_slices in csrc/panels.cpp)
+    on matrices with empty rows, whole slices of empty rows, rows of up to 700
+    nonzeros and ragged last slices: offsets padded to each slice's longest
+    row, every nonzero once at its (slice, k, lane), every column a valid
+    index of x, and the product in the kernel's order equal to the CSR
+    product to the bit."""
+    exe = str(tmp_path / "slices_check")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", f"-I{CSRC}", os.path.join(HERE, "sanitize", "slices_check.cpp"),
+           os.path.join(CSRC, "panels.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert run.returncode == 0, run.stdout[-4000:] + run.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in run.stderr and "runtime error" not in run.stderr
+    assert run.stdout.strip().endswith("ok: 0 failures")
