@@ -287,9 +287,9 @@ __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sketch(const int* __re
 // row is clamped to its last: in bounds, not added).  Padding (k >= the row's
 // length) holds +0.0 when pad0, and is then added like the nonzeros (exactly
 // 0 for finite x, and no row lengths are read); otherwise it is loaded but not
-// added.  The row's sketch column is hashed while
-// the first group is in flight.  Slices are dealt to the XCDs in contiguous
-// eighths, as the row tiles are.  TS as in k_spmv_sketch.
+// added.  The row's sketch column is hashed while the first group is in
+// flight.  Slices are dealt to the XCDs in contiguous eighths, as the row
+// tiles are.  TS as in k_spmv_sketch.
 template <typename TV, typename TW, typename TA, int KIND, typename TS>
 __global__ __launch_bounds__(64 * kSpmvWaves) void k_spmv_sell(const int* __restrict__ rp,
                                                    const int64_t* __restrict__ sl_off, int nsl,
